@@ -1,0 +1,801 @@
+/*
+ * wd_oracle.c -- plain FP64 CPU oracle for PDE-based wall distance
+ * (Kakumani, Vadlamani & Tucker, arXiv 2111.09859).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It is written
+ * from the paper's equations in their order, with plain loops, a Thomas
+ * solver and a Sherman-Morrison cyclic solver, and shares nothing with the
+ * GPU library.
+ *
+ * What each part follows:
+ *   - transformed equations, contravariant velocity, chain-rule Laplacian:
+ *     Sec. 3.1, Eqs. (Ek_eq_trans), (Ham_Jac_trans), (Poiss_trans);
+ *   - first derivatives (explicit E2/E4 and compact C4/C6 central schemes,
+ *     interior formula of Sec. 3.2 "Enhanced solver"); E6 adds the
+ *     standard third term c (f_{i+3}-f_{i-3})/6;
+ *   - pseudo-time forms: Eqs. (USeq1), (USeq3), (USeq4); 4-stage RK with
+ *     local time stepping (Sec. 3.3);
+ *   - convergence: Eq. (Con-criter);
+ *   - implicit filter: Sec. 3.4 (order 10 inside, reduced near boundaries);
+ *   - boundary conditions and initialisation: Sec. 3.5, Eqs. (eq7), (eq8);
+ *   - Gamma: Eqs. (Gamma_form1), (Gamma_form2);
+ *   - curvature correction: Sec. 5.4 (modified Nakanishi form);
+ *   - Poisson distance: Eq. (Poiss2).
+ * Readings where the paper is silent (boundary closures, near-boundary
+ * filter, local time step, LAD discretisation, Neumann discretisation,
+ * Poisson sign) are listed with each function below.
+ */
+#include "wd_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* Scheme coefficients.  Interior relation (index space):
+ *   al f'_{i-1} + f'_i + al f'_{i+1}
+ *      = a (f_{i+1}-f_{i-1})/2 + b (f_{i+2}-f_{i-2})/4 + c (f_{i+3}-f_{i-3})/6
+ * E2: a=1.  E4: a=4/3, b=-1/3.  E6: a=3/2, b=-3/5, c=1/10.
+ * C4: al=1/4, a=3/2.  C6: al=1/3, a=14/9, b=1/9.                         */
+typedef struct {
+    double al, a, b, c;
+    int radius;   /* half width of the explicit right-hand side */
+    int compact;
+} scheme_t;
+
+static scheme_t scheme_of(int s)
+{
+    scheme_t r;
+    memset(&r, 0, sizeof r);
+    switch (s) {
+    case WDO_E2: r.a = 1.0; r.radius = 1; break;
+    case WDO_E4: r.a = 4.0 / 3.0; r.b = -1.0 / 3.0; r.radius = 2; break;
+    case WDO_E6: r.a = 1.5; r.b = -0.6; r.c = 0.1; r.radius = 3; break;
+    case WDO_C4: r.al = 0.25; r.a = 1.5; r.radius = 1; r.compact = 1; break;
+    default:     r.al = 1.0 / 3.0; r.a = 14.0 / 9.0; r.b = 1.0 / 9.0;
+                 r.radius = 2; r.compact = 1; break;
+    }
+    return r;
+}
+
+/* Largest modified wavenumber of each scheme, three decimals (used only in
+ * the local time step below). */
+static double kprime_of(int s)
+{
+    switch (s) {
+    case WDO_E2: return 1.0;
+    case WDO_E4: return 1.372;
+    case WDO_E6: return 1.586;
+    case WDO_C4: return 1.732;
+    default:     return 1.989;
+    }
+}
+
+/* value of a line at integer position i, with periodic wrap and seam jump */
+static double lval(const double *f, int n, int periodic, double jump, int i)
+{
+    if (!periodic)
+        return f[i];
+    int w = (i >= 0) ? i / n : -((-i + n - 1) / n);
+    int k = i - w * n;
+    return f[k] + (double)w * jump;
+}
+
+/* ------------------------------------------------------------------ */
+/* Tridiagonal solvers.  Row i: a[i] x[i-1] + b[i] x[i] + c[i] x[i+1] = d[i]. */
+static void thomas(int n, const double *a, const double *b, const double *c,
+                   double *d, double *w)
+{
+    double beta = b[0];
+    d[0] /= beta;
+    for (int i = 1; i < n; ++i) {
+        w[i] = c[i - 1] / beta;
+        beta = b[i] - a[i] * w[i];
+        d[i] = (d[i] - a[i] * d[i - 1]) / beta;
+    }
+    for (int i = n - 2; i >= 0; --i)
+        d[i] -= w[i + 1] * d[i + 1];
+}
+
+/* Cyclic system: a[0] multiplies x[n-1], c[n-1] multiplies x[0].
+ * Sherman-Morrison on top of two Thomas solves. */
+static void cyclic(int n, const double *a, const double *b, const double *c,
+                   double *d)
+{
+    double *bb = malloc(sizeof(double) * n);
+    double *u = calloc(n, sizeof(double));
+    double *w = malloc(sizeof(double) * n);
+    double gam = -b[0];
+    for (int i = 0; i < n; ++i) bb[i] = b[i];
+    bb[0] = b[0] - gam;
+    bb[n - 1] = b[n - 1] - c[n - 1] * a[0] / gam;
+    thomas(n, a, bb, c, d, w);          /* d <- y */
+    u[0] = gam;
+    u[n - 1] = c[n - 1];
+    thomas(n, a, bb, c, u, w);          /* u <- z */
+    double fact = (d[0] + a[0] * d[n - 1] / gam) /
+                  (1.0 + u[0] + a[0] * u[n - 1] / gam);
+    for (int i = 0; i < n; ++i) d[i] -= fact * u[i];
+    free(bb); free(u); free(w);
+}
+
+/* ------------------------------------------------------------------ */
+/* Explicit one-sided / biased closures at distance k from a boundary,
+ * applied to g_j (g_0 on the boundary, j increasing inward).  Reading of
+ * the closures the paper defers to its reference [visbal]:
+ *   E2, node 0 : (-3, 4, -1)/2                         (exact to degree 2)
+ *   E4/E6, node 0: (-25, 48, -36, 16, -3)/12           (degree 4)
+ *   E4/E6, node 1: (-3, -10, 18, -6, 1)/12             (degree 4)
+ *   E6, node 2   : fourth-order central (1, -8, 0, 8, -1)/12 */
+static double explicit_closure(int scheme, int k, const double *g)
+{
+    if (scheme == WDO_E2)
+        return (-3.0 * g[0] + 4.0 * g[1] - g[2]) / 2.0;
+    if (k == 0)
+        return (-25.0 * g[0] + 48.0 * g[1] - 36.0 * g[2] + 16.0 * g[3]
+                - 3.0 * g[4]) / 12.0;
+    if (k == 1)
+        return (-3.0 * g[0] - 10.0 * g[1] + 18.0 * g[2] - 6.0 * g[3]
+                + g[4]) / 12.0;
+    return (g[0] - 8.0 * g[1] + 8.0 * g[3] - g[4]) / 12.0;
+}
+
+static double central_rhs(const scheme_t *s, const double *f, int n,
+                          int periodic, double jump, int i)
+{
+    double r = s->a * (lval(f, n, periodic, jump, i + 1)
+                       - lval(f, n, periodic, jump, i - 1)) / 2.0;
+    if (s->radius >= 2 && s->b != 0.0)
+        r += s->b * (lval(f, n, periodic, jump, i + 2)
+                     - lval(f, n, periodic, jump, i - 2)) / 4.0;
+    if (s->radius >= 3)
+        r += s->c * (lval(f, n, periodic, jump, i + 3)
+                     - lval(f, n, periodic, jump, i - 3)) / 6.0;
+    return r;
+}
+
+/* First derivative along a line (Sec. 3.2).  Compact boundary reading:
+ *   node 0   : f'_0 + 3 f'_1 = -17/6 f_0 + 3/2 f_1 + 3/2 f_2 - 1/6 f_3
+ *   node 1   : (C6 only) the C4 row 1/4 f'_0 + f'_1 + 1/4 f'_2 = 3/4 (f_2 - f_0)
+ * mirrored (with the sign of the right-hand side flipped) at the far end. */
+int wdo_deriv_line(int n, int periodic, int scheme, double jump,
+                   const double *f, double *df)
+{
+    scheme_t s = scheme_of(scheme);
+    if (n < 8 || scheme < WDO_E2 || scheme > WDO_C6)
+        return -1;
+    if (!s.compact) {
+        for (int i = 0; i < n; ++i) {
+            if (periodic || (i >= s.radius && i <= n - 1 - s.radius)) {
+                df[i] = central_rhs(&s, f, n, periodic, jump, i);
+            } else if (i < s.radius) {
+                df[i] = explicit_closure(scheme, i, f);
+            } else {
+                int k = n - 1 - i;
+                double g[5];
+                for (int j = 0; j < 5; ++j) g[j] = f[n - 1 - j];
+                df[i] = -explicit_closure(scheme, k, g);
+            }
+        }
+        return 0;
+    }
+    double *a = malloc(sizeof(double) * n);
+    double *b = malloc(sizeof(double) * n);
+    double *c = malloc(sizeof(double) * n);
+    double *w = malloc(sizeof(double) * n);
+    for (int i = 0; i < n; ++i) {
+        a[i] = s.al; b[i] = 1.0; c[i] = s.al;
+        if (periodic) {
+            df[i] = central_rhs(&s, f, n, 1, jump, i);
+            continue;
+        }
+        if (i == 0) {
+            a[i] = 0.0; c[i] = 3.0;
+            df[i] = -17.0 / 6.0 * f[0] + 1.5 * f[1] + 1.5 * f[2] - f[3] / 6.0;
+        } else if (i == n - 1) {
+            a[i] = 3.0; c[i] = 0.0;
+            df[i] = -(-17.0 / 6.0 * f[n - 1] + 1.5 * f[n - 2] + 1.5 * f[n - 3]
+                      - f[n - 4] / 6.0);
+        } else if (scheme == WDO_C6 && (i == 1 || i == n - 2)) {
+            a[i] = 0.25; c[i] = 0.25;
+            df[i] = 0.75 * (f[i + 1] - f[i - 1]);
+        } else {
+            df[i] = central_rhs(&s, f, n, 0, 0.0, i);
+        }
+    }
+    if (periodic)
+        cyclic(n, a, b, c, df);
+    else
+        thomas(n, a, b, c, df, w);
+    free(a); free(b); free(c); free(w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Implicit filter (Sec. 3.4):
+ *   af fh_{i-1} + fh_i + af fh_{i+1} = sum_{n=0}^{N} a_n/2 (f_{i+n} + f_{i-n})
+ * with the published coefficients of the order-2N family (Gaitonde &
+ * Visbal), written as functions of af.  Reading of the boundary treatment:
+ * boundary points are not filtered; a point at distance k = 1..4 from a
+ * non-periodic boundary uses the centred order-2k member; N = 5 elsewhere. */
+static void filter_coeffs(int N, double af, double *an)
+{
+    for (int k = 0; k < 6; ++k) an[k] = 0.0;
+    switch (N) {
+    case 1:
+        an[0] = 0.5 + af;
+        an[1] = 0.5 + af;
+        break;
+    case 2:
+        an[0] = 5.0 / 8.0 + 3.0 * af / 4.0;
+        an[1] = 0.5 + af;
+        an[2] = -1.0 / 8.0 + af / 4.0;
+        break;
+    case 3:
+        an[0] = 11.0 / 16.0 + 5.0 * af / 8.0;
+        an[1] = 15.0 / 32.0 + 17.0 * af / 16.0;
+        an[2] = -3.0 / 16.0 + 3.0 * af / 8.0;
+        an[3] = 1.0 / 32.0 - af / 16.0;
+        break;
+    case 4:
+        an[0] = 93.0 / 128.0 + 70.0 * af / 128.0;
+        an[1] = 7.0 / 16.0 + 18.0 * af / 16.0;
+        an[2] = -7.0 / 32.0 + 14.0 * af / 32.0;
+        an[3] = 1.0 / 16.0 - af / 8.0;
+        an[4] = -1.0 / 128.0 + af / 64.0;
+        break;
+    default:
+        an[0] = (193.0 + 126.0 * af) / 256.0;
+        an[1] = (105.0 + 302.0 * af) / 256.0;
+        an[2] = 15.0 * (-1.0 + 2.0 * af) / 64.0;
+        an[3] = 45.0 * (1.0 - 2.0 * af) / 512.0;
+        an[4] = 5.0 * (-1.0 + 2.0 * af) / 256.0;
+        an[5] = (1.0 - 2.0 * af) / 512.0;
+        break;
+    }
+}
+
+int wdo_filter_line(int n, int periodic, double alpha_f, const double *f,
+                    double *out)
+{
+    if (n < 8)
+        return -1;
+    double an[6];
+    if (periodic) {
+        double *a = malloc(sizeof(double) * n);
+        double *b = malloc(sizeof(double) * n);
+        double *c = malloc(sizeof(double) * n);
+        filter_coeffs(5, alpha_f, an);
+        for (int i = 0; i < n; ++i) {
+            a[i] = alpha_f; b[i] = 1.0; c[i] = alpha_f;
+            double r = 0.0;
+            for (int k = 0; k <= 5; ++k)
+                r += an[k] / 2.0 * (lval(f, n, 1, 0.0, i + k)
+                                    + lval(f, n, 1, 0.0, i - k));
+            out[i] = r;
+        }
+        cyclic(n, a, b, c, out);
+        free(a); free(b); free(c);
+        return 0;
+    }
+    /* unknowns are points 1..n-2; the boundary values stay as they are */
+    int m = n - 2;
+    double *a = malloc(sizeof(double) * m);
+    double *b = malloc(sizeof(double) * m);
+    double *c = malloc(sizeof(double) * m);
+    double *d = malloc(sizeof(double) * m);
+    double *w = malloc(sizeof(double) * m);
+    for (int i = 1; i <= n - 2; ++i) {
+        int dist = i < n - 1 - i ? i : n - 1 - i;
+        int N = dist < 5 ? dist : 5;
+        filter_coeffs(N, alpha_f, an);
+        double r = 0.0;
+        for (int k = 0; k <= N; ++k)
+            r += an[k] / 2.0 * (f[i + k] + f[i - k]);
+        int j = i - 1;
+        a[j] = alpha_f; b[j] = 1.0; c[j] = alpha_f;
+        if (i == 1) r -= alpha_f * f[0];
+        if (i == n - 2) r -= alpha_f * f[n - 1];
+        d[j] = r;
+    }
+    thomas(m, a, b, c, d, w);
+    out[0] = f[0];
+    out[n - 1] = f[n - 1];
+    for (int j = 0; j < m; ++j) out[j + 1] = d[j];
+    free(a); free(b); free(c); free(d); free(w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Grid helpers */
+static long npoints(const wdo_grid *g)
+{
+    long N = 1;
+    for (int l = 0; l < g->ndim; ++l) N *= g->n[l];
+    return N;
+}
+
+static long stride_of(const wdo_grid *g, int l)
+{
+    long s = 1;
+    for (int k = 0; k < l; ++k) s *= g->n[k];
+    return s;
+}
+
+/* base offset of line k of direction l */
+static long line_base(const wdo_grid *g, int l, long k)
+{
+    int n0 = g->n[0], n1 = g->ndim > 1 ? g->n[1] : 1;
+    if (l == 0)
+        return k * n0;
+    if (l == 1) {
+        long i0 = k % n0, i2 = k / n0;
+        return i0 + i2 * (long)n0 * n1;
+    }
+    {
+        long i0 = k % n0, i1 = k / n0;
+        return i0 + i1 * n0;
+    }
+}
+
+static void index_of(const wdo_grid *g, long q, int *idx)
+{
+    idx[0] = (int)(q % g->n[0]);
+    long r = q / g->n[0];
+    idx[1] = g->ndim > 1 ? (int)(r % g->n[1]) : 0;
+    idx[2] = g->ndim > 2 ? (int)(r / g->n[1]) : 0;
+}
+
+/* apply D_l to field f (grid-shaped), jump for coordinate seams */
+static int deriv_dir(const wdo_grid *g, int l, int scheme, double jump,
+                     const double *f, double *out)
+{
+    int n = g->n[l];
+    long s = stride_of(g, l);
+    long nl = npoints(g) / n;
+    int periodic = g->bc[l][0] == WDO_PERIODIC;
+    double *line = malloc(sizeof(double) * n);
+    double *dl = malloc(sizeof(double) * n);
+    int rc = 0;
+    for (long k = 0; k < nl && rc == 0; ++k) {
+        long base = line_base(g, l, k);
+        for (int i = 0; i < n; ++i) line[i] = f[base + i * s];
+        rc = wdo_deriv_line(n, periodic, scheme, jump, line, dl);
+        for (int i = 0; i < n; ++i) out[base + i * s] = dl[i];
+    }
+    free(line); free(dl);
+    return rc;
+}
+
+static int filter_dir(const wdo_grid *g, int l, double af, double *f)
+{
+    int n = g->n[l];
+    long s = stride_of(g, l);
+    long nl = npoints(g) / n;
+    int periodic = g->bc[l][0] == WDO_PERIODIC;
+    double *line = malloc(sizeof(double) * n);
+    double *fl = malloc(sizeof(double) * n);
+    int rc = 0;
+    for (long k = 0; k < nl && rc == 0; ++k) {
+        long base = line_base(g, l, k);
+        for (int i = 0; i < n; ++i) line[i] = f[base + i * s];
+        rc = wdo_filter_line(n, periodic, af, line, fl);
+        for (int i = 0; i < n; ++i) f[base + i * s] = fl[i];
+    }
+    free(line); free(fl);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Metrics (Sec. 3.1 with the solve's own scheme, Sec. 3.2): the Jacobian
+ * J[m][l] = d x_m / d xi_l from the derivative operator, then its inverse
+ * M[l][m] = d xi_l / d x_m at every point. */
+int wdo_metrics(const wdo_grid *g, int scheme, double *met)
+{
+    int d = g->ndim;
+    long N = npoints(g);
+    if (g->uniform) {
+        for (int l = 0; l < d; ++l)
+            for (int m = 0; m < d; ++m)
+                for (long q = 0; q < N; ++q)
+                    met[(l * d + m) * N + q] = (l == m) ? 1.0 / g->h[l] : 0.0;
+        return 0;
+    }
+    double *J = malloc(sizeof(double) * N * d * d);
+    for (int m = 0; m < d; ++m)
+        for (int l = 0; l < d; ++l) {
+            int rc = deriv_dir(g, l, scheme, g->period[l][m],
+                               g->coords + m * N, J + (m * d + l) * N);
+            if (rc) { free(J); return rc; }
+        }
+    for (long q = 0; q < N; ++q) {
+        double A[3][3], Inv[3][3];
+        for (int m = 0; m < d; ++m)
+            for (int l = 0; l < d; ++l)
+                A[m][l] = J[(m * d + l) * N + q];
+        if (d == 2) {
+            double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+            Inv[0][0] = A[1][1] / det;
+            Inv[0][1] = -A[0][1] / det;
+            Inv[1][0] = -A[1][0] / det;
+            Inv[1][1] = A[0][0] / det;
+        } else {
+            double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1])
+                       - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0])
+                       + A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+            Inv[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det;
+            Inv[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+            Inv[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+            Inv[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / det;
+            Inv[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+            Inv[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+            Inv[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det;
+            Inv[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+            Inv[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+        }
+        /* Inv[l][m] is d xi_l / d x_m */
+        for (int l = 0; l < d; ++l)
+            for (int m = 0; m < d; ++m)
+                met[(l * d + m) * N + q] = Inv[l][m];
+    }
+    free(J);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Boundary conditions (Sec. 3.5).  Wall faces and solid points are set to
+ * zero (Eq. eq7).  Reading of the far-field Neumann condition (Eq. eq8):
+ * second-order one-sided zero gradient along the grid line normal to the
+ * face, phi_b = (4 phi_{b+1} - phi_{b+2}) / 3.  Outflow faces (an option
+ * beside the paper's far field) extrapolate linearly along the grid line,
+ * phi_b = 2 phi_{b+1} - phi_{b+2}.  Both are applied face by face in the
+ * order (dir 0 low, dir 0 high, dir 1 low, ...) after the zeroing, and
+ * skip points that lie on a wall face or inside a solid. */
+static int on_wall(const wdo_grid *g, const int *idx)
+{
+    for (int l = 0; l < g->ndim; ++l) {
+        if (idx[l] == 0 && g->bc[l][0] == WDO_WALL) return 1;
+        if (idx[l] == g->n[l] - 1 && g->bc[l][1] == WDO_WALL) return 1;
+    }
+    return 0;
+}
+
+void wdo_apply_bc(const wdo_grid *g, double *phi)
+{
+    long N = npoints(g);
+    int idx[3];
+    for (long q = 0; q < N; ++q) {
+        index_of(g, q, idx);
+        if (on_wall(g, idx) || (g->mask && g->mask[q]))
+            phi[q] = 0.0;
+    }
+    for (int l = 0; l < g->ndim; ++l)
+        for (int side = 0; side < 2; ++side) {
+            int code = g->bc[l][side];
+            if (code != WDO_NEUMANN && code != WDO_OUTFLOW) continue;
+            long s = stride_of(g, l);
+            int target = side == 0 ? 0 : g->n[l] - 1;
+            long inward = side == 0 ? s : -s;
+            for (long q = 0; q < N; ++q) {
+                index_of(g, q, idx);
+                if (idx[l] != target) continue;
+                if (on_wall(g, idx) || (g->mask && g->mask[q])) continue;
+                if (code == WDO_NEUMANN)
+                    phi[q] = (4.0 * phi[q + inward] - phi[q + 2 * inward]) / 3.0;
+                else
+                    phi[q] = 2.0 * phi[q + inward] - phi[q + 2 * inward];
+            }
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Five-point fourth difference along direction l at every point.  Reading
+ * of Eq. (Gamma_form2)'s fourth derivative: index-space difference
+ * f_{i-2} - 4 f_{i-1} + 6 f_i - 4 f_{i+1} + f_{i+2}; the two points nearest
+ * a non-periodic boundary take the value of the nearest point where the
+ * stencil fits. */
+static void fourth_diff_dir(const wdo_grid *g, int l, const double *f,
+                            double *out)
+{
+    int n = g->n[l];
+    long s = stride_of(g, l);
+    long nl = npoints(g) / n;
+    int periodic = g->bc[l][0] == WDO_PERIODIC;
+    for (long k = 0; k < nl; ++k) {
+        long base = line_base(g, l, k);
+        for (int i = 0; i < n; ++i) {
+            int c = i;
+            if (!periodic) {
+                if (c < 2) c = 2;
+                if (c > n - 3) c = n - 3;
+            }
+            double v[5];
+            for (int j = -2; j <= 2; ++j) {
+                int p = c + j;
+                if (periodic) p = ((p % n) + n) % n;
+                v[j + 2] = f[base + p * s];
+            }
+            out[base + i * s] = v[0] - 4.0 * v[1] + 6.0 * v[2] - 4.0 * v[3] + v[4];
+        }
+    }
+}
+
+/* Right-hand side of the pseudo-time equation at phi (Sec. 3.3):
+ *   Eikonal (USeq1):  R = 1 - U.grad(phi) = 1 - |grad phi|^2
+ *   HJ      (USeq3):  R = 1 + Gamma lap(phi) - |grad phi|^2
+ *   HJ + curvature:   R = 1 + (Gamma + nu) (lap(phi) - max(0, |grad phi| kappa))
+ *                         - |grad phi|^2      (Sec. 5.4; Gamma is either form)
+ *   Poisson (USeq4):  R = 1 + lap(phi)
+ * with U_m = sum_l xi_{l,m} D_l phi and lap = sum_m sum_l xi_{l,m} D_l U_m
+ * (Eq. Ham_Jac_trans).  Reading of the local time step (the paper only
+ * names local time stepping):
+ *   dt = sigma / ( 2 k' S1 max(|grad phi|, 1) + k'^2 (Gamma + nu) S2 ),
+ *   S1 = sum_l |grad xi_l|, S2 = sum_l |grad xi_l|^2, k' the scheme's
+ *   largest modified wavenumber; Eikonal drops the second term, Poisson
+ *   uses dt = sigma / (k'^2 S2). */
+int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
+             const double *phi, double *R, double *gmag, double *gam,
+             double *lap, double *kap, double *dt)
+{
+    int d = g->ndim;
+    long N = npoints(g);
+    int rc = 0;
+    double *F = malloc(sizeof(double) * N * d);
+    double *U = malloc(sizeof(double) * N * d);
+    double *tmp = malloc(sizeof(double) * N);
+    double *L = calloc(N, sizeof(double));
+    double *K = calloc(N, sizeof(double));
+    double *G = malloc(sizeof(double) * N);
+    for (int l = 0; l < d && !rc; ++l)
+        rc = deriv_dir(g, l, m->scheme, 0.0, phi, F + l * N);
+    for (int mm = 0; mm < d; ++mm)
+        for (long q = 0; q < N; ++q) {
+            double u = 0.0;
+            for (int l = 0; l < d; ++l)
+                u += met[(l * d + mm) * N + q] * F[l * N + q];
+            U[mm * N + q] = u;
+        }
+    for (long q = 0; q < N; ++q) {
+        double s = 0.0;
+        for (int mm = 0; mm < d; ++mm) s += U[mm * N + q] * U[mm * N + q];
+        G[q] = sqrt(s);
+    }
+    int need_lap = m->equation != WDO_EIKONAL;
+    int curv = m->equation == WDO_HJ && m->curvature;
+    if (need_lap)
+        for (int mm = 0; mm < d && !rc; ++mm)
+            for (int l = 0; l < d && !rc; ++l) {
+                rc = deriv_dir(g, l, m->scheme, 0.0, U + mm * N, tmp);
+                for (long q = 0; q < N; ++q)
+                    L[q] += met[(l * d + mm) * N + q] * tmp[q];
+            }
+    if (curv) {
+        double *nv = malloc(sizeof(double) * N);
+        for (int mm = 0; mm < d && !rc; ++mm) {
+            for (long q = 0; q < N; ++q)
+                nv[q] = U[mm * N + q] / (G[q] + m->eps0);
+            for (int l = 0; l < d && !rc; ++l) {
+                rc = deriv_dir(g, l, m->scheme, 0.0, nv, tmp);
+                for (long q = 0; q < N; ++q)
+                    K[q] += met[(l * d + mm) * N + q] * tmp[q];
+            }
+        }
+        free(nv);
+    }
+    /* Gamma: standard eps*phi (Gamma_form1) or LAD (Gamma_form2) with
+     * Delta x_l = 1/|grad xi_l| (reading); clipped at zero. */
+    double *Gam = calloc(N, sizeof(double));
+    if (m->equation == WDO_HJ) {
+        double *S = NULL;
+        if (m->gamma == WDO_GAMMA_LAD) {
+            S = calloc(N, sizeof(double));
+            for (int l = 0; l < d; ++l) {
+                fourth_diff_dir(g, l, phi, tmp);
+                for (long q = 0; q < N; ++q) {
+                    double s2 = 0.0;
+                    for (int mm = 0; mm < d; ++mm) {
+                        double e = met[(l * d + mm) * N + q];
+                        s2 += e * e;
+                    }
+                    double dx = 1.0 / sqrt(s2);
+                    S[q] += s2 * s2 * tmp[q] * dx * dx * dx;
+                }
+            }
+        }
+        for (long q = 0; q < N; ++q) {
+            double gq = m->eps * phi[q];
+            if (S) {
+                double lad = m->C * fabs(S[q]);
+                if (lad < gq) gq = lad;
+            }
+            Gam[q] = gq > 0.0 ? gq : 0.0;
+        }
+        free(S);
+    }
+    double kp = kprime_of(m->scheme);
+    for (long q = 0; q < N; ++q) {
+        double g2 = 0.0;
+        for (int mm = 0; mm < d; ++mm) g2 += U[mm * N + q] * U[mm * N + q];
+        double nu = curv ? m->nu0 * (1.0 - G[q]) * (1.0 - G[q]) : 0.0;
+        double r;
+        if (m->equation == WDO_EIKONAL)
+            r = 1.0 - g2;
+        else if (m->equation == WDO_POISSON)
+            r = 1.0 + L[q];
+        else if (curv) {
+            double gk = G[q] * K[q];
+            r = 1.0 + (Gam[q] + nu) * (L[q] - (gk > 0.0 ? gk : 0.0)) - g2;
+        } else
+            r = 1.0 + Gam[q] * L[q] - g2;
+        if (R) R[q] = r;
+        if (gmag) gmag[q] = G[q];
+        if (gam) gam[q] = Gam[q];
+        if (lap) lap[q] = L[q];
+        if (kap) kap[q] = K[q];
+        if (dt) {
+            double S1 = 0.0, S2 = 0.0;
+            for (int l = 0; l < d; ++l) {
+                double s2 = 0.0;
+                for (int mm = 0; mm < d; ++mm) {
+                    double e = met[(l * d + mm) * N + q];
+                    s2 += e * e;
+                }
+                S1 += sqrt(s2);
+                S2 += s2;
+            }
+            double gm = G[q] > 1.0 ? G[q] : 1.0;
+            double den;
+            if (m->equation == WDO_EIKONAL)
+                den = 2.0 * kp * S1 * gm;
+            else if (m->equation == WDO_POISSON)
+                den = kp * kp * S2;
+            else
+                den = 2.0 * kp * S1 * gm + kp * kp * (Gam[q] + nu) * S2;
+            dt[q] = m->sigma / den;
+        }
+    }
+    free(F); free(U); free(tmp); free(L); free(K); free(G); free(Gam);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Pseudo-time march (Sec. 3.3-3.5, Fig. flow chart (b)):
+ *   phi = 0, BCs; per iteration: local dt from phi^n; RK stages, each
+ *   followed by the BCs; filter along xi, eta, zeta in turn; BCs;
+ *   r_n = max |phi^{n+1} - phi^n| (Eq. Con-criter); stop when r_n <= tol.
+ * RK4 is the classical four-stage scheme; RK3 is the Shu-Osher SSP
+ * scheme (reading: a three-stage option beside the paper's RK4). */
+int wdo_solve(const wdo_grid *g, const wdo_method *m, double *phi, int warm,
+              double *hist, int hist_cap, int *iters)
+{
+    if (!g || !m || !phi || g->ndim < 2 || g->ndim > 3)
+        return -1;
+    long N = npoints(g);
+    int d = g->ndim;
+    double *met = malloc(sizeof(double) * N * d * d);
+    if (wdo_metrics(g, m->scheme, met)) { free(met); return -1; }
+    double *pn = malloc(sizeof(double) * N);
+    double *p = malloc(sizeof(double) * N);
+    double *k1 = malloc(sizeof(double) * N);
+    double *k2 = malloc(sizeof(double) * N);
+    double *k3 = malloc(sizeof(double) * N);
+    double *k4 = malloc(sizeof(double) * N);
+    double *dt = malloc(sizeof(double) * N);
+    if (!warm)
+        for (long q = 0; q < N; ++q) phi[q] = 0.0;
+    wdo_apply_bc(g, phi);
+    int status = 1, it = 0;
+    int limit = m->fixed_iters > 0 ? m->fixed_iters : m->max_iter;
+    for (it = 0; it < limit; ++it) {
+        memcpy(pn, phi, sizeof(double) * N);
+        if (m->rk == WDO_RK4) {
+            wdo_eval(g, m, met, pn, k1, NULL, NULL, NULL, NULL, dt);
+            for (long q = 0; q < N; ++q) p[q] = pn[q] + dt[q] / 2.0 * k1[q];
+            wdo_apply_bc(g, p);
+            wdo_eval(g, m, met, p, k2, NULL, NULL, NULL, NULL, NULL);
+            for (long q = 0; q < N; ++q) p[q] = pn[q] + dt[q] / 2.0 * k2[q];
+            wdo_apply_bc(g, p);
+            wdo_eval(g, m, met, p, k3, NULL, NULL, NULL, NULL, NULL);
+            for (long q = 0; q < N; ++q) p[q] = pn[q] + dt[q] * k3[q];
+            wdo_apply_bc(g, p);
+            wdo_eval(g, m, met, p, k4, NULL, NULL, NULL, NULL, NULL);
+            for (long q = 0; q < N; ++q)
+                phi[q] = pn[q] + dt[q] / 6.0 * (k1[q] + 2.0 * k2[q]
+                                                + 2.0 * k3[q] + k4[q]);
+            wdo_apply_bc(g, phi);
+        } else {
+            wdo_eval(g, m, met, pn, k1, NULL, NULL, NULL, NULL, dt);
+            for (long q = 0; q < N; ++q) p[q] = pn[q] + dt[q] * k1[q];
+            wdo_apply_bc(g, p);
+            wdo_eval(g, m, met, p, k2, NULL, NULL, NULL, NULL, NULL);
+            for (long q = 0; q < N; ++q)
+                k3[q] = 0.75 * pn[q] + 0.25 * (p[q] + dt[q] * k2[q]);
+            wdo_apply_bc(g, k3);
+            wdo_eval(g, m, met, k3, k2, NULL, NULL, NULL, NULL, NULL);
+            for (long q = 0; q < N; ++q)
+                phi[q] = pn[q] / 3.0 + 2.0 / 3.0 * (k3[q] + dt[q] * k2[q]);
+            wdo_apply_bc(g, phi);
+        }
+        if (m->filter) {
+            for (int l = 0; l < d; ++l)
+                filter_dir(g, l, m->alpha_f, phi);
+            wdo_apply_bc(g, phi);
+        }
+        double rmax = 0.0, s2 = 0.0;
+        for (long q = 0; q < N; ++q) {
+            double e = fabs(phi[q] - pn[q]);
+            if (e > rmax || e != e) rmax = e;
+            s2 += e * e;
+        }
+        double l2 = sqrt(s2 / (double)N);
+        if (hist && it < hist_cap) {
+            hist[2 * it] = rmax;
+            hist[2 * it + 1] = l2;
+        }
+        if (!isfinite(rmax) || !isfinite(l2)) {
+            status = -3;
+            ++it;
+            break;
+        }
+        if (m->fixed_iters <= 0 && rmax <= m->tol) {
+            status = 0;
+            ++it;
+            break;
+        }
+    }
+    if (m->fixed_iters > 0 && status == 1)
+        status = 0;
+    if (iters) *iters = it;
+    free(met); free(pn); free(p); free(k1); free(k2); free(k3); free(k4);
+    free(dt);
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Eq. (Poiss2) with the minus sign (reading: the root that vanishes at the
+ * wall and gives min(y, 1-y) in a channel), gradient by the solve's scheme
+ * and metrics. */
+int wdo_poisson_distance(const wdo_grid *g, int scheme, const double *met,
+                         const double *phip, double *dist)
+{
+    int d = g->ndim;
+    long N = npoints(g);
+    double *F = malloc(sizeof(double) * N * d);
+    int rc = 0;
+    for (int l = 0; l < d && !rc; ++l)
+        rc = deriv_dir(g, l, scheme, 0.0, phip, F + l * N);
+    for (long q = 0; q < N && !rc; ++q) {
+        double s = 0.0;
+        for (int mm = 0; mm < d; ++mm) {
+            double u = 0.0;
+            for (int l = 0; l < d; ++l)
+                u += met[(l * d + mm) * N + q] * F[l * N + q];
+            s += u * u;
+        }
+        double inner = s + 2.0 * phip[q];
+        if (inner < 0.0) inner = 0.0;
+        dist[q] = -sqrt(s) + sqrt(inner);
+    }
+    free(F);
+    return rc;
+}
+
+/* Nearest-wall search by brute force (the search approach of Sec. 1),
+ * used only to check tiny cases. */
+void wdo_brute_force(int ndim, int npts, const double *pts, int nwall,
+                     const double *wall, double *dist)
+{
+    for (int i = 0; i < npts; ++i) {
+        double best = INFINITY;
+        for (int k = 0; k < nwall; ++k) {
+            double s = 0.0;
+            for (int m = 0; m < ndim; ++m) {
+                double e = pts[i * ndim + m] - wall[k * ndim + m];
+                s += e * e;
+            }
+            if (s < best) best = s;
+        }
+        dist[i] = sqrt(best);
+    }
+}

@@ -1,0 +1,97 @@
+/*
+ * wd_oracle.h -- plain FP64 CPU oracle for PDE-based wall distance
+ * (Kakumani, Vadlamani & Tucker, "On the use of high order central
+ * difference schemes for differential equation based wall distance
+ * computations", arXiv 2111.09859).
+ *
+ * TEST INFRASTRUCTURE.  This library exists only to check the GPU path.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code, header, table or constant
+ * generator with the GPU library, and it never includes anything from it.
+ *
+ * Conventions (all arrays are dense, x index fastest):
+ *   point (i0,i1,i2) -> q = i0 + n0*(i1 + n1*i2); n2 = 1 in 2D.
+ *   metrics: ndim*ndim SoA components, component (l*ndim+m) holds
+ *            d xi_l / d x_m  (Sec. 3.1, transformed equations).
+ *   coords:  ndim SoA components x_m.
+ */
+#ifndef WD_ORACLE_H
+#define WD_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { WDO_WALL = 0, WDO_NEUMANN = 1, WDO_OUTFLOW = 2, WDO_PERIODIC = 3 };
+enum { WDO_EIKONAL = 0, WDO_HJ = 1, WDO_POISSON = 2 };
+enum { WDO_GAMMA_LINEAR = 0, WDO_GAMMA_LAD = 1 };
+enum { WDO_E2 = 0, WDO_E4 = 1, WDO_E6 = 2, WDO_C4 = 3, WDO_C6 = 4 };
+enum { WDO_RK3 = 0, WDO_RK4 = 1 };
+
+typedef struct {
+    int ndim;
+    int n[3];
+    int bc[3][2];              /* per direction, low / high face        */
+    int uniform;               /* 1: Cartesian spacing h[]; 0: coords    */
+    double h[3];
+    const double *coords;      /* ndim SoA components (uniform == 0)     */
+    double period[3][3];       /* x_m(i_l + n_l) = x_m(i_l) + period[l][m] */
+    const unsigned char *mask; /* optional, 1 = solid point              */
+} wdo_grid;
+
+typedef struct {
+    int equation;              /* WDO_EIKONAL / WDO_HJ / WDO_POISSON      */
+    int gamma;                 /* WDO_GAMMA_LINEAR / WDO_GAMMA_LAD        */
+    int curvature;             /* 1: Nakanishi-type curvature correction  */
+    double eps;                /* Gamma = eps*phi                         */
+    double C;                  /* LAD constant                            */
+    double nu0;                /* curvature stabiliser coefficient        */
+    double eps0;               /* regulariser of the unit normal          */
+    int scheme;                /* WDO_E2 .. WDO_C6                        */
+    int filter;                /* 1: implicit filter after each step      */
+    double alpha_f;
+    int rk;                    /* WDO_RK3 (SSP) / WDO_RK4                 */
+    double sigma;              /* local time step safety factor           */
+    double tol;                /* stop when max |phi - phi_o| <= tol      */
+    int max_iter;
+    int fixed_iters;           /* > 0: run exactly this many iterations   */
+} wdo_method;
+
+/* 1-D operators in index space (unit spacing).  jump: f(i+n) = f(i)+jump
+ * for periodic lines (coordinate seams).  Return 0 on success. */
+int wdo_deriv_line(int n, int periodic, int scheme, double jump,
+                   const double *f, double *df);
+int wdo_filter_line(int n, int periodic, double alpha_f,
+                    const double *f, double *out);
+
+/* Metric terms by the solve's own scheme (d xi_l / d x_m). */
+int wdo_metrics(const wdo_grid *g, int scheme, double *met);
+
+/* One evaluation of the pseudo-time right-hand side at phi.  Any output
+ * pointer may be NULL.  dt is the local pseudo time step at phi. */
+int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
+             const double *phi, double *R, double *gmag, double *gam,
+             double *lap, double *kap, double *dt);
+
+/* Boundary conditions and solid mask, in place. */
+void wdo_apply_bc(const wdo_grid *g, double *phi);
+
+/* Pseudo-time march.  warm: 0 -> phi starts at zero.  hist receives
+ * (Linf, L2) of the pseudo-step change per iteration.  Returns 0 when
+ * converged (or fixed_iters done), 1 when max_iter was exhausted, -3 on a
+ * non-finite residual, -1 on bad arguments. */
+int wdo_solve(const wdo_grid *g, const wdo_method *m, double *phi, int warm,
+              double *hist, int hist_cap, int *iters);
+
+/* Poisson auxiliary variable -> distance. */
+int wdo_poisson_distance(const wdo_grid *g, int scheme, const double *met,
+                         const double *phip, double *d);
+
+/* Brute-force nearest distance from npts points to nwall wall samples. */
+void wdo_brute_force(int ndim, int npts, const double *pts, int nwall,
+                     const double *wall, double *d);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
