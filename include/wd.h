@@ -1,0 +1,245 @@
+/*
+ * wd.h -- C ABI of the MI355X (gfx950) wall-distance library.
+ *
+ * The library drives the wall-distance PDEs of Kakumani, Vadlamani &
+ * Tucker (arXiv 2111.09859) -- Eikonal (Eq. ek_eq), Hamilton-Jacobi
+ * (Eq. Ham_Jac, with Gamma from Eq. Gamma_form1 or the LAD form of
+ * Eq. Gamma_form2, optionally with the curvature correction of Sec. 5.4)
+ * and Poisson (Eqs. Poiss1/Poiss2) -- to steady state by pseudo-time
+ * marching (Sec. 3.3) on structured 2D/3D grids written in generalised
+ * coordinates (Sec. 3.1), with explicit or compact central differences
+ * (Sec. 3.2) and the implicit filter of Sec. 3.4 after every pseudo step.
+ *
+ * Conventions for every call:
+ *   - Fields are dense, x index (direction 0) fastest: point (i0,i1,i2) is
+ *     element i0 + n0*(i1 + n1*i2); n2 = 1 for 2D grids.
+ *   - Pointers documented as "device" are HIP device pointers on the
+ *     context's device; "host" pointers are ordinary host memory.
+ *   - The caller owns every buffer it passes (fields, metrics, masks,
+ *     workspace, history); the library owns only its context caches and the
+ *     server's internal arena, released by the matching destroy call.
+ *   - Work is issued on the given stream (hipStream_t passed as void*; NULL
+ *     means the default stream).  The solve calls return after the solve has
+ *     finished on that stream.
+ *   - Return value: WD_OK (0) or a positive warning (the outputs are valid)
+ *     or a negative error; wd_last_error() describes the last failure of the
+ *     calling thread.
+ */
+#ifndef WD_H
+#define WD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define WD_OK 0
+#define WD_NOT_CONVERGED 1     /* max_iter reached; field + history valid   */
+#define WD_STAGNATED 2         /* residual stopped decreasing (stall_window) */
+#define WD_PENDING 3           /* server request not finished yet           */
+#define WD_ERR_INVALID_ARG (-1)
+#define WD_ERR_UNSUPPORTED (-2)
+#define WD_ERR_DIVERGED (-3)   /* non-finite pseudo-step change             */
+#define WD_ERR_NO_MEMORY (-4)  /* workspace / budget too small              */
+#define WD_ERR_HIP (-5)        /* HIP runtime error, text in wd_last_error  */
+#define WD_ERR_CANCELLED (-6)
+#define WD_ERR_NOT_FOUND (-7)
+
+/* ---- enumerations ---------------------------------------------------- */
+/* Face conditions (Sec. 3.5): WALL is the Dirichlet phi = 0 of Eq. eq7;
+ * NEUMANN is the zero normal gradient of Eq. eq8, discretised as
+ * phi_b = (4 phi_{b+1} - phi_{b+2})/3 along the grid line; OUTFLOW (an
+ * option beside the paper's far field) extrapolates linearly,
+ * phi_b = 2 phi_{b+1} - phi_{b+2}; both are re-imposed after every RK stage
+ * and after the filter, face by face in direction order, skipping points on
+ * wall faces or in solids.  PERIODIC wraps the index (n distinct points,
+ * both faces of a direction). */
+enum wd_bc { WD_BC_WALL = 0, WD_BC_NEUMANN = 1, WD_BC_OUTFLOW = 2,
+             WD_BC_PERIODIC = 3 };
+enum wd_metric_mode { WD_METRIC_UNIFORM = 0, WD_METRIC_FIELDS = 1 };
+enum wd_equation { WD_EQ_EIKONAL = 0, WD_EQ_HJ = 1, WD_EQ_POISSON = 2 };
+enum wd_gamma { WD_GAMMA_LINEAR = 0, WD_GAMMA_LAD = 1 };
+/* Sec. 3.2 schemes; E6 is the sixth-order explicit member of the same
+ * family (third term c (f_{i+3} - f_{i-3})/6). */
+enum wd_scheme { WD_E2 = 0, WD_E4 = 1, WD_E6 = 2, WD_C4 = 3, WD_C6 = 4 };
+enum wd_rk { WD_RK3_SSP = 0, WD_RK4 = 1 };
+enum wd_precision { WD_FP32 = 0, WD_FP64 = 1 };
+
+/* ---- grid descriptor (Sec. 3.1 generalised coordinates, Sec. 3.5) ----- */
+typedef struct wd_grid_desc {
+    int ndim;             /* 2 or 3                                         */
+    int n[3];             /* points per direction (>= 8); n[2] = 1 in 2D    */
+    int bc[3][2];         /* wd_bc per direction, [low face, high face];
+                             PERIODIC must be set on both faces             */
+    int metric_mode;      /* wd_metric_mode                                 */
+    double h[3];          /* UNIFORM: grid spacing per direction            */
+    const void *metrics;  /* FIELDS (2D only): device array of ndim*ndim SoA
+                             components in the solve precision; component
+                             (l*ndim + m) holds d xi_l / d x_m               */
+    const unsigned char *mask; /* optional device array, 1 = solid point
+                                  (phi = 0 there); NULL = no solids         */
+} wd_grid_desc;
+
+/* ---- method descriptor ---------------------------------------------- */
+typedef struct wd_method {
+    int equation;         /* wd_equation                                    */
+    int gamma;            /* wd_gamma (HJ only)                             */
+    int curvature;        /* 1: curvature correction of Sec. 5.4 (HJ only)  */
+    double eps;           /* Gamma = eps * phi (Eq. Gamma_form1), 0.1..1    */
+    double c_lad;         /* C of Eq. Gamma_form2 (0.1)                     */
+    double nu0;           /* nu = nu0 (1 - |grad phi|)^2 (0.001)            */
+    double eps0;          /* n = grad phi / (|grad phi| + eps0) (1e-6)      */
+    int scheme;           /* wd_scheme, used for metrics and derivatives    */
+    int filter;           /* 1: implicit filter after every pseudo step     */
+    double alpha_f;       /* filter coefficient, 0.48 .. 0.5 (0.5 = none)   */
+    int rk;               /* wd_rk                                          */
+    double sigma;         /* local pseudo-time step safety factor (1.0)     */
+    double tol;           /* stop when max |phi - phi_o| <= tol (Eq.
+                             Con-criter, L_ref = 1)                         */
+    int max_iter;         /* iteration limit                                */
+    int stall_window;     /* > 0: stop (WD_STAGNATED) when the max change has
+                             not reached a new minimum for this many
+                             iterations; 0 disables                         */
+    int precision;        /* wd_precision of fields and arithmetic; the
+                             convergence reductions are always FP64         */
+    int warm_start;       /* 1: phi holds the initial guess; 0: phi = 0     */
+} wd_method;
+
+typedef struct wd_ctx wd_ctx;
+typedef struct wd_server wd_server;
+
+/* Version string, e.g. "wd 1.0 gfx950". */
+const char *wd_version(void);
+
+/* Text of the last failing call on this thread ("" if none). */
+const char *wd_last_error(void);
+
+/* Fill *m with the defaults: HJ, LAD, no curvature, eps 0.2, C 0.1,
+ * nu0 1e-3, eps0 1e-6, C6, filter on, alpha_f 0.495, RK4, sigma 1,
+ * tol 1e-10, max_iter 100000, stall_window 0, FP64, cold start. */
+int wd_method_default(wd_method *m);
+
+/* Create a context on HIP device `device`: owns the line-operator tables
+ * and the tile autotuning cache.  *out receives the context. */
+int wd_ctx_create(int device, wd_ctx **out);
+int wd_ctx_destroy(wd_ctx *ctx);
+
+/* Metric terms (Sec. 3.1) of a curvilinear grid with the solve's own
+ * derivative scheme (Sec. 3.2: metrics use the same central schemes).
+ *   coords  : device, ndim SoA FP64 components x_m, grid layout.
+ *   period  : host, period[l*3+m] = jump of x_m across the periodic seam of
+ *             direction l (x_m(i_l + n_l) = x_m(i_l) + period); NULL = 0.
+ *   out     : device, ndim*ndim SoA components in `out_precision`, the
+ *             layout wd_grid_desc.metrics expects.
+ * desc->metric_mode and desc->metrics are ignored. */
+int wd_compute_metrics(wd_ctx *ctx, const wd_grid_desc *desc, int scheme,
+                       const double *coords, const double *period, void *out,
+                       int out_precision, void *stream);
+
+/* Workspace bytes a wd_solve / wd_solve_batched of these grids needs.  The
+ * caller allocates it on the device (any allocator) and passes it in. */
+int wd_workspace_bytes(wd_ctx *ctx, int n_grids, const wd_grid_desc *descs,
+                       const wd_method *methods, size_t *bytes);
+
+/* Plain per-grid solve (Sec. 3.3-3.5 pseudo-time march to steady state).
+ *   phi      : device, grid layout, method precision.  Initial guess when
+ *              warm_start is set (else overwritten with zero); on return the
+ *              wall distance.  For WD_EQ_POISSON the converted distance of
+ *              Eq. Poiss2; phi_aux (device, may be NULL) then receives the
+ *              Poisson variable phi'.
+ *   hist     : host, 2*hist_cap doubles: (max change, RMS change) of each
+ *              pseudo iteration, FP64; may be NULL.
+ *   iters    : host, iterations performed; may be NULL.
+ *   ws       : device workspace of at least wd_workspace_bytes bytes.
+ * Returns WD_OK on convergence, WD_NOT_CONVERGED, WD_STAGNATED or an
+ * error (WD_ERR_DIVERGED leaves the last field in phi). */
+int wd_solve(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method,
+             void *phi, void *phi_aux, double *hist, int hist_cap, int *iters,
+             void *ws, size_t ws_bytes, void *stream);
+
+/* Batched solve of n independent grids in one set of launches per RK
+ * stage.  All grids share ndim, precision and rk; everything else (size,
+ * scheme, equation, Gamma, metrics, faces, tolerances) may differ.  Each
+ * grid's result is bitwise the one wd_solve gives for it alone.
+ *   phis[i], aux[i] (aux may be NULL or hold NULLs): device, as in wd_solve.
+ *   hists[i]: host or NULL; iters[i], status[i]: host arrays of n or NULL.
+ * Returns the worst status over the grids (errors before warnings). */
+int wd_solve_batched(wd_ctx *ctx, int n, const wd_grid_desc *descs,
+                     const wd_method *methods, void *const *phis,
+                     void *const *aux, double *const *hists, int hist_cap,
+                     int *iters, int *status, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* Eq. Poiss2 on its own: distance = -|grad phi'| + sqrt(|grad phi'|^2 +
+ * 2 phi') with the gradient by `scheme` and the metrics, evaluated in FP64.
+ *   phip, dist: device, grid layout, `precision` (FP32 or FP64).
+ *   ws: device, >= wd_workspace_bytes of a Poisson solve of this grid. */
+int wd_poisson_distance(wd_ctx *ctx, const wd_grid_desc *desc, int scheme,
+                        int precision, const void *phip, void *dist, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* ---- host-side diagnostics ------------------------------------------ */
+/* Applies, on the host and in FP64 arithmetic, the parallel-cyclic-reduction
+ * multipliers the kernels use for a line system (Sec. 3.2 compact first
+ * derivative when kind == 0, Sec. 3.4 filter correction when kind == 1):
+ * x = A^{-1} rhs for the line's fixed tridiagonal matrix A.  With fp64 == 0
+ * the multipliers are first rounded to FP32, as the FP32 kernels hold them.
+ *   rhs, x : host arrays of n doubles (may alias).
+ *   *nlev  : receives the number of reduction levels (may be NULL).
+ * Touches no GPU; returns WD_ERR_INVALID_ARG for bad sizes or codes. */
+int wd_line_solve_host(int kind, int n, int periodic, int scheme,
+                       double alpha_f, int fp64, const double *rhs, double *x,
+                       int *nlev);
+
+/* ---- serving (continuous batching) ---------------------------------- */
+/* A host thread owns a stream and a device arena of `budget_bytes`.  It
+ * admits queued requests while their workspace fits in the arena and a slot
+ * (of max_slots) is free, advances every admitted grid together, and
+ * retires each one as soon as it stops.  Requests admitted while others run
+ * join at the next iteration boundary.  Results do not depend on what else
+ * runs (bitwise equal to wd_solve). */
+int wd_server_create(wd_ctx *ctx, size_t budget_bytes, int max_slots,
+                     wd_server **out);
+
+/* Queue one solve.  desc/method are copied; desc->metrics, desc->mask and
+ * phi (device) must stay valid until the request finishes.  session >= 0
+ * serialises requests of one session in submission order (an unsteady
+ * sequence re-solved with warm_start from its previous field); -1 = none.
+ * hist_cap (>= 0) FP64 history pairs are kept for wd_server_history.
+ * *req_id receives the request id. */
+int wd_server_submit(wd_server *srv, const wd_grid_desc *desc,
+                     const wd_method *method, void *phi, long long session,
+                     int hist_cap, long long *req_id);
+
+/* State of a request: *status = WD_PENDING while queued or running, else
+ * its final status; times (host seconds, steady clock) of submission,
+ * admission and completion; iterations.  Any output pointer may be NULL. */
+int wd_server_poll(wd_server *srv, long long req_id, int *status,
+                   double *t_submit, double *t_admit, double *t_done,
+                   int *iters);
+
+/* Block until the request finishes or timeout_s passes (< 0: no limit). */
+int wd_server_wait(wd_server *srv, long long req_id, double timeout_s);
+
+/* Copy a finished request's history (host, 2*cap doubles); *n receives the
+ * number of pairs written. */
+int wd_server_history(wd_server *srv, long long req_id, double *hist, int cap,
+                      int *n);
+
+/* Cancel a queued or running request (its phi is left as it stands). */
+int wd_server_cancel(wd_server *srv, long long req_id);
+
+/* Counters: requests done, iterations advanced, peak arena bytes, peak
+ * concurrent grids.  Any pointer may be NULL. */
+int wd_server_stats(wd_server *srv, long long *done, long long *iterations,
+                    size_t *peak_bytes, int *peak_active);
+
+/* Stop the thread (running requests are cancelled) and free the arena. */
+int wd_server_destroy(wd_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,93 @@
+// wd_common.h -- structures shared by the host planner and the gfx950
+// kernels of the wall-distance library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace wd {
+
+constexpr int kThreads = 512;             // threads per workgroup (8 waves)
+constexpr int kPPT = 8;                   // max points per thread in a tile
+constexpr int kTileMax = kThreads * kPPT; // max points held by one tile
+constexpr int kMaxLev = 14;               // max PCR levels of a line system
+constexpr int kChunk = 4096;              // points per pointwise work item
+constexpr int kMaxLine = kTileMax;        // longest grid line supported
+
+// A tridiagonal line system whose matrix does not depend on the data
+// (compact first derivative or filter correction).  The host reduces it by
+// parallel cyclic reduction once, in FP64, and stores per level and per
+// position the two multipliers that fold the neighbours at distance
+// s = 2^level into the right-hand side.  After `nlev` levels every row is
+// decoupled to within rounding and x_i = d_i * scale_i.
+struct LineOpDev {
+    int n;
+    int periodic;
+    int nlev;                 // 0: no solve (explicit scheme), scale == 1
+    int pad;
+    int smod[kMaxLev];        // neighbour distance of each level (mod n)
+    const void *tab;          // T2 [nlev][n]: (left, right) multipliers
+    const void *scale;        // T [n]
+};
+
+enum GridMode { MODE_CART = 0, MODE_GENERAL = 1 };
+enum { XBC_NONE = 0, XBC_NEUMANN = 1, XBC_OUTFLOW = 2 };
+
+// Per-grid state kept on the device.
+struct GridState {
+    int done;                 // set once the grid has stopped
+    int iter;                 // pseudo iterations completed
+    int status;               // wd status code
+    int best_iter;            // iteration of the smallest max change
+    double best;              // smallest max change so far
+    double last;              // last max change
+};
+
+// Everything a kernel needs about one grid of a batch.
+struct GridDev {
+    int ndim, mode;
+    int n[3];
+    long long N;
+    long long stride[3];
+    int periodic[3];
+    int wall_lo[3], wall_hi[3];
+    int xbc[6];               // XBC_* per face (dir*2 + side)
+    int uniform;
+    double invh[3];
+    double jump[3];           // coordinate seam jump (metric helper only)
+    const void *met;          // FIELDS metrics (T), ndim*ndim SoA
+    const unsigned char *mask;
+
+    // method
+    int eq, lad, curv, scheme, rk, need_lap, filter, fused_resid;
+    int stages;
+    double eps, C, nu0, eps0, sigma, kp, tol;
+    int max_iter, stall;
+    int warm;                 // initial field given by the caller
+    double fcoef[6];          // filter correction factor for N = 1..5
+    double da, db, dc;        // interior derivative coefficients
+    int dradius, compact;
+
+    // buffers (T unless stated)
+    void *phi, *ps, *acc, *dt;
+    void *F[3];
+    void *P[3];               // partial sums carried between passes
+    double *rpart;            // [nparts][2] residual partials
+    double *hist;             // [hist_cap][2]
+    int hist_cap;
+    int nparts;
+    GridState *state;
+
+    LineOpDev dop[3];         // first-derivative operator per direction
+    LineOpDev fop[3];         // filter-correction operator per direction
+    int tw[3];                // tile width (lines per tile) per direction
+    int ntiles[3];
+    int nchunks;              // pointwise work items
+};
+
+struct Item {
+    int grid;
+    int tile;
+};
+
+}  // namespace wd

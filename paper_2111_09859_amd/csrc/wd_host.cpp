@@ -1,0 +1,1120 @@
+// wd_host.cpp -- host side of the wall-distance library: contexts, line
+// operator tables, batch planning, graph-captured iteration and the C ABI
+// entry points declared in include/wd.h (except the server).
+#include "wd_host.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace wd {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+// ---------------------------------------------------------------------
+// Line systems.  Rows a_i x_{i-1} + b_i x_i + c_i x_{i+1}; for periodic
+// lines a_0 multiplies x_{n-1} and c_{n-1} multiplies x_0.
+
+// compact first derivative (Sec. 3.2): interior (al, 1, al); non-periodic
+// ends: the fourth-order one-sided relation f'_0 + 3 f'_1 (and mirror),
+// and for C6 the C4 row (1/4, 1, 1/4) next to it.
+static void deriv_rows(int n, int periodic, int scheme, std::vector<double> &a,
+                       std::vector<double> &b, std::vector<double> &c)
+{
+    const double al = scheme == SCHEME_C4 ? 0.25 : 1.0 / 3.0;
+    a.assign(n, al);
+    b.assign(n, 1.0);
+    c.assign(n, al);
+    if (periodic) return;
+    a[0] = 0.0; c[0] = 3.0;
+    a[n - 1] = 3.0; c[n - 1] = 0.0;
+    if (scheme == SCHEME_C6) {
+        a[1] = c[1] = 0.25;
+        a[n - 2] = c[n - 2] = 0.25;
+    }
+}
+
+// filter correction (Sec. 3.4): (af, 1, af); non-periodic boundary points
+// are not filtered (identity rows with zero right-hand side).
+static void filter_rows(int n, int periodic, double af, std::vector<double> &a,
+                        std::vector<double> &b, std::vector<double> &c)
+{
+    a.assign(n, af);
+    b.assign(n, 1.0);
+    c.assign(n, af);
+    if (periodic) return;
+    a[0] = c[0] = 0.0;
+    a[n - 1] = c[n - 1] = 0.0;
+}
+
+// Parallel cyclic reduction of a fixed matrix, FP64.  Level k folds the
+// rows at distance s = 2^k (mod n) into each row: multipliers
+//   left_i = -a_i / b_{i-s},  right_i = -c_i / b_{i+s}.
+// Stops when every row's off-diagonal weight is below `tol` relative to its
+// diagonal, or, on a periodic line, when the distance wraps onto the point
+// itself (then the couplings fold into the diagonal exactly).
+int pcr_reduce(int n, int periodic, std::vector<double> a, std::vector<double> b,
+               std::vector<double> c, double tol, std::vector<int> &smod,
+               std::vector<double> &left, std::vector<double> &right,
+               std::vector<double> &scale)
+{
+    smod.clear();
+    left.clear();
+    right.clear();
+    long long s = 1;
+    int lev = 0;
+    for (;;) {
+        double worst = 0.0;
+        for (int i = 0; i < n; ++i)
+            worst = std::max(worst, (std::fabs(a[i]) + std::fabs(c[i])) / std::fabs(b[i]));
+        if (worst <= tol) break;
+        if (periodic && s % n == 0) {
+            for (int i = 0; i < n; ++i) {
+                b[i] += a[i] + c[i];
+                a[i] = c[i] = 0.0;
+            }
+            break;
+        }
+        if (!periodic && s >= n) break;
+        if (lev == kMaxLev) return -1;
+        const int sm = (int)(periodic ? s % n : s);
+        std::vector<double> a2(n), b2(n), c2(n);
+        left.resize((size_t)(lev + 1) * n);
+        right.resize((size_t)(lev + 1) * n);
+        for (int i = 0; i < n; ++i) {
+            int im = i - sm, ip = i + sm;
+            const bool hm = periodic || im >= 0;
+            const bool hp = periodic || ip < n;
+            if (periodic) {
+                im = (im + n) % n;
+                ip = ip % n;
+            }
+            const double L = hm ? -a[i] / b[im] : 0.0;
+            const double R = hp ? -c[i] / b[ip] : 0.0;
+            a2[i] = hm ? L * a[im] : 0.0;
+            c2[i] = hp ? R * c[ip] : 0.0;
+            b2[i] = b[i] + (hm ? L * c[im] : 0.0) + (hp ? R * a[ip] : 0.0);
+            left[(size_t)lev * n + i] = L;
+            right[(size_t)lev * n + i] = R;
+        }
+        a.swap(a2);
+        b.swap(b2);
+        c.swap(c2);
+        smod.push_back(sm);
+        ++lev;
+        s *= 2;
+    }
+    scale.resize(n);
+    for (int i = 0; i < n; ++i) scale[i] = 1.0 / b[i];
+    return lev;
+}
+
+static double pcr_tol(int fp64) { return fp64 ? std::ldexp(1.0, -57) : std::ldexp(1.0, -30); }
+
+int build_line_system(int kind, int n, int periodic, int scheme, double af,
+                      int fp64, std::vector<int> &smod, std::vector<double> &left,
+                      std::vector<double> &right, std::vector<double> &scale)
+{
+    std::vector<double> a, b, c;
+    if (kind == OP_FILTER)
+        filter_rows(n, periodic, af, a, b, c);
+    else
+        deriv_rows(n, periodic, scheme, a, b, c);
+    return pcr_reduce(n, periodic, a, b, c, pcr_tol(fp64), smod, left, right, scale);
+}
+
+const LineOpDev *ctx_lineop(wd_ctx *ctx, int kind, int n, int periodic, int scheme,
+                            double af, int fp64)
+{
+    OpKey key{kind, n, periodic, kind == OP_FILTER ? -1 : scheme, fp64,
+              kind == OP_FILTER ? af : 0.0};
+    auto it = ctx->ops.find(key);
+    if (it != ctx->ops.end()) return &it->second.dev;
+    OpEntry e;
+    std::memset(&e.dev, 0, sizeof e.dev);
+    e.dev.n = n;
+    e.dev.periodic = periodic;
+    const bool solve = kind == OP_FILTER || scheme == SCHEME_C4 || scheme == SCHEME_C6;
+    std::vector<int> smod;
+    std::vector<double> left, right, scale;
+    int nlev = 0;
+    if (solve) {
+        nlev = build_line_system(kind, n, periodic, scheme, af, fp64, smod, left, right, scale);
+        if (nlev < 0) {
+            fail(WD_ERR_UNSUPPORTED, "line system (n=%d) did not reduce within %d levels", n, kMaxLev);
+            return nullptr;
+        }
+    } else {
+        scale.assign(n, 1.0);
+    }
+    e.dev.nlev = nlev;
+    for (int k = 0; k < nlev; ++k) e.dev.smod[k] = smod[k];
+    const size_t es = fp64 ? 8 : 4;
+    const size_t tab_bytes = (size_t)nlev * n * 2 * es;
+    const size_t bytes = tab_bytes + (size_t)n * es + 256;
+    void *mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) {
+        fail(WD_ERR_NO_MEMORY, "hipMalloc of %zu bytes for a line operator failed", bytes);
+        return nullptr;
+    }
+    std::vector<unsigned char> host(bytes, 0);
+    for (size_t i = 0; i < (size_t)nlev * n; ++i) {
+        if (fp64) {
+            double *t = reinterpret_cast<double *>(host.data());
+            t[2 * i] = left[i];
+            t[2 * i + 1] = right[i];
+        } else {
+            float *t = reinterpret_cast<float *>(host.data());
+            t[2 * i] = (float)left[i];
+            t[2 * i + 1] = (float)right[i];
+        }
+    }
+    const size_t soff = (tab_bytes + 255) & ~(size_t)255;
+    for (int i = 0; i < n; ++i) {
+        if (fp64)
+            reinterpret_cast<double *>(host.data() + soff)[i] = scale[i];
+        else
+            reinterpret_cast<float *>(host.data() + soff)[i] = (float)scale[i];
+    }
+    if (hipMemcpy(mem, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(mem);
+        fail(WD_ERR_HIP, "upload of a line operator failed");
+        return nullptr;
+    }
+    e.mem = mem;
+    e.dev.tab = mem;
+    e.dev.scale = static_cast<unsigned char *>(mem) + soff;
+    auto ins = ctx->ops.emplace(key, e);
+    return &ins.first->second.dev;
+}
+
+// ---------------------------------------------------------------------
+// validation
+int check_desc(const wd_grid_desc *d)
+{
+    if (!d) return fail(WD_ERR_INVALID_ARG, "null grid descriptor");
+    if (d->ndim != 2 && d->ndim != 3) return fail(WD_ERR_INVALID_ARG, "ndim must be 2 or 3");
+    long long N = 1;
+    for (int l = 0; l < d->ndim; ++l) {
+        if (d->n[l] < 8) return fail(WD_ERR_INVALID_ARG, "n[%d] = %d < 8", l, d->n[l]);
+        if (d->n[l] > kMaxLine)
+            return fail(WD_ERR_UNSUPPORTED, "n[%d] = %d exceeds the line limit %d", l, d->n[l], kMaxLine);
+        for (int s = 0; s < 2; ++s)
+            if (d->bc[l][s] < WD_BC_WALL || d->bc[l][s] > WD_BC_PERIODIC)
+                return fail(WD_ERR_INVALID_ARG, "bad face code on direction %d", l);
+        if ((d->bc[l][0] == WD_BC_PERIODIC) != (d->bc[l][1] == WD_BC_PERIODIC))
+            return fail(WD_ERR_INVALID_ARG, "PERIODIC must be set on both faces of direction %d", l);
+        N *= d->n[l];
+    }
+    if (d->ndim == 2 && d->n[2] != 1) return fail(WD_ERR_INVALID_ARG, "2D grids need n[2] == 1");
+    if (N >= (1LL << 31)) return fail(WD_ERR_UNSUPPORTED, "grid of %lld points is too large", N);
+    if (d->metric_mode == WD_METRIC_UNIFORM) {
+        for (int l = 0; l < d->ndim; ++l)
+            if (!(d->h[l] > 0.0)) return fail(WD_ERR_INVALID_ARG, "h[%d] must be > 0", l);
+    } else if (d->metric_mode == WD_METRIC_FIELDS) {
+        if (d->ndim != 2) return fail(WD_ERR_UNSUPPORTED, "metric fields are supported on 2D grids");
+        if (!d->metrics) return fail(WD_ERR_INVALID_ARG, "metric fields pointer is null");
+    } else {
+        return fail(WD_ERR_INVALID_ARG, "bad metric mode");
+    }
+    return WD_OK;
+}
+
+int check_method(const wd_method *m)
+{
+    if (!m) return fail(WD_ERR_INVALID_ARG, "null method");
+    if (m->equation < WD_EQ_EIKONAL || m->equation > WD_EQ_POISSON) return fail(WD_ERR_INVALID_ARG, "bad equation");
+    if (m->gamma != WD_GAMMA_LINEAR && m->gamma != WD_GAMMA_LAD) return fail(WD_ERR_INVALID_ARG, "bad gamma");
+    if (m->scheme < WD_E2 || m->scheme > WD_C6) return fail(WD_ERR_INVALID_ARG, "bad scheme");
+    if (m->rk != WD_RK3_SSP && m->rk != WD_RK4) return fail(WD_ERR_INVALID_ARG, "bad rk");
+    if (m->precision != WD_FP32 && m->precision != WD_FP64) return fail(WD_ERR_INVALID_ARG, "bad precision");
+    if (m->filter && !(m->alpha_f >= 0.0 && m->alpha_f < 0.5))
+        return fail(WD_ERR_INVALID_ARG, "alpha_f must be in [0, 0.5) when the filter is on");
+    if (!(m->sigma > 0.0)) return fail(WD_ERR_INVALID_ARG, "sigma must be > 0");
+    if (m->max_iter < 1) return fail(WD_ERR_INVALID_ARG, "max_iter must be >= 1");
+    if (!(m->tol >= 0.0)) return fail(WD_ERR_INVALID_ARG, "tol must be >= 0");
+    if (m->stall_window < 0) return fail(WD_ERR_INVALID_ARG, "stall_window must be >= 0");
+    if (m->equation == WD_EQ_HJ && m->curvature && !(m->eps0 > 0.0))
+        return fail(WD_ERR_INVALID_ARG, "eps0 must be > 0");
+    return WD_OK;
+}
+
+static long long npoints(const wd_grid_desc &d)
+{
+    long long N = 1;
+    for (int l = 0; l < d.ndim; ++l) N *= d.n[l];
+    return N;
+}
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int grid_mode(const wd_grid_desc &d, const wd_method &m)
+{
+    const bool curv = m.equation == WD_EQ_HJ && m.curvature;
+    return (d.metric_mode == WD_METRIC_UNIFORM && !curv) ? MODE_CART : MODE_GENERAL;
+}
+
+int hist_dev_cap(const wd_method &m) { return std::min(m.max_iter, 1 << 17); }
+
+// device bytes of one grid's buffers
+static size_t grid_bytes(const wd_grid_desc &d, const wd_method &m)
+{
+    const long long N = npoints(d);
+    const size_t S = m.precision == WD_FP64 ? 8 : 4;
+    const size_t f = al256((size_t)N * S);
+    size_t b = 0;
+    b += f;                                      // ps
+    if (m.rk == WD_RK4) b += f;                  // acc
+    b += f;                                      // dt
+    if (grid_mode(d, m) == MODE_GENERAL) b += (size_t)d.ndim * f;  // F_l
+    b += 3 * f;                                  // partial sums
+    if (m.equation == WD_EQ_POISSON)
+        b += (size_t)(d.ndim + 1) * al256((size_t)N * 8);  // FP64 conversion
+    long long parts = N / d.n[d.ndim - 1];
+    parts = std::max(parts, (N + kChunk - 1) / kChunk);
+    b += al256((size_t)parts * 16);
+    b += al256((size_t)hist_dev_cap(m) * 16);
+    b += al256(sizeof(GridState));
+    return b;
+}
+
+// worst-case work items of one grid (tile width 1)
+static long long grid_items(const wd_grid_desc &d)
+{
+    const long long N = npoints(d);
+    long long lines = 0;
+    for (int l = 0; l < d.ndim; ++l) lines += N / d.n[l];
+    const long long chunks = (N + kChunk - 1) / kChunk;
+    long long face = 0;
+    for (int l = 0; l < d.ndim; ++l) face += 2 * ((N / d.n[l] + kChunk - 1) / kChunk);
+    return 5 * lines + 3 * chunks + 2 * face + 8;
+}
+
+size_t batch_bytes(int n, const wd_grid_desc *d, const wd_method *m)
+{
+    size_t b = al256((size_t)n * sizeof(GridDev)) + al256(sizeof(GridDev)) * 2;
+    long long items = 0;
+    for (int i = 0; i < n; ++i) {
+        b += grid_bytes(d[i], m[i]);
+        items += grid_items(d[i]);
+    }
+    b += al256((size_t)items * sizeof(Item));
+    b += al256((size_t)(n + 1) * sizeof(GridState));
+    return b + 4096;
+}
+
+// ---------------------------------------------------------------------
+// tile widths
+int pick_tile(wd_ctx *ctx, const wd_grid_desc &d, int l, int fp64)
+{
+    TuneKey key{d.ndim, d.n[0], d.n[1], d.n[2], l, fp64};
+    auto it = ctx->tune.find(key);
+    if (it != ctx->tune.end()) return it->second;
+    const long long N = npoints(d);
+    const int n = d.n[l];
+    const long long target = 2LL * ctx->cus;
+    int w;
+    if (l == 0) {
+        const long long lines = N / n;
+        w = std::max(1, kTileMax / n);
+        while (w > 1 && (lines + w - 1) / w < target) w /= 2;
+    } else {
+        int wmax = std::max(1, std::min(64, kTileMax / n));
+        w = 1;
+        while (w * 2 <= wmax) w *= 2;
+        const long long planes = N / ((long long)d.n[0] * n);
+        while (w > 4 && planes * ((d.n[0] + w - 1) / w) < target) w /= 2;
+    }
+    return w;
+}
+
+static double kprime(int scheme)
+{
+    switch (scheme) {
+    case WD_E2: return 1.0;
+    case WD_E4: return 1.372;
+    case WD_E6: return 1.586;
+    case WD_C4: return 1.732;
+    default: return 1.989;
+    }
+}
+
+// ---------------------------------------------------------------------
+// planning of a batch into a caller workspace
+int plan_batch(wd_ctx *ctx, int n, const wd_grid_desc *descs, const wd_method *meths,
+               void *const *phis, void *ws, size_t ws_bytes, Plan &P)
+{
+    P = Plan();
+    P.n = n;
+    P.fp64 = meths[0].precision == WD_FP64;
+    P.rk = meths[0].rk;
+    P.stages = P.rk == WD_RK4 ? 4 : 3;
+    P.maxdim = 0;
+    const size_t need = batch_bytes(n, descs, meths);
+    if (!ws || ws_bytes < need)
+        return fail(WD_ERR_NO_MEMORY, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    unsigned char *base = static_cast<unsigned char *>(ws);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        void *p = base + off;
+        off += al256(bytes);
+        return p;
+    };
+    P.d_grids = static_cast<GridDev *>(take((size_t)n * sizeof(GridDev)));
+    P.d_aux = static_cast<GridDev *>(take(sizeof(GridDev)));
+    P.d_aux2 = static_cast<GridDev *>(take(sizeof(GridDev)));
+    P.d_states = static_cast<GridState *>(take((size_t)(n + 1) * sizeof(GridState)));
+    long long items_cap = 0;
+    for (int i = 0; i < n; ++i) items_cap += grid_items(descs[i]);
+    P.d_items = static_cast<Item *>(take((size_t)items_cap * sizeof(Item)));
+    P.grids.resize(n);
+    const size_t S = P.fp64 ? 8 : 4;
+    for (int i = 0; i < n; ++i) {
+        const wd_grid_desc &d = descs[i];
+        const wd_method &m = meths[i];
+        GridDev &g = P.grids[i];
+        std::memset(&g, 0, sizeof g);
+        const long long N = npoints(d);
+        g.ndim = d.ndim;
+        g.mode = grid_mode(d, m);
+        g.N = N;
+        long long st = 1;
+        for (int l = 0; l < 3; ++l) {
+            g.n[l] = l < d.ndim ? d.n[l] : 1;
+            g.stride[l] = st;
+            st *= g.n[l];
+        }
+        for (int l = 0; l < d.ndim; ++l) {
+            g.periodic[l] = d.bc[l][0] == WD_BC_PERIODIC;
+            g.wall_lo[l] = d.bc[l][0] == WD_BC_WALL;
+            g.wall_hi[l] = d.bc[l][1] == WD_BC_WALL;
+            for (int s = 0; s < 2; ++s) {
+                const int b = d.bc[l][s];
+                g.xbc[2 * l + s] = b == WD_BC_NEUMANN ? XBC_NEUMANN : b == WD_BC_OUTFLOW ? XBC_OUTFLOW : XBC_NONE;
+            }
+        }
+        g.uniform = d.metric_mode == WD_METRIC_UNIFORM;
+        for (int l = 0; l < 3; ++l) g.invh[l] = (g.uniform && l < d.ndim) ? 1.0 / d.h[l] : 0.0;
+        g.met = d.metrics;
+        g.mask = d.mask;
+        g.eq = m.equation;
+        g.lad = m.equation == WD_EQ_HJ && m.gamma == WD_GAMMA_LAD;
+        g.curv = m.equation == WD_EQ_HJ && m.curvature;
+        g.scheme = m.scheme;
+        g.rk = m.rk == WD_RK4;
+        g.stages = P.stages;
+        g.need_lap = m.equation != WD_EQ_EIKONAL;
+        g.filter = m.filter;
+        bool has_x = false;
+        for (int f = 0; f < 6; ++f) has_x |= g.xbc[f] != XBC_NONE;
+        g.fused_resid = m.filter && !has_x;
+        g.eps = m.eps;
+        g.C = m.c_lad;
+        g.nu0 = m.nu0;
+        g.eps0 = m.eps0;
+        g.sigma = m.sigma;
+        g.kp = kprime(m.scheme);
+        g.tol = m.tol;
+        g.max_iter = m.max_iter;
+        g.stall = m.stall_window;
+        g.warm = m.warm_start;
+        // filter correction factor -(1 - 2 af)(-1)^N / 4^N
+        for (int N5 = 1; N5 <= 5; ++N5)
+            g.fcoef[N5] = -(1.0 - 2.0 * m.alpha_f) * ((N5 & 1) ? -1.0 : 1.0) / std::ldexp(1.0, 2 * N5);
+        switch (m.scheme) {
+        case WD_E2: g.da = 1.0; g.dradius = 1; break;
+        case WD_E4: g.da = 4.0 / 3.0; g.db = -1.0 / 3.0; g.dradius = 2; break;
+        case WD_E6: g.da = 1.5; g.db = -0.6; g.dc = 0.1; g.dradius = 3; break;
+        case WD_C4: g.da = 1.5; g.dradius = 1; g.compact = 1; break;
+        default: g.da = 14.0 / 9.0; g.db = 1.0 / 9.0; g.dradius = 2; g.compact = 1; break;
+        }
+        const size_t f = (size_t)N * S;
+        g.phi = phis ? phis[i] : nullptr;
+        g.ps = take(f);
+        g.acc = m.rk == WD_RK4 ? take(f) : nullptr;
+        g.dt = take(f);
+        if (g.mode == MODE_GENERAL)
+            for (int l = 0; l < d.ndim; ++l) g.F[l] = take(f);
+        for (int k = 0; k < 3; ++k) g.P[k] = take(f);
+        if (m.equation == WD_EQ_POISSON) {
+            P.pois_phip.push_back(take((size_t)N * 8));
+            for (int l = 0; l < 3; ++l) P.pois_F.push_back(l < d.ndim ? take((size_t)N * 8) : nullptr);
+        }
+        long long parts = N / d.n[d.ndim - 1];
+        parts = std::max(parts, (N + kChunk - 1) / kChunk);
+        g.rpart = static_cast<double *>(take((size_t)parts * 16));
+        g.hist_cap = hist_dev_cap(m);
+        g.hist = static_cast<double *>(take((size_t)g.hist_cap * 16));
+        g.state = P.d_states + i;
+        for (int l = 0; l < d.ndim; ++l) {
+            const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, d.n[l], g.periodic[l], m.scheme, 0.0, P.fp64);
+            if (!dop) return WD_ERR_NO_MEMORY;
+            g.dop[l] = *dop;
+            if (m.filter) {
+                const LineOpDev *fop = ctx_lineop(ctx, OP_FILTER, d.n[l], g.periodic[l], m.scheme, m.alpha_f, P.fp64);
+                if (!fop) return WD_ERR_NO_MEMORY;
+                g.fop[l] = *fop;
+            }
+            g.tw[l] = pick_tile(ctx, d, l, P.fp64);
+            if (l == 0)
+                g.ntiles[l] = (int)((N / d.n[0] + g.tw[0] - 1) / g.tw[0]);
+            else
+                g.ntiles[l] = (int)((N / ((long long)d.n[0] * d.n[l])) * ((d.n[0] + g.tw[l] - 1) / g.tw[l]));
+        }
+        g.nchunks = (int)((N + kChunk - 1) / kChunk);
+        g.nparts = g.fused_resid ? g.ntiles[d.ndim - 1] : g.nchunks;
+        P.maxdim = std::max(P.maxdim, d.ndim);
+    }
+    if (off > ws_bytes) return fail(WD_ERR_NO_MEMORY, "workspace layout overflow");
+    build_items(P);
+    if ((long long)P.items.size() > items_cap) return fail(WD_ERR_INVALID_ARG, "internal: item overflow");
+    return WD_OK;
+}
+
+// work lists in launch order
+void build_items(Plan &P)
+{
+    P.items.clear();
+    P.lists.clear();
+    auto list = [&](int kind, int l, int stage_arg) -> ItemList & {
+        ItemList L;
+        L.kind = kind;
+        L.l = l;
+        L.arg = stage_arg;
+        L.first = (int)P.items.size();
+        L.count = 0;
+        P.lists.push_back(L);
+        return P.lists.back();
+    };
+    auto add_tiles = [&](ItemList &L, int gi, int nt) {
+        for (int t = 0; t < nt; ++t) P.items.push_back(Item{gi, t});
+        L.count += nt;
+    };
+    const int n = P.n;
+    // directional passes
+    for (int l = 0; l < 3; ++l) {
+        ItemList &L = list(PASS_CART, l, 0);
+        for (int i = 0; i < n; ++i)
+            if (P.grids[i].mode == MODE_CART && l < P.grids[i].ndim) add_tiles(L, i, P.grids[i].ntiles[l]);
+        P.cart[l] = (int)P.lists.size() - 1;
+    }
+    for (int l = 0; l < 3; ++l) {
+        ItemList &L = list(PASS_D1, l, 0);
+        for (int i = 0; i < n; ++i)
+            if (P.grids[i].mode == MODE_GENERAL && l < P.grids[i].ndim) add_tiles(L, i, P.grids[i].ntiles[l]);
+        P.d1[l] = (int)P.lists.size() - 1;
+    }
+    for (int l = 0; l < 3; ++l) {
+        ItemList &L = list(PASS_D2, l, 0);
+        for (int i = 0; i < n; ++i)
+            if (P.grids[i].mode == MODE_GENERAL && P.grids[i].need_lap && l < P.grids[i].ndim)
+                add_tiles(L, i, P.grids[i].ntiles[l]);
+        P.d2[l] = (int)P.lists.size() - 1;
+    }
+    {
+        ItemList &L = list(PASS_FINAL, 0, 0);
+        for (int i = 0; i < n; ++i)
+            if (P.grids[i].mode == MODE_GENERAL && !P.grids[i].need_lap) add_tiles(L, i, P.grids[i].nchunks);
+        P.fin = (int)P.lists.size() - 1;
+    }
+    for (int l = 0; l < 3; ++l) {
+        ItemList &L = list(PASS_LAD, l, 0);
+        for (int i = 0; i < n; ++i)
+            if (P.grids[i].lad && l < P.grids[i].ndim) add_tiles(L, i, P.grids[i].ntiles[l]);
+        P.lad[l] = (int)P.lists.size() - 1;
+    }
+    for (int l = 0; l < 3; ++l) {
+        ItemList &L = list(PASS_FILTER, l, 0);
+        for (int i = 0; i < n; ++i)
+            if (P.grids[i].filter && l < P.grids[i].ndim) add_tiles(L, i, P.grids[i].ntiles[l]);
+        P.filt[l] = (int)P.lists.size() - 1;
+    }
+    {
+        ItemList &L = list(PASS_RESID, 0, 0);
+        for (int i = 0; i < n; ++i)
+            if (!P.grids[i].fused_resid) add_tiles(L, i, P.grids[i].nchunks);
+        P.resid = (int)P.lists.size() - 1;
+    }
+    for (int f = 0; f < 6; ++f) {
+        ItemList &L = list(PASS_FACE, f, 1);
+        for (int i = 0; i < n; ++i) {
+            const GridDev &g = P.grids[i];
+            const int l = f >> 1;
+            if (l < g.ndim && g.xbc[f] != XBC_NONE) {
+                const long long nf = g.N / g.n[l];
+                add_tiles(L, i, (int)((nf + kChunk - 1) / kChunk));
+            }
+        }
+        P.face[f] = (int)P.lists.size() - 1;
+    }
+    {
+        ItemList &L = list(PASS_INIT, 0, 0);
+        for (int i = 0; i < n; ++i) add_tiles(L, i, P.grids[i].nchunks);
+        P.init = (int)P.lists.size() - 1;
+    }
+}
+
+// ---------------------------------------------------------------------
+// issuing work
+static int nwg_for(wd_ctx *ctx, int fp64, int count)
+{
+    int cap = ctx->cus * (fp64 ? 2 : 4);
+    cap = std::max(8, cap & ~7);
+    return std::min(count, cap);
+}
+
+void issue_list(wd_ctx *ctx, const Plan &P, int li, int stage, hipStream_t s)
+{
+    const ItemList &L = P.lists[li];
+    if (L.count == 0) return;
+    const int arg = (L.kind == PASS_FACE || L.kind == PASS_INIT) ? L.arg : stage;
+    launch_pass(L.kind, P.fp64, P.d_grids, P.d_items + L.first, L.count, L.l, arg,
+                nwg_for(ctx, P.fp64, L.count), s);
+}
+
+void issue_faces(wd_ctx *ctx, const Plan &P, int target, hipStream_t s)
+{
+    for (int f = 0; f < 6; ++f) {
+        const ItemList &L = P.lists[P.face[f]];
+        if (L.count == 0) continue;
+        launch_pass(PASS_FACE, P.fp64, P.d_grids, P.d_items + L.first, L.count, f, target,
+                    nwg_for(ctx, P.fp64, L.count), s);
+    }
+}
+
+void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s)
+{
+    // LAD diffusivity from phi^n: sensor, then smoothing, per direction
+    for (int mode = 0; mode < 2; ++mode)
+        for (int l = 0; l < P.maxdim; ++l) issue_list(ctx, P, P.lad[l], mode, s);
+    for (int st = 0; st < P.stages; ++st) {
+        for (int l = 0; l < P.maxdim; ++l) {
+            issue_list(ctx, P, P.cart[l], st, s);
+            issue_list(ctx, P, P.d1[l], st, s);
+        }
+        for (int l = 0; l < P.maxdim; ++l) issue_list(ctx, P, P.d2[l], st, s);
+        issue_list(ctx, P, P.fin, st, s);
+        issue_faces(ctx, P, 1, s);
+    }
+    for (int l = 0; l < P.maxdim; ++l) issue_list(ctx, P, P.filt[l], 0, s);
+    issue_faces(ctx, P, 1, s);
+    issue_list(ctx, P, P.resid, 0, s);
+    launch_finalize(P.d_grids, P.n, s);
+}
+
+void issue_init(wd_ctx *ctx, const Plan &P, hipStream_t s)
+{
+    issue_list(ctx, P, P.init, 0, s);
+    issue_faces(ctx, P, 0, s);
+}
+
+int upload_plan(wd_ctx *ctx, const Plan &P, hipStream_t s)
+{
+    if (hipMemcpyAsync(P.d_grids, P.grids.data(), P.grids.size() * sizeof(GridDev),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(P.d_items, P.items.data(), P.items.size() * sizeof(Item),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(WD_ERR_HIP, "plan upload failed");
+    (void)ctx;
+    return WD_OK;
+}
+
+// ---------------------------------------------------------------------
+// graphs of K iterations, cached per plan
+static bool same_plan(const Plan &a, const CachedGraph &c)
+{
+    if (a.grids.size() * sizeof(GridDev) != c.grids_bytes.size()) return false;
+    if (a.items.size() * sizeof(Item) != c.items_bytes.size()) return false;
+    if (std::memcmp(a.grids.data(), c.grids_bytes.data(), c.grids_bytes.size()) != 0) return false;
+    if (std::memcmp(a.items.data(), c.items_bytes.data(), c.items_bytes.size()) != 0) return false;
+    return a.d_grids == c.d_grids && a.d_items == c.d_items;
+}
+
+hipGraphExec_t graph_for(wd_ctx *ctx, const Plan &P, int K)
+{
+    for (auto &c : ctx->graphs)
+        if (c.K == K && same_plan(P, c)) {
+            c.stamp = ++ctx->clock;
+            return c.exec;
+        }
+    hipStream_t s = ctx->stream;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        fail(WD_ERR_HIP, "hipStreamBeginCapture failed");
+        return nullptr;
+    }
+    for (int k = 0; k < K; ++k) issue_iteration(ctx, P, s);
+    hipGraph_t graph = nullptr;
+    if (hipStreamEndCapture(s, &graph) != hipSuccess || !graph) {
+        fail(WD_ERR_HIP, "hipStreamEndCapture failed");
+        return nullptr;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        fail(WD_ERR_HIP, "hipGraphInstantiate failed");
+        return nullptr;
+    }
+    (void)hipGraphDestroy(graph);
+    if (ctx->graphs.size() >= 16) {
+        auto oldest = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                       [](const CachedGraph &a, const CachedGraph &b) { return a.stamp < b.stamp; });
+        (void)hipGraphExecDestroy(oldest->exec);
+        ctx->graphs.erase(oldest);
+    }
+    CachedGraph c;
+    c.K = K;
+    c.exec = exec;
+    c.d_grids = P.d_grids;
+    c.d_items = P.d_items;
+    c.grids_bytes.assign(reinterpret_cast<const unsigned char *>(P.grids.data()),
+                         reinterpret_cast<const unsigned char *>(P.grids.data()) + P.grids.size() * sizeof(GridDev));
+    c.items_bytes.assign(reinterpret_cast<const unsigned char *>(P.items.data()),
+                         reinterpret_cast<const unsigned char *>(P.items.data()) + P.items.size() * sizeof(Item));
+    c.stamp = ++ctx->clock;
+    ctx->graphs.push_back(std::move(c));
+    return exec;
+}
+
+void ctx_drop_graphs(wd_ctx *ctx)
+{
+    for (auto &c : ctx->graphs) (void)hipGraphExecDestroy(c.exec);
+    ctx->graphs.clear();
+}
+
+// Iterate until every grid of the plan has stopped.  States are read back
+// after each graph replay of K iterations.
+int run_plan(wd_ctx *ctx, const Plan &P, int K, std::vector<GridState> &states)
+{
+    hipStream_t s = ctx->stream;
+    int maxit = 0;
+    for (int i = 0; i < P.n; ++i) maxit = std::max(maxit, P.grids[i].max_iter);
+    const int use_graph = ctx->use_graphs;
+    hipGraphExec_t exec = use_graph ? graph_for(ctx, P, K) : nullptr;
+    if (use_graph && !exec) return WD_ERR_HIP;
+    states.resize(P.n);
+    const long long max_rounds = (maxit + K - 1) / K + 1;
+    for (long long r = 0; r < max_rounds; ++r) {
+        if (exec) {
+            if (hipGraphLaunch(exec, s) != hipSuccess) return fail(WD_ERR_HIP, "hipGraphLaunch failed");
+        } else {
+            for (int k = 0; k < K; ++k) issue_iteration(ctx, P, s);
+        }
+        if (hipMemcpyAsync(ctx->pinned_states, P.d_states, P.n * sizeof(GridState),
+                           hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(WD_ERR_HIP, "state read-back failed: %s", hipGetErrorString(hipGetLastError()));
+        bool all = true;
+        for (int i = 0; i < P.n; ++i) {
+            states[i] = ctx->pinned_states[i];
+            all &= states[i].done != 0;
+        }
+        if (all) return WD_OK;
+    }
+    return fail(WD_ERR_HIP, "grids did not stop within max_iter");
+}
+
+// FP64 Poisson conversion of grid i of a plan (after the march): phi' is in
+// g.phi (solve precision); the distance replaces it, phi' goes to aux.
+int poisson_convert(wd_ctx *ctx, const Plan &P, int i, int pidx, void *aux, hipStream_t s)
+{
+    const GridDev &g = P.grids[i];
+    const size_t S = P.fp64 ? 8 : 4;
+    if (aux && hipMemcpyAsync(aux, g.phi, (size_t)g.N * S, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(WD_ERR_HIP, "copy of phi' failed");
+    double *phip = static_cast<double *>(P.pois_phip[pidx]);
+    launch_convert(P.fp64, 1, g.phi, phip, g.N, s);
+    // FP64 first derivatives of phi' with a one-grid FP64 view
+    GridDev v = g;
+    v.phi = phip;
+    v.lad = 0;
+    for (int l = 0; l < g.ndim; ++l) {
+        v.F[l] = P.pois_F[(size_t)pidx * 3 + l];
+        const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, g.n[l], g.periodic[l], g.scheme, 0.0, 1);
+        if (!dop) return WD_ERR_NO_MEMORY;
+        v.dop[l] = *dop;
+    }
+    v.state = P.d_states + P.n;  // scratch state, never done
+    GridState zero{};
+    std::vector<Item> items;
+    if (hipMemcpyAsync(v.state, &zero, sizeof zero, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(P.d_aux, &v, sizeof v, hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(WD_ERR_HIP, "poisson view upload failed");
+    (void)items;
+    for (int l = 0; l < g.ndim; ++l) {
+        const int nt = g.ntiles[l];
+        std::vector<Item> it(nt);
+        for (int t = 0; t < nt; ++t) it[t] = Item{0, t};
+        Item *d_it = P.d_items + P.items.size();  // spare item space after the plan's lists
+        if (hipMemcpyAsync(d_it, it.data(), nt * sizeof(Item), hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(WD_ERR_HIP, "poisson items upload failed");
+        launch_pass(PASS_D1, 1, P.d_aux, d_it, nt, l, 0, nwg_for(ctx, 1, nt), s);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(WD_ERR_HIP, "poisson pass failed");
+    }
+    GridDev w = g;  // metrics in the solve precision, F in FP64
+    for (int l = 0; l < g.ndim; ++l) w.F[l] = v.F[l];
+    if (hipMemcpyAsync(P.d_aux2, &w, sizeof w, hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(WD_ERR_HIP, "poisson view upload failed");
+    launch_poisson_dist(P.d_aux2, P.fp64, g.N, phip, g.phi, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(WD_ERR_HIP, "poisson conversion failed");
+    return WD_OK;
+}
+
+// one batch from start to finish on the context stream
+int solve_plan(wd_ctx *ctx, Plan &P, void *const *aux, double *const *hists, int hist_cap,
+               int *iters, int *status)
+{
+    hipStream_t s = ctx->stream;
+    int rc = upload_plan(ctx, P, s);
+    if (rc) return rc;
+    issue_init(ctx, P, s);
+    std::vector<GridState> states;
+    rc = run_plan(ctx, P, ctx->graph_iters, states);
+    if (rc) return rc;
+    int worst = WD_OK;
+    int pidx = 0;
+    for (int i = 0; i < P.n; ++i) {
+        const GridDev &g = P.grids[i];
+        int st = states[i].status;
+        if (g.eq == 2) {
+            int r2 = poisson_convert(ctx, P, i, pidx, aux ? aux[i] : nullptr, s);
+            ++pidx;
+            if (r2) return r2;
+        }
+        if (iters) iters[i] = states[i].iter;
+        if (status) status[i] = st;
+        if (hists && hists[i] && hist_cap > 0) {
+            const int nh = std::min(std::min(states[i].iter, hist_cap), g.hist_cap);
+            if (nh > 0 &&
+                hipMemcpyAsync(hists[i], g.hist, (size_t)nh * 16, hipMemcpyDeviceToHost, s) != hipSuccess)
+                return fail(WD_ERR_HIP, "history copy failed");
+        }
+        if (st < 0 && (worst >= 0 || st < worst)) worst = st;
+        else if (worst >= 0 && st > worst) worst = st;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(WD_ERR_HIP, "final sync failed");
+    if (worst == WD_ERR_DIVERGED) fail(WD_ERR_DIVERGED, "a pseudo-step change was not finite");
+    return worst;
+}
+
+}  // namespace wd
+
+// =====================================================================
+// C ABI
+using namespace wd;
+
+struct StreamJoin {
+    wd_ctx *ctx;
+    hipStream_t user;
+    StreamJoin(wd_ctx *c, void *stream) : ctx(c), user(static_cast<hipStream_t>(stream))
+    {
+        (void)hipEventRecord(ctx->ev_in, user);
+        (void)hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0);
+    }
+    ~StreamJoin()
+    {
+        (void)hipEventRecord(ctx->ev_out, ctx->stream);
+        (void)hipStreamWaitEvent(user, ctx->ev_out, 0);
+    }
+};
+
+extern "C" {
+
+const char *wd_version(void) { return "wd 1.0 gfx950"; }
+
+const char *wd_last_error(void) { return g_last_error.c_str(); }
+
+int wd_method_default(wd_method *m)
+{
+    if (!m) return fail(WD_ERR_INVALID_ARG, "null method");
+    std::memset(m, 0, sizeof *m);
+    m->equation = WD_EQ_HJ;
+    m->gamma = WD_GAMMA_LAD;
+    m->curvature = 0;
+    m->eps = 0.2;
+    m->c_lad = 0.1;
+    m->nu0 = 1e-3;
+    m->eps0 = 1e-6;
+    m->scheme = WD_C6;
+    m->filter = 1;
+    m->alpha_f = 0.495;
+    m->rk = WD_RK4;
+    m->sigma = 1.0;
+    m->tol = 1e-10;
+    m->max_iter = 100000;
+    m->stall_window = 0;
+    m->precision = WD_FP64;
+    m->warm_start = 0;
+    return WD_OK;
+}
+
+int wd_ctx_create(int device, wd_ctx **out)
+{
+    if (!out) return fail(WD_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return fail(WD_ERR_INVALID_ARG, "no HIP device %d (found %d)", device, count);
+    if (hipSetDevice(device) != hipSuccess) return fail(WD_ERR_HIP, "hipSetDevice(%d) failed", device);
+    wd_ctx *c = new wd_ctx();
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return fail(WD_ERR_HIP, "hipGetDeviceProperties failed");
+    }
+    c->cus = prop.multiProcessorCount;
+    std::snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void **)&c->pinned_states, sizeof(GridState) * 4096, 0) != hipSuccess) {
+        delete c;
+        return fail(WD_ERR_HIP, "stream/event/pinned allocation failed");
+    }
+    c->pinned_cap = 4096;
+    const char *g = std::getenv("WD_NO_GRAPHS");
+    c->use_graphs = !(g && g[0] == '1');
+    c->graph_iters = 32;
+    *out = c;
+    return WD_OK;
+}
+
+int wd_ctx_destroy(wd_ctx *ctx)
+{
+    if (!ctx) return WD_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx_drop_graphs(ctx);
+    for (auto &kv : ctx->ops) (void)hipFree(kv.second.mem);
+    if (ctx->pinned_states) (void)hipHostFree(ctx->pinned_states);
+    (void)hipEventDestroy(ctx->ev_in);
+    (void)hipEventDestroy(ctx->ev_out);
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return WD_OK;
+}
+
+int wd_workspace_bytes(wd_ctx *ctx, int n, const wd_grid_desc *descs,
+                       const wd_method *methods, size_t *bytes)
+{
+    (void)ctx;
+    if (!bytes || n < 1 || !descs || !methods) return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    for (int i = 0; i < n; ++i) {
+        int rc = check_desc(&descs[i]);
+        if (!rc) rc = check_method(&methods[i]);
+        if (rc) return rc;
+    }
+    *bytes = batch_bytes(n, descs, methods);
+    return WD_OK;
+}
+
+int wd_solve_batched(wd_ctx *ctx, int n, const wd_grid_desc *descs, const wd_method *methods,
+                     void *const *phis, void *const *aux, double *const *hists, int hist_cap,
+                     int *iters, int *status, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx || n < 1 || !descs || !methods || !phis) return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    for (int i = 0; i < n; ++i) {
+        int rc = check_desc(&descs[i]);
+        if (!rc) rc = check_method(&methods[i]);
+        if (rc) return rc;
+        if (!phis[i]) return fail(WD_ERR_INVALID_ARG, "phi[%d] is null", i);
+        if (methods[i].precision != methods[0].precision || methods[i].rk != methods[0].rk)
+            return fail(WD_ERR_UNSUPPORTED, "a batch needs one precision and one RK scheme");
+    }
+    if (n + 1 > ctx->pinned_cap) return fail(WD_ERR_UNSUPPORTED, "batch of %d grids is too large", n);
+    (void)hipSetDevice(ctx->device);
+    StreamJoin join(ctx, stream);
+    Plan P;
+    int rc = plan_batch(ctx, n, descs, methods, phis, ws, ws_bytes, P);
+    if (rc) return rc;
+    return solve_plan(ctx, P, aux, hists, hist_cap, iters, status);
+}
+
+int wd_solve(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method, void *phi,
+             void *phi_aux, double *hist, int hist_cap, int *iters, void *ws, size_t ws_bytes,
+             void *stream)
+{
+    void *phis[1] = {phi};
+    void *auxs[1] = {phi_aux};
+    double *hs[1] = {hist};
+    int st = 0;
+    int rc = wd_solve_batched(ctx, 1, desc, method, phis, auxs, hs, hist_cap, iters, &st, ws,
+                              ws_bytes, stream);
+    return rc;
+}
+
+int wd_compute_metrics(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, const double *coords,
+                       const double *period, void *out, int out_precision, void *stream)
+{
+    if (!ctx || !desc || !coords || !out) return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    wd_grid_desc d = *desc;
+    d.metric_mode = WD_METRIC_UNIFORM;
+    for (int l = 0; l < 3; ++l) d.h[l] = 1.0;
+    d.metrics = nullptr;
+    int rc = check_desc(&d);
+    if (rc) return rc;
+    if (scheme < WD_E2 || scheme > WD_C6) return fail(WD_ERR_INVALID_ARG, "bad scheme");
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    StreamJoin join(ctx, stream);
+    hipStream_t s = ctx->stream;
+    const int dim = d.ndim;
+    const long long N = npoints(d);
+    // scratch: J (dim*dim*N doubles), one grid view, items, state
+    void *scratch = nullptr;
+    long long maxt = 0;
+    for (int l = 0; l < dim; ++l) maxt = std::max(maxt, N / d.n[l]);
+    const size_t bytes = al256((size_t)dim * dim * N * 8) + al256(sizeof(GridDev)) +
+                         al256((size_t)maxt * sizeof(Item)) + al256(sizeof(GridState));
+    if (hipMalloc(&scratch, bytes) != hipSuccess) return fail(WD_ERR_NO_MEMORY, "metric scratch allocation failed");
+    unsigned char *b = static_cast<unsigned char *>(scratch);
+    double *J = reinterpret_cast<double *>(b);
+    GridDev *dg = reinterpret_cast<GridDev *>(b + al256((size_t)dim * dim * N * 8));
+    Item *ditems = reinterpret_cast<Item *>(reinterpret_cast<unsigned char *>(dg) + al256(sizeof(GridDev)));
+    GridState *dst = reinterpret_cast<GridState *>(reinterpret_cast<unsigned char *>(ditems) +
+                                                   al256((size_t)maxt * sizeof(Item)));
+    GridState zero{};
+    rc = WD_OK;
+    if (hipMemcpyAsync(dst, &zero, sizeof zero, hipMemcpyHostToDevice, s) != hipSuccess)
+        rc = fail(WD_ERR_HIP, "state upload failed");
+    GridDev g;
+    std::memset(&g, 0, sizeof g);
+    g.ndim = dim;
+    g.mode = MODE_GENERAL;
+    g.N = N;
+    long long st = 1;
+    for (int l = 0; l < 3; ++l) {
+        g.n[l] = l < dim ? d.n[l] : 1;
+        g.stride[l] = st;
+        st *= g.n[l];
+    }
+    for (int l = 0; l < dim; ++l) g.periodic[l] = d.bc[l][0] == WD_BC_PERIODIC;
+    g.uniform = 1;
+    g.scheme = scheme;
+    switch (scheme) {
+    case WD_E2: g.da = 1.0; g.dradius = 1; break;
+    case WD_E4: g.da = 4.0 / 3.0; g.db = -1.0 / 3.0; g.dradius = 2; break;
+    case WD_E6: g.da = 1.5; g.db = -0.6; g.dc = 0.1; g.dradius = 3; break;
+    case WD_C4: g.da = 1.5; g.dradius = 1; g.compact = 1; break;
+    default: g.da = 14.0 / 9.0; g.db = 1.0 / 9.0; g.dradius = 2; g.compact = 1; break;
+    }
+    g.state = dst;
+    for (int l = 0; l < dim && !rc; ++l) {
+        const LineOpDev *op = ctx_lineop(ctx, OP_DERIV, d.n[l], g.periodic[l], scheme, 0.0, 1);
+        if (!op) rc = WD_ERR_NO_MEMORY;
+        else g.dop[l] = *op;
+        g.tw[l] = pick_tile(ctx, d, l, 1);
+        g.ntiles[l] = l == 0 ? (int)((N / d.n[0] + g.tw[0] - 1) / g.tw[0])
+                             : (int)((N / ((long long)d.n[0] * d.n[l])) * ((d.n[0] + g.tw[l] - 1) / g.tw[l]));
+    }
+    for (int m = 0; m < dim && !rc; ++m) {
+        for (int l = 0; l < dim && !rc; ++l) {
+            GridDev v = g;
+            v.phi = const_cast<double *>(coords + (size_t)m * N);
+            v.F[l] = J + (size_t)(m * dim + l) * N;
+            v.jump[l] = period ? period[l * 3 + m] : 0.0;
+            std::vector<Item> it(g.ntiles[l]);
+            for (int t = 0; t < g.ntiles[l]; ++t) it[t] = Item{0, t};
+            if (hipMemcpyAsync(dg, &v, sizeof v, hipMemcpyHostToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(ditems, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice, s) != hipSuccess) {
+                rc = fail(WD_ERR_HIP, "metric view upload failed");
+                break;
+            }
+            launch_pass(PASS_D1, 1, dg, ditems, g.ntiles[l], l, 0, nwg_for(ctx, 1, g.ntiles[l]), s);
+            if (hipStreamSynchronize(s) != hipSuccess) rc = fail(WD_ERR_HIP, "metric pass failed");
+        }
+    }
+    if (!rc) {
+        launch_invert(J, out, out_precision == WD_FP64, dim, N, s);
+        if (hipStreamSynchronize(s) != hipSuccess) rc = fail(WD_ERR_HIP, "metric inversion failed");
+    }
+    (void)hipFree(scratch);
+    return rc;
+}
+
+int wd_line_solve_host(int kind, int n, int periodic, int scheme, double alpha_f, int fp64,
+                       const double *rhs, double *x, int *nlev)
+{
+    if (!rhs || !x || n < 8 || n > kMaxLine || (kind != OP_DERIV && kind != OP_FILTER) ||
+        scheme < WD_E2 || scheme > WD_C6)
+        return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    std::vector<double> d(rhs, rhs + n);
+    const bool solve = kind == OP_FILTER || scheme == WD_C4 || scheme == WD_C6;
+    int lev = 0;
+    if (solve) {
+        std::vector<int> smod;
+        std::vector<double> left, right, scale;
+        lev = build_line_system(kind, n, periodic, scheme, alpha_f, fp64, smod, left, right, scale);
+        if (lev < 0) return fail(WD_ERR_UNSUPPORTED, "line system did not reduce");
+        auto rnd = [fp64](double v) { return fp64 ? v : (double)(float)v; };
+        for (int k = 0; k < lev; ++k) {
+            const int s = smod[k];
+            std::vector<double> nx(n);
+            for (int i = 0; i < n; ++i) {
+                int im = i - s, ip = i + s;
+                if (periodic) {
+                    im += im < 0 ? n : 0;
+                    ip -= ip >= n ? n : 0;
+                } else {
+                    im = std::max(im, 0);
+                    ip = std::min(ip, n - 1);
+                }
+                nx[i] = d[i] + rnd(left[(size_t)k * n + i]) * d[im] + rnd(right[(size_t)k * n + i]) * d[ip];
+            }
+            d.swap(nx);
+        }
+        for (int i = 0; i < n; ++i) d[i] *= rnd(scale[i]);
+    }
+    for (int i = 0; i < n; ++i) x[i] = d[i];
+    if (nlev) *nlev = lev;
+    return WD_OK;
+}
+
+int wd_poisson_distance(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, int precision,
+                        const void *phip, void *dist, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx || !desc || !phip || !dist) return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    wd_method m;
+    wd_method_default(&m);
+    m.equation = WD_EQ_POISSON;
+    m.scheme = scheme;
+    m.precision = precision;
+    m.filter = 0;
+    int rc = check_desc(desc);
+    if (!rc) rc = check_method(&m);
+    if (rc) return rc;
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    StreamJoin join(ctx, stream);
+    hipStream_t s = ctx->stream;
+    void *phis[1] = {dist};
+    Plan P;
+    rc = plan_batch(ctx, 1, desc, &m, phis, ws, ws_bytes, P);
+    if (rc) return rc;
+    rc = upload_plan(ctx, P, s);
+    if (rc) return rc;
+    const size_t S = precision == WD_FP64 ? 8 : 4;
+    if (dist != phip &&
+        hipMemcpyAsync(dist, phip, (size_t)P.grids[0].N * S, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(WD_ERR_HIP, "copy failed");
+    return poisson_convert(ctx, P, 0, 0, nullptr, s);
+}
+
+}  // extern "C"

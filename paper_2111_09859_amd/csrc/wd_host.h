@@ -1,0 +1,118 @@
+// wd_host.h -- host-side internals of the wall-distance library.
+#pragma once
+
+#include "../../include/wd.h"
+#include "wd_common.h"
+#include "wd_kernels.h"
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+namespace wd {
+
+enum { OP_DERIV = 0, OP_FILTER = 1 };
+enum { SCHEME_E2 = 0, SCHEME_E4 = 1, SCHEME_E6 = 2, SCHEME_C4 = 3, SCHEME_C6 = 4 };
+
+struct OpKey {
+    int kind, n, periodic, scheme, fp64;
+    double alpha;
+    bool operator<(const OpKey &o) const
+    {
+        return std::tie(kind, n, periodic, scheme, fp64, alpha) <
+               std::tie(o.kind, o.n, o.periodic, o.scheme, o.fp64, o.alpha);
+    }
+};
+
+struct OpEntry {
+    LineOpDev dev;
+    void *mem = nullptr;
+};
+
+struct TuneKey {
+    int ndim, n0, n1, n2, dir, fp64;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(ndim, n0, n1, n2, dir, fp64) <
+               std::tie(o.ndim, o.n0, o.n1, o.n2, o.dir, o.fp64);
+    }
+};
+
+struct CachedGraph {
+    int K = 0;
+    hipGraphExec_t exec = nullptr;
+    GridDev *d_grids = nullptr;
+    Item *d_items = nullptr;
+    std::vector<unsigned char> grids_bytes, items_bytes;
+    unsigned long long stamp = 0;
+};
+
+struct ItemList {
+    int kind, l, arg, first, count;
+};
+
+struct Plan {
+    int n = 0, fp64 = 0, rk = 1, stages = 4, maxdim = 0;
+    std::vector<GridDev> grids;
+    std::vector<Item> items;
+    std::vector<ItemList> lists;
+    int cart[3], d1[3], d2[3], filt[3], face[6], lad[3];
+    int fin = 0, resid = 0, init = 0;
+    GridDev *d_grids = nullptr;
+    GridDev *d_aux = nullptr, *d_aux2 = nullptr;
+    GridState *d_states = nullptr;
+    Item *d_items = nullptr;
+    std::vector<void *> pois_phip;   // per Poisson grid: FP64 phi'
+    std::vector<void *> pois_F;      // per Poisson grid: 3 FP64 derivative buffers
+};
+
+int fail(int code, const char *fmt, ...);
+extern thread_local std::string g_last_error;
+
+int check_desc(const wd_grid_desc *d);
+int check_method(const wd_method *m);
+int grid_mode(const wd_grid_desc &d, const wd_method &m);
+size_t batch_bytes(int n, const wd_grid_desc *d, const wd_method *m);
+int pick_tile(wd_ctx *ctx, const wd_grid_desc &d, int l, int fp64);
+int pcr_reduce(int n, int periodic, std::vector<double> a, std::vector<double> b,
+               std::vector<double> c, double tol, std::vector<int> &smod,
+               std::vector<double> &left, std::vector<double> &right,
+               std::vector<double> &scale);
+int build_line_system(int kind, int n, int periodic, int scheme, double af, int fp64,
+                      std::vector<int> &smod, std::vector<double> &left,
+                      std::vector<double> &right, std::vector<double> &scale);
+const LineOpDev *ctx_lineop(wd_ctx *ctx, int kind, int n, int periodic, int scheme,
+                            double af, int fp64);
+int plan_batch(wd_ctx *ctx, int n, const wd_grid_desc *descs, const wd_method *meths,
+               void *const *phis, void *ws, size_t ws_bytes, Plan &P);
+void build_items(Plan &P);
+int upload_plan(wd_ctx *ctx, const Plan &P, hipStream_t s);
+void issue_init(wd_ctx *ctx, const Plan &P, hipStream_t s);
+void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s);
+hipGraphExec_t graph_for(wd_ctx *ctx, const Plan &P, int K);
+void ctx_drop_graphs(wd_ctx *ctx);
+int run_plan(wd_ctx *ctx, const Plan &P, int K, std::vector<GridState> &states);
+int poisson_convert(wd_ctx *ctx, const Plan &P, int i, int pidx, void *aux, hipStream_t s);
+int solve_plan(wd_ctx *ctx, Plan &P, void *const *aux, double *const *hists, int hist_cap,
+               int *iters, int *status);
+
+}  // namespace wd
+
+struct wd_ctx {
+    int device = 0;
+    int cus = 256;
+    char arch[64] = {0};
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    wd::GridState *pinned_states = nullptr;
+    int pinned_cap = 0;
+    int use_graphs = 1;
+    int graph_iters = 32;
+    std::map<wd::OpKey, wd::OpEntry> ops;
+    std::map<wd::TuneKey, int> tune;
+    std::vector<wd::CachedGraph> graphs;
+    unsigned long long clock = 0;
+    std::recursive_mutex mu;
+};

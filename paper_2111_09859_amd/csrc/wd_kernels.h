@@ -1,0 +1,32 @@
+// wd_kernels.h -- launchers of the gfx950 kernels (host side).
+#pragma once
+
+#include "wd_common.h"
+
+namespace wd {
+
+enum PassKind {
+    PASS_CART = 0,    // Cartesian directional pass (derivatives + partials)
+    PASS_D1 = 1,      // general pass 1: F_l = D_l phi
+    PASS_D2 = 2,      // general pass 2: D_l U_m (and D_l n_m)
+    PASS_FILTER = 3,  // filter along l
+    PASS_FINAL = 4,   // pointwise stage finish (general, no Laplacian)
+    PASS_RESID = 5,   // pointwise pseudo-step change
+    PASS_FACE = 6,    // extrapolated face; l = face, stage = target buffer
+    PASS_INIT = 7,    // initial field; stage = unused
+    PASS_LAD = 8,     // LAD diffusivity along l; stage = 0 sensor, 1 smoothing
+};
+
+// One launch of a pass over `nitems` work items with at most `nwg`
+// workgroups (a persistent loop covers the rest).
+void launch_pass(int kind, int fp64, const GridDev *grids, const Item *items,
+                 int nitems, int l, int stage, int nwg, hipStream_t s);
+void launch_finalize(const GridDev *grids, int ngrids, hipStream_t s);
+void launch_convert(int src_fp64, int dst_fp64, const void *src, void *dst,
+                    long long n, hipStream_t s);
+void launch_invert(const double *J, void *out, int out_fp64, int d,
+                   long long N, hipStream_t s);
+void launch_poisson_dist(const GridDev *g, int fp64, long long N,
+                         const double *phip, void *out, hipStream_t s);
+
+}  // namespace wd

@@ -1,0 +1,95 @@
+"""CPU tests of the library's host side: exported symbols, descriptor
+validation paths that need no device, and the line-system reduction tables
+the kernels use (checked against dense solves built here from the scheme
+definitions)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2111_09859_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def test_exports_every_declared_symbol(L):
+    text = open(os.path.join(ROOT, "include", "wd.h")).read()
+    names = set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(wd_\w+)\s*\(", text, re.M))
+    assert len(names) >= 20
+    lib = C.CDLL(L.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_defaults(L):
+    assert "gfx950" in L.wd_version()
+    m = L.wd_method_default()
+    assert m.equation == L.WD_EQ_HJ and m.scheme == L.WD_C6 and m.alpha_f == 0.495
+
+
+def dense_deriv(n, periodic, scheme):
+    al = {"C4": 0.25, "C6": 1 / 3}[scheme]
+    A = np.eye(n)
+    for i in range(n):
+        for o in (-1, 1):
+            j = i + o
+            if periodic:
+                A[i, j % n] += al
+            elif 0 <= j < n:
+                A[i, j] = al
+    if not periodic:
+        A[0, :] = 0
+        A[0, 0], A[0, 1] = 1, 3
+        A[-1, :] = 0
+        A[-1, -1], A[-1, -2] = 1, 3
+        if scheme == "C6":
+            A[1, :3] = [0.25, 1, 0.25]
+            A[-2, -3:] = [0.25, 1, 0.25]
+    return A
+
+
+def dense_filter(n, periodic, a):
+    A = np.eye(n)
+    for i in range(n):
+        for o in (-1, 1):
+            j = i + o
+            if periodic:
+                A[i, j % n] += a
+            elif 0 < i < n - 1:
+                A[i, j] = a
+    return A
+
+
+@pytest.mark.parametrize("n", [8, 33, 129, 256, 512, 1025, 2049])
+@pytest.mark.parametrize("periodic", [0, 1])
+def test_line_reduction_matches_dense(L, n, periodic):
+    rng = np.random.default_rng(n + periodic)
+    r = rng.standard_normal(n)
+    for scheme in ("C4", "C6"):
+        A = dense_deriv(n, periodic, scheme)
+        want = np.linalg.solve(A, r)
+        x, lev = L.wd_line_solve_host(0, r, periodic, scheme, 0.495, True)
+        assert np.abs(x - want).max() < 1e-13 * max(1, np.abs(want).max()), (scheme, lev)
+        x32, _ = L.wd_line_solve_host(0, r, periodic, scheme, 0.495, False)
+        assert np.abs(x32 - want).max() < 2e-6 * max(1, np.abs(want).max())
+    for a in (0.48, 0.495):
+        A = dense_filter(n, periodic, a)
+        rr = r.copy()
+        if not periodic:
+            rr[0] = rr[-1] = 0.0
+        want = np.linalg.solve(A, rr)
+        x, lev = L.wd_line_solve_host(1, rr, periodic, "C6", a, True)
+        assert np.abs(x - want).max() < 1e-12 * max(1, np.abs(want).max()), (a, lev)
+        assert lev <= 14
+
+
+def test_line_reduction_rejects_bad_sizes(L):
+    with pytest.raises(L.WDError):
+        L.wd_line_solve_host(0, np.zeros(4), 0, "C6", 0.495, True)
