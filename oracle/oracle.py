@@ -53,7 +53,7 @@ class _Method(C.Structure):
                 ("scheme", C.c_int), ("filter", C.c_int),
                 ("alpha_f", C.c_double), ("rk", C.c_int),
                 ("sigma", C.c_double), ("tol", C.c_double),
-                ("max_iter", C.c_int), ("fixed_iters", C.c_int)]
+                ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("lad_raw", C.c_int)]
 
 
 _lib = None
@@ -70,7 +70,8 @@ def lib():
         L.wdo_filter_line.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp]
         L.wdo_metrics.argtypes = [C.POINTER(_Grid), C.c_int, dp]
         L.wdo_eval.argtypes = [C.POINTER(_Grid), C.POINTER(_Method), dp, dp,
-                               dp, dp, dp, dp, dp, dp]
+                               dp, dp, dp, dp, dp, dp, dp]
+        L.wdo_lad_field.argtypes = [C.POINTER(_Grid), C.POINTER(_Method), dp, dp, dp]
         L.wdo_apply_bc.argtypes = [C.POINTER(_Grid), dp]
         L.wdo_apply_bc.restype = None
         L.wdo_solve.argtypes = [C.POINTER(_Grid), C.POINTER(_Method), dp,
@@ -122,13 +123,14 @@ class OracleGrid:
 
 def make_method(equation=HJ, gamma=GAMMA_LINEAR, curvature=0, eps=0.1, C_lad=0.1,
                 nu0=1e-3, eps0=1e-6, scheme=E4, filter=1, alpha_f=0.495,
-                rk=RK4, sigma=1.0, tol=1e-10, max_iter=100000, fixed_iters=0):
+                rk=RK4, sigma=1.0, tol=1e-10, max_iter=100000, fixed_iters=0, lad_raw=0):
     m = _Method()
     m.equation, m.gamma, m.curvature = equation, gamma, curvature
     m.eps, m.C, m.nu0, m.eps0 = eps, C_lad, nu0, eps0
     m.scheme = SCHEMES[scheme] if isinstance(scheme, str) else scheme
     m.filter, m.alpha_f, m.rk = filter, alpha_f, rk
     m.sigma, m.tol, m.max_iter, m.fixed_iters = sigma, tol, max_iter, fixed_iters
+    m.lad_raw = lad_raw
     return m
 
 
@@ -169,11 +171,21 @@ def evaluate(spec, method, phi, met=None):
         met = metrics(spec, method.scheme)
     phi = np.ascontiguousarray(phi, dtype=np.float64)
     outs = {k: np.empty(og.shape) for k in ("R", "g", "gamma", "lap", "kappa", "dt")}
-    rc = lib().wdo_eval(C.byref(og.g), C.byref(method), _ptr(met), _ptr(phi),
+    rc = lib().wdo_eval(C.byref(og.g), C.byref(method), _ptr(met), _ptr(phi), None,
                         *(_ptr(outs[k]) for k in ("R", "g", "gamma", "lap", "kappa", "dt")))
     if rc:
         raise ValueError("wdo_eval failed")
     return outs
+
+
+def lad_field(spec, method, phi, met=None):
+    og = OracleGrid(spec)
+    if met is None:
+        met = metrics(spec, method.scheme)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    out = np.empty(og.shape)
+    lib().wdo_lad_field(C.byref(og.g), C.byref(method), _ptr(met), _ptr(phi), _ptr(out))
+    return out
 
 
 def apply_bc(spec, phi):

@@ -521,6 +521,66 @@ static void fourth_diff_dir(const wdo_grid *g, int l, const double *f,
     }
 }
 
+/* Truncated Gaussian smoothing along direction l (nine points, Kawai & Lele
+ * style), in place; non-periodic lines use the nearest in-range value
+ * beyond the ends. */
+static void gauss_dir(const wdo_grid *g, int l, double *f, double *tmp)
+{
+    static const double b[5] = {3565.0 / 10368.0, 3091.0 / 12960.0,
+                                1997.0 / 25920.0, 149.0 / 12960.0,
+                                107.0 / 103680.0};
+    int n = g->n[l];
+    long s = stride_of(g, l);
+    long nl = npoints(g) / n;
+    int periodic = g->bc[l][0] == WDO_PERIODIC;
+    for (long k = 0; k < nl; ++k) {
+        long base = line_base(g, l, k);
+        for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int o = -4; o <= 4; ++o) {
+                int p = i + o;
+                if (periodic) p = ((p % n) + n) % n;
+                else p = p < 0 ? 0 : (p > n - 1 ? n - 1 : p);
+                acc += b[o < 0 ? -o : o] * f[base + p * s];
+            }
+            tmp[base + i * s] = acc;
+        }
+        for (int i = 0; i < n; ++i) f[base + i * s] = tmp[base + i * s];
+    }
+}
+
+/* LAD diffusivity (second argument of Eq. Gamma_form2):
+ *   C | sum_l (sum_m xi_{l,m}^2)^2 d4_l phi dx_l^3 |,  dx_l = 1/|grad xi_l|
+ * (reading: dx_l from the metrics, d4 the five-point index difference).
+ * Reading of the LAD scheme the paper follows (Kawai & Lele): the
+ * diffusivity is smoothed with their truncated Gaussian filter along each
+ * direction in turn. */
+int wdo_lad_field(const wdo_grid *g, const wdo_method *m, const double *met,
+                  const double *phi, double *out)
+{
+    int d = g->ndim;
+    long N = npoints(g);
+    double *tmp = malloc(sizeof(double) * N);
+    for (long q = 0; q < N; ++q) out[q] = 0.0;
+    for (int l = 0; l < d; ++l) {
+        fourth_diff_dir(g, l, phi, tmp);
+        for (long q = 0; q < N; ++q) {
+            double s2 = 0.0;
+            for (int mm = 0; mm < d; ++mm) {
+                double e = met[(l * d + mm) * N + q];
+                s2 += e * e;
+            }
+            double dx = 1.0 / sqrt(s2);
+            out[q] += s2 * s2 * tmp[q] * dx * dx * dx;
+        }
+    }
+    for (long q = 0; q < N; ++q) out[q] = m->C * fabs(out[q]);
+    if (!m->lad_raw)
+        for (int l = 0; l < d; ++l) gauss_dir(g, l, out, tmp);
+    free(tmp);
+    return 0;
+}
+
 /* Right-hand side of the pseudo-time equation at phi (Sec. 3.3):
  *   Eikonal (USeq1):  R = 1 - U.grad(phi) = 1 - |grad phi|^2
  *   HJ      (USeq3):  R = 1 + Gamma lap(phi) - |grad phi|^2
@@ -535,8 +595,8 @@ static void fourth_diff_dir(const wdo_grid *g, int l, const double *f,
  *   largest modified wavenumber; Eikonal drops the second term, Poisson
  *   uses dt = sigma / (k'^2 S2). */
 int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
-             const double *phi, double *R, double *gmag, double *gam,
-             double *lap, double *kap, double *dt)
+             const double *phi, const double *lad_in, double *R, double *gmag,
+             double *gam, double *lap, double *kap, double *dt)
 {
     int d = g->ndim;
     long N = npoints(g);
@@ -583,32 +643,20 @@ int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
         }
         free(nv);
     }
-    /* Gamma: standard eps*phi (Gamma_form1) or LAD (Gamma_form2) with
-     * Delta x_l = 1/|grad xi_l| (reading); clipped at zero. */
+    /* Gamma: standard eps*phi (Gamma_form1) or min(eps*phi, LAD field)
+     * (Gamma_form2); clipped at zero. */
     double *Gam = calloc(N, sizeof(double));
     if (m->equation == WDO_HJ) {
         double *S = NULL;
-        if (m->gamma == WDO_GAMMA_LAD) {
-            S = calloc(N, sizeof(double));
-            for (int l = 0; l < d; ++l) {
-                fourth_diff_dir(g, l, phi, tmp);
-                for (long q = 0; q < N; ++q) {
-                    double s2 = 0.0;
-                    for (int mm = 0; mm < d; ++mm) {
-                        double e = met[(l * d + mm) * N + q];
-                        s2 += e * e;
-                    }
-                    double dx = 1.0 / sqrt(s2);
-                    S[q] += s2 * s2 * tmp[q] * dx * dx * dx;
-                }
-            }
+        const double *lad = lad_in;
+        if (m->gamma == WDO_GAMMA_LAD && !lad) {
+            S = malloc(sizeof(double) * N);
+            wdo_lad_field(g, m, met, phi, S);
+            lad = S;
         }
         for (long q = 0; q < N; ++q) {
             double gq = m->eps * phi[q];
-            if (S) {
-                double lad = m->C * fabs(S[q]);
-                if (lad < gq) gq = lad;
-            }
+            if (m->gamma == WDO_GAMMA_LAD && lad[q] < gq) gq = lad[q];
             Gam[q] = gq > 0.0 ? gq : 0.0;
         }
         free(S);
@@ -682,6 +730,9 @@ int wdo_solve(const wdo_grid *g, const wdo_method *m, double *phi, int warm,
     double *k3 = malloc(sizeof(double) * N);
     double *k4 = malloc(sizeof(double) * N);
     double *dt = malloc(sizeof(double) * N);
+    double *lad = NULL;
+    if (m->equation == WDO_HJ && m->gamma == WDO_GAMMA_LAD && !m->lad_raw)
+        lad = malloc(sizeof(double) * N);
     if (!warm)
         for (long q = 0; q < N; ++q) phi[q] = 0.0;
     wdo_apply_bc(g, phi);
@@ -689,30 +740,32 @@ int wdo_solve(const wdo_grid *g, const wdo_method *m, double *phi, int warm,
     int limit = m->fixed_iters > 0 ? m->fixed_iters : m->max_iter;
     for (it = 0; it < limit; ++it) {
         memcpy(pn, phi, sizeof(double) * N);
+        if (lad)
+            wdo_lad_field(g, m, met, pn, lad);
         if (m->rk == WDO_RK4) {
-            wdo_eval(g, m, met, pn, k1, NULL, NULL, NULL, NULL, dt);
+            wdo_eval(g, m, met, pn, lad, k1, NULL, NULL, NULL, NULL, dt);
             for (long q = 0; q < N; ++q) p[q] = pn[q] + dt[q] / 2.0 * k1[q];
             wdo_apply_bc(g, p);
-            wdo_eval(g, m, met, p, k2, NULL, NULL, NULL, NULL, NULL);
+            wdo_eval(g, m, met, p, lad, k2, NULL, NULL, NULL, NULL, NULL);
             for (long q = 0; q < N; ++q) p[q] = pn[q] + dt[q] / 2.0 * k2[q];
             wdo_apply_bc(g, p);
-            wdo_eval(g, m, met, p, k3, NULL, NULL, NULL, NULL, NULL);
+            wdo_eval(g, m, met, p, lad, k3, NULL, NULL, NULL, NULL, NULL);
             for (long q = 0; q < N; ++q) p[q] = pn[q] + dt[q] * k3[q];
             wdo_apply_bc(g, p);
-            wdo_eval(g, m, met, p, k4, NULL, NULL, NULL, NULL, NULL);
+            wdo_eval(g, m, met, p, lad, k4, NULL, NULL, NULL, NULL, NULL);
             for (long q = 0; q < N; ++q)
                 phi[q] = pn[q] + dt[q] / 6.0 * (k1[q] + 2.0 * k2[q]
                                                 + 2.0 * k3[q] + k4[q]);
             wdo_apply_bc(g, phi);
         } else {
-            wdo_eval(g, m, met, pn, k1, NULL, NULL, NULL, NULL, dt);
+            wdo_eval(g, m, met, pn, lad, k1, NULL, NULL, NULL, NULL, dt);
             for (long q = 0; q < N; ++q) p[q] = pn[q] + dt[q] * k1[q];
             wdo_apply_bc(g, p);
-            wdo_eval(g, m, met, p, k2, NULL, NULL, NULL, NULL, NULL);
+            wdo_eval(g, m, met, p, lad, k2, NULL, NULL, NULL, NULL, NULL);
             for (long q = 0; q < N; ++q)
                 k3[q] = 0.75 * pn[q] + 0.25 * (p[q] + dt[q] * k2[q]);
             wdo_apply_bc(g, k3);
-            wdo_eval(g, m, met, k3, k2, NULL, NULL, NULL, NULL, NULL);
+            wdo_eval(g, m, met, k3, lad, k2, NULL, NULL, NULL, NULL, NULL);
             for (long q = 0; q < N; ++q)
                 phi[q] = pn[q] / 3.0 + 2.0 / 3.0 * (k3[q] + dt[q] * k2[q]);
             wdo_apply_bc(g, phi);
@@ -748,7 +801,7 @@ int wdo_solve(const wdo_grid *g, const wdo_method *m, double *phi, int warm,
         status = 0;
     if (iters) *iters = it;
     free(met); free(pn); free(p); free(k1); free(k2); free(k3); free(k4);
-    free(dt);
+    free(dt); free(lad);
     return status;
 }
 

@@ -55,6 +55,12 @@ typedef struct {
     double tol;                /* stop when max |phi - phi_o| <= tol      */
     int max_iter;
     int fixed_iters;           /* > 0: run exactly this many iterations   */
+    int lad_raw;               /* LAD reading: 0 (default) = sensor C|S|
+                                  from phi^n once per iteration, smoothed by
+                                  the truncated Gaussian filter along each
+                                  direction; 1 = unsmoothed, recomputed from
+                                  each stage value (kept to document its
+                                  instability)                           */
 } wdo_method;
 
 /* 1-D operators in index space (unit spacing).  jump: f(i+n) = f(i)+jump
@@ -70,8 +76,13 @@ int wdo_metrics(const wdo_grid *g, int scheme, double *met);
 /* One evaluation of the pseudo-time right-hand side at phi.  Any output
  * pointer may be NULL.  dt is the local pseudo time step at phi. */
 int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
-             const double *phi, double *R, double *gmag, double *gam,
-             double *lap, double *kap, double *dt);
+             const double *phi, const double *lad_in, double *R, double *gmag,
+             double *gam, double *lap, double *kap, double *dt);
+
+/* LAD diffusivity field of Eq. (Gamma_form2)'s second argument at phi
+ * (smoothed unless m->lad_raw). */
+int wdo_lad_field(const wdo_grid *g, const wdo_method *m, const double *met,
+                  const double *phi, double *out);
 
 /* Boundary conditions and solid mask, in place. */
 void wdo_apply_bc(const wdo_grid *g, double *phi);

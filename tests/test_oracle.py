@@ -318,3 +318,24 @@ def test_ogrid_distance_order(oracle):
         assert st == 0
         errs.append(np.abs(phi - spec.exact).max())
     assert errs[1] < errs[0]
+
+
+def _perturbation_growth(oracle, spec, n, **kw):
+    rng = np.random.default_rng(0)
+    p1, _, _, _ = oracle.solve(spec, oracle.make_method(fixed_iters=1, **kw))
+    p1b = p1 * (1 + 1e-15 * rng.standard_normal(p1.shape))
+    a, _, _, _ = oracle.solve(spec, oracle.make_method(fixed_iters=n - 1, **kw), phi0=p1)
+    b, _, _, _ = oracle.solve(spec, oracle.make_method(fixed_iters=n - 1, **kw), phi0=p1b)
+    return np.abs(a - b).max() / np.abs(a).max()
+
+
+def test_lad_reading_keeps_rounding_at_rounding_level(oracle):
+    """The LAD reading (diffusivity from phi^n once per iteration, smoothed
+    with the truncated Gaussian filter) leaves a 1e-15 perturbation at
+    rounding level over 20 iterations; the unsmoothed per-stage variant
+    amplifies it by many orders of magnitude (fourth-difference
+    anti-diffusion through the sensor), which is why it is not the reading."""
+    spec = G.channel(37, 29)
+    kw = dict(equation=oracle.HJ, gamma=oracle.GAMMA_LAD, scheme="E6", eps=0.2)
+    assert _perturbation_growth(oracle, spec, 20, lad_raw=0, **kw) < 1e-12
+    assert _perturbation_growth(oracle, spec, 20, lad_raw=1, **kw) > 1e-8
