@@ -1,0 +1,199 @@
+"""Benchmark of the wall-distance hot path on one MI355X.
+
+Workload (default): 2D cylinder O-grid 512 (theta) x 256 (r), wall R = 0.5,
+far field r = 20 (outflow), radial spacing min(1e-3 * 1.03^j, cap);
+6th-order compact derivatives, 10th-order implicit filter (alpha_f 0.495),
+LAD pseudo-HJ (eps 0.2, C 0.1) with curvature correction, RK4 with local
+time stepping.  One step = one complete solve from phi = 0 to the stopping
+rule (FP32: max change <= 1e-6 or no new minimum for 1000 iterations;
+FP64: max change <= 1e-10) with grid, metrics and fields resident in HBM.
+
+value = grid-point updates per second (points x pseudo iterations / time);
+one update is one point through one full pseudo iteration (LAD field, all
+RK stages, the filter in every direction, boundary conditions, residual).
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    from paper_2111_09859_amd import grids as G
+    if name == "cylinder":
+        spec = G.cylinder(512, 256)
+        kw = dict(equation="HJ", gamma="LAD", curvature=True, eps=0.2, scheme="C6", rk="RK4")
+        desc = ("cylinder O-grid 512x256, R=0.5, r_out=20, stretch 1.03 from 1e-3 (capped), "
+                "C6 + F10(0.495), LAD pseudo-HJ + curvature, RK4")
+    elif name == "duct":
+        spec = G.duct(256)
+        kw = dict(equation="HJ", gamma="LAD", eps=0.2, scheme="C6", rk="RK4")
+        desc = "3D square duct 256^3, C6 + F10(0.495), LAD pseudo-HJ, RK4"
+    elif name == "channel":
+        spec = G.channel(129, 65)
+        kw = dict(equation="HJ", gamma="LINEAR", eps=0.1, scheme="E4", rk="RK3")
+        desc = "2D channel 129x65, E4 + F10(0.495), standard HJ eps 0.1, RK3"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return spec, kw, desc
+
+
+def stop_rule(prec, fixed):
+    if fixed:
+        return dict(tol=0.0, max_iter=fixed, stall_window=0)
+    if prec == "fp32":
+        return dict(tol=1e-6, max_iter=20000, stall_window=1000)
+    return dict(tol=1e-10, max_iter=20000, stall_window=0)
+
+
+def run_gpu(args, spec, kw, prec, profile=False):
+    import torch
+    from paper_2111_09859_amd import _lib as L, api
+    s = api.Solver(0)
+    prep = s.prepare(spec, kw["scheme"], prec)
+    m = api.make_method(precision=prec, **kw, **stop_rule(prec, args.fixed_iters))
+    phi = torch.zeros(spec.shape, dtype=prep.dtype, device=s.device)
+    for _ in range(args.warmup):
+        s.solve(prep, m, phi=phi, check=False)
+    torch.cuda.synchronize()
+    iters = 0
+    statuses = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = s.solve(prep, m, phi=phi, check=False)
+        iters += out["iters"]
+        statuses.append(out["status"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = []
+    if profile:
+        # kernel timing pass: the same steps again, each launch bracketed by
+        # HIP events on the library's stream (direct launches, no graph)
+        L.wd_ctx_profile(s.ctx, True)
+        for _ in range(args.steps):
+            s.solve(prep, m, phi=phi, check=False)
+        torch.cuda.synchronize()
+        stats = L.wd_ctx_profile_read(s.ctx)
+        L.wd_ctx_profile(s.ctx, False)
+    res = phi.double().cpu().numpy()
+    err = float(np.abs(res - spec.exact).max()) if spec.exact is not None else None
+    return dict(time=dt, iters=iters, statuses=statuses, err=err, stats=stats)
+
+
+def roofline(stats, workload_key):
+    """Dominant kernel (largest total time): compulsory bytes per launch over
+    its mean event-timed duration, against the 8 TB/s HBM peak."""
+    if not stats:
+        return None
+    k = max(stats, key=lambda r: r["total_ms"])
+    if k["alg_bytes"] <= 0:
+        return None
+    per_launch = k["alg_bytes"] / k["launches"]
+    avg_s = k["total_ms"] * 1e-3 / k["launches"]
+    achieved = per_launch / avg_s / 1e9
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        import hashlib
+        src = os.path.join(ROOT, "paper_2111_09859_amd", "csrc", "wd_kernels.hip")
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        rec = json.load(open(tpath)).get(workload_key, {})
+        if rec.get("kernel") == k["name"] and rec.get("source_sha256") == sha:
+            traffic = rec.get("hbm_bytes_per_launch")
+    return {"bound": "hbm", "kernel": k["name"], "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "alg_bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6,
+            "launches": k["launches"],
+            "kernels": {r["name"]: {"launches": r["launches"], "ms": round(r["total_ms"], 3),
+                                    "GBps": (r["alg_bytes"] / (r["total_ms"] * 1e-3) / 1e9
+                                             if r["total_ms"] > 0 else None)}
+                        for r in stats}}
+
+
+def run_cpu_baseline(spec, kw, sample_iters):
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle as O
+    O.build(force=False)
+    m = O.make_method(equation={"HJ": O.HJ, "EIKONAL": O.EIKONAL, "POISSON": O.POISSON}[kw["equation"]],
+                      gamma={"LAD": O.GAMMA_LAD, "LINEAR": O.GAMMA_LINEAR}[kw["gamma"]],
+                      curvature=int(kw.get("curvature", False)), eps=kw["eps"], scheme=kw["scheme"],
+                      rk={"RK4": O.RK4, "RK3": O.RK3}[kw["rk"]], fixed_iters=sample_iters)
+    t0 = time.perf_counter()
+    O.solve(spec, m)
+    dt = time.perf_counter() - t0
+    return spec.npoints * sample_iters / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cylinder")
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--fixed-iters", type=int, default=0,
+                    help="time this many iterations per step instead of full solves")
+    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="no per-kernel event timing (roofline is then null)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(grids are independent; see the multi-GPU design notes)", file=sys.stderr)
+        raise SystemExit(2)
+
+    spec, kw, desc = workload(args.workload)
+    r = run_gpu(args, spec, kw, args.precision, profile=not args.no_profile)
+    ups = spec.npoints * r["iters"] / r["time"]
+    line = {
+        "metric": "grid-point updates/s",
+        "value": ups,
+        "unit": "point-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r["time"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "points": spec.npoints,
+                   "iters_per_step": r["iters"] / args.steps,
+                   "solves_per_s": args.steps / r["time"],
+                   "status": r["statuses"][-1], "linf_err_vs_exact": r["err"],
+                   "stop": stop_rule(args.precision, args.fixed_iters)},
+    }
+    if not args.no_fp64 and args.precision == "fp32":
+        r64 = run_gpu(args, spec, kw, "fp64")
+        line["config"]["fp64"] = {"value": spec.npoints * r64["iters"] / r64["time"],
+                                  "ms_per_step": 1e3 * r64["time"] / args.steps,
+                                  "iters_per_step": r64["iters"] / args.steps,
+                                  "linf_err_vs_exact": r64["err"],
+                                  "status": r64["statuses"][-1]}
+    line["roofline"] = roofline(r["stats"], f"{args.workload}-{args.precision}")
+    if not args.no_cpu:
+        v, dt = run_cpu_baseline(spec, kw, args.cpu_iters)
+        line["cpu_baseline"] = {"value": v, "unit": "point-updates/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"{args.cpu_iters} pseudo iterations of the same "
+                                          f"workload from phi = 0 ({dt:.1f} s, FP64, 1 thread)"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -180,6 +180,24 @@ int wd_poisson_distance(wd_ctx *ctx, const wd_grid_desc *desc, int scheme,
                         int precision, const void *phip, void *dist, void *ws,
                         size_t ws_bytes, void *stream);
 
+/* ---- live kernel timing --------------------------------------------- */
+typedef struct wd_kernel_stat {
+    char name[32];        /* kernel family, e.g. "k_d2", "k_filter"        */
+    long long launches;   /* launches timed                                */
+    double total_ms;      /* sum of event-timed durations                  */
+    double alg_bytes;     /* sum of compulsory bytes (each field a pass
+                             must touch, once per point)                   */
+} wd_kernel_stat;
+
+/* enable != 0: later solves on this context launch without graph capture
+ * and time every kernel with HIP events on the context stream (for
+ * measurement; slower).  Clears the statistics either way. */
+int wd_ctx_profile(wd_ctx *ctx, int enable);
+
+/* Copy up to cap statistics (host array) gathered since wd_ctx_profile;
+ * *n receives the number available. */
+int wd_ctx_profile_read(wd_ctx *ctx, wd_kernel_stat *out, int cap, int *n);
+
 /* ---- host-side diagnostics ------------------------------------------ */
 /* Applies, on the host and in FP64 arithmetic, the parallel-cyclic-reduction
  * multipliers the kernels use for a line system (Sec. 3.2 compact first

@@ -44,6 +44,11 @@ class wd_method(C.Structure):
                 ("precision", C.c_int), ("warm_start", C.c_int)]
 
 
+class wd_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_longlong), ("total_ms", C.c_double),
+                ("alg_bytes", C.c_double)]
+
+
 class WDError(RuntimeError):
     def __init__(self, code, where):
         self.code = code
@@ -77,6 +82,8 @@ def lib():
         "wd_solve_batched": ([vp, C.c_int, gd, me, C.POINTER(vp), C.POINTER(vp),
                               C.POINTER(dp), C.c_int, ip, ip, vp, C.c_size_t, vp], C.c_int),
         "wd_poisson_distance": ([vp, gd, C.c_int, C.c_int, vp, vp, vp, C.c_size_t, vp], C.c_int),
+        "wd_ctx_profile": ([vp, C.c_int], C.c_int),
+        "wd_ctx_profile_read": ([vp, C.POINTER(wd_kernel_stat), C.c_int, ip], C.c_int),
         "wd_line_solve_host": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, dp,
                                 dp, ip], C.c_int),
         "wd_server_create": ([vp, C.c_size_t, C.c_int, C.POINTER(vp)], C.c_int),
@@ -187,6 +194,19 @@ def wd_poisson_distance(ctx, desc, scheme, precision, phip_ptr, dist_ptr, ws_ptr
     return _check(lib().wd_poisson_distance(ctx, C.byref(desc), scheme, precision, phip_ptr,
                                             dist_ptr, ws_ptr, ws_bytes, stream),
                   "wd_poisson_distance")
+
+
+def wd_ctx_profile(ctx, enable: bool) -> None:
+    _check(lib().wd_ctx_profile(ctx, int(bool(enable))), "wd_ctx_profile", ok=(WD_OK,))
+
+
+def wd_ctx_profile_read(ctx):
+    arr = (wd_kernel_stat * 64)()
+    n = C.c_int(0)
+    _check(lib().wd_ctx_profile_read(ctx, arr, 64, C.byref(n)), "wd_ctx_profile_read", ok=(WD_OK,))
+    return [{"name": arr[i].name.decode(), "launches": arr[i].launches,
+             "total_ms": arr[i].total_ms, "alg_bytes": arr[i].alg_bytes}
+            for i in range(min(n.value, 64))]
 
 
 def wd_line_solve_host(kind, rhs, periodic, scheme="C6", alpha_f=0.495, fp64=True):

@@ -571,6 +571,140 @@ void build_items(Plan &P)
 }
 
 // ---------------------------------------------------------------------
+// live kernel timing
+static const char *kind_name(int kind)
+{
+    switch (kind) {
+    case PASS_CART: return "k_cart";
+    case PASS_D1: return "k_d1";
+    case PASS_D2: return "k_d2";
+    case PASS_FILTER: return "k_filter";
+    case PASS_FINAL: return "k_final";
+    case PASS_RESID: return "k_resid";
+    case PASS_FACE: return "k_face";
+    case PASS_INIT: return "k_init";
+    case PASS_LAD: return "k_lad";
+    default: return "k_finalize";
+    }
+}
+
+// Compulsory field accesses per point of one launch of `kind` on grid g:
+// every distinct field the pass must read or write once.
+static double point_accesses(const GridDev &g, int kind, int l, int stage)
+{
+    const int d = g.ndim;
+    const bool last = l == d - 1;
+    const int met = g.uniform ? 0 : d * d;
+    const int rk4 = g.rk;
+    // fields touched by the pointwise stage finish
+    auto finish = [&](int src_counted) {
+        double r = src_counted ? 0 : 1;            // stage value
+        if (stage > 0) r += 1;                     // phi^n
+        if (rk4 && stage > 0) r += 1;              // acc read
+        if (stage > 0) r += 1;                     // dt read
+        double w = 1;                              // new stage value
+        if (rk4 && stage < 3) w += 1;              // acc write
+        if (stage == 0) w += 1;                    // dt write
+        if (g.lad) r += 1;                         // LAD field
+        return r + w;
+    };
+    switch (kind) {
+    case PASS_CART: {
+        const int np = 1 + g.need_lap;             // partial sums
+        double a = 1;                              // source line
+        if (l > 0) a += np;
+        if (!last) a += np;
+        else a += finish(1) - (g.lad ? 0 : 0);
+        return a;
+    }
+    case PASS_D1:
+        return 2;                                  // phi in, F_l out
+    case PASS_D2: {
+        const int np = 1 + g.curv;
+        double a = d + met;                        // F and metrics
+        if (l > 0) a += np;
+        if (!last) a += np;
+        else a += finish(0);
+        return a;
+    }
+    case PASS_FINAL:
+        return d + met + finish(0);
+    case PASS_FILTER:
+        return last && g.fused_resid ? 3 : 2;      // (+ phi read/write when fused)
+    case PASS_RESID:
+        return 3;
+    case PASS_LAD:
+        return stage == 0 ? (l == 0 ? 2 : 3) + met / d : 2;
+    case PASS_INIT:
+        return 1;
+    default:
+        return 0;
+    }
+}
+
+static double launch_bytes(const Plan &P, const ItemList &L, int stage)
+{
+    if (L.kind == PASS_FACE) return 0.0;
+    const double S = P.fp64 ? 8.0 : 4.0;
+    double b = 0.0;
+    int last_grid = -1;
+    for (int i = 0; i < L.count; ++i) {
+        const int gi = P.items[L.first + i].grid;
+        if (gi == last_grid) continue;
+        last_grid = gi;
+        const GridDev &g = P.grids[gi];
+        b += (double)g.N * point_accesses(g, L.kind, L.l, stage) * S;
+    }
+    return b;
+}
+
+static hipEvent_t pool_event(wd_ctx *ctx)
+{
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+static void prof_begin(wd_ctx *ctx, PendingLaunch &pl, const char *name, double bytes, hipStream_t s)
+{
+    pl.a = pool_event(ctx);
+    pl.b = pool_event(ctx);
+    pl.name = name;
+    pl.bytes = bytes;
+    (void)hipEventRecord(pl.a, s);
+}
+
+static void prof_end(wd_ctx *ctx, PendingLaunch &pl, hipStream_t s)
+{
+    (void)hipEventRecord(pl.b, s);
+    ctx->pending.push_back(pl);
+}
+
+// after a stream sync: fold finished launches into the statistics
+void prof_collect(wd_ctx *ctx)
+{
+    for (auto &pl : ctx->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pl.a, pl.b) == hipSuccess) {
+            KStat &k = ctx->kstats[pl.name];
+            k.launches += 1;
+            k.ms += ms;
+            k.bytes += pl.bytes;
+        } else {
+            (void)hipGetLastError();   // do not leave a sticky error behind
+        }
+        ctx->ev_pool.push_back(pl.a);
+        ctx->ev_pool.push_back(pl.b);
+    }
+    ctx->pending.clear();
+}
+
+// ---------------------------------------------------------------------
 // issuing work
 static int nwg_for(wd_ctx *ctx, int fp64, int count)
 {
@@ -584,8 +718,11 @@ void issue_list(wd_ctx *ctx, const Plan &P, int li, int stage, hipStream_t s)
     const ItemList &L = P.lists[li];
     if (L.count == 0) return;
     const int arg = (L.kind == PASS_FACE || L.kind == PASS_INIT) ? L.arg : stage;
+    PendingLaunch pl;
+    if (ctx->profile) prof_begin(ctx, pl, kind_name(L.kind), launch_bytes(P, L, stage), s);
     launch_pass(L.kind, P.fp64, P.d_grids, P.d_items + L.first, L.count, L.l, arg,
                 nwg_for(ctx, P.fp64, L.count), s);
+    if (ctx->profile) prof_end(ctx, pl, s);
 }
 
 void issue_faces(wd_ctx *ctx, const Plan &P, int target, hipStream_t s)
@@ -593,8 +730,11 @@ void issue_faces(wd_ctx *ctx, const Plan &P, int target, hipStream_t s)
     for (int f = 0; f < 6; ++f) {
         const ItemList &L = P.lists[P.face[f]];
         if (L.count == 0) continue;
+        PendingLaunch pl;
+        if (ctx->profile) prof_begin(ctx, pl, "k_face", 0.0, s);
         launch_pass(PASS_FACE, P.fp64, P.d_grids, P.d_items + L.first, L.count, f, target,
                     nwg_for(ctx, P.fp64, L.count), s);
+        if (ctx->profile) prof_end(ctx, pl, s);
     }
 }
 
@@ -615,7 +755,10 @@ void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s)
     for (int l = 0; l < P.maxdim; ++l) issue_list(ctx, P, P.filt[l], 0, s);
     issue_faces(ctx, P, 1, s);
     issue_list(ctx, P, P.resid, 0, s);
+    PendingLaunch pl;
+    if (ctx->profile) prof_begin(ctx, pl, "k_finalize", 0.0, s);
     launch_finalize(P.d_grids, P.n, s);
+    if (ctx->profile) prof_end(ctx, pl, s);
 }
 
 void issue_init(wd_ctx *ctx, const Plan &P, hipStream_t s)
@@ -646,13 +789,21 @@ static bool same_plan(const Plan &a, const CachedGraph &c)
     return a.d_grids == c.d_grids && a.d_items == c.d_items;
 }
 
-hipGraphExec_t graph_for(wd_ctx *ctx, const Plan &P, int K)
+static void drop_graph(wd_ctx *ctx, CachedGraph &c)
+{
+    (void)hipGraphExecDestroy(c.exec);
+    for (auto e : c.ev) ctx->ev_pool.push_back(e);
+    c.ev.clear();
+}
+
+CachedGraph *graph_for(wd_ctx *ctx, const Plan &P, int K)
 {
     for (auto &c : ctx->graphs)
-        if (c.K == K && same_plan(P, c)) {
+        if (c.K == K && c.profile == ctx->profile && same_plan(P, c)) {
             c.stamp = ++ctx->clock;
-            return c.exec;
+            return &c;
         }
+    prof_collect(ctx);
     hipStream_t s = ctx->stream;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         fail(WD_ERR_HIP, "hipStreamBeginCapture failed");
@@ -664,6 +815,7 @@ hipGraphExec_t graph_for(wd_ctx *ctx, const Plan &P, int K)
         fail(WD_ERR_HIP, "hipStreamEndCapture failed");
         return nullptr;
     }
+    std::vector<PendingLaunch> captured;
     hipGraphExec_t exec = nullptr;
     if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGraphDestroy(graph);
@@ -674,12 +826,19 @@ hipGraphExec_t graph_for(wd_ctx *ctx, const Plan &P, int K)
     if (ctx->graphs.size() >= 16) {
         auto oldest = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
                                        [](const CachedGraph &a, const CachedGraph &b) { return a.stamp < b.stamp; });
-        (void)hipGraphExecDestroy(oldest->exec);
+        drop_graph(ctx, *oldest);
         ctx->graphs.erase(oldest);
     }
     CachedGraph c;
     c.K = K;
+    c.profile = ctx->profile;
     c.exec = exec;
+    for (auto &pl : captured) {
+        c.ev.push_back(pl.a);
+        c.ev.push_back(pl.b);
+        c.ev_name.push_back(pl.name);
+        c.ev_bytes.push_back(pl.bytes);
+    }
     c.d_grids = P.d_grids;
     c.d_items = P.d_items;
     c.grids_bytes.assign(reinterpret_cast<const unsigned char *>(P.grids.data()),
@@ -688,12 +847,12 @@ hipGraphExec_t graph_for(wd_ctx *ctx, const Plan &P, int K)
                          reinterpret_cast<const unsigned char *>(P.items.data()) + P.items.size() * sizeof(Item));
     c.stamp = ++ctx->clock;
     ctx->graphs.push_back(std::move(c));
-    return exec;
+    return &ctx->graphs.back();
 }
 
 void ctx_drop_graphs(wd_ctx *ctx)
 {
-    for (auto &c : ctx->graphs) (void)hipGraphExecDestroy(c.exec);
+    for (auto &c : ctx->graphs) drop_graph(ctx, c);
     ctx->graphs.clear();
 }
 
@@ -704,14 +863,16 @@ int run_plan(wd_ctx *ctx, const Plan &P, int K, std::vector<GridState> &states)
     hipStream_t s = ctx->stream;
     int maxit = 0;
     for (int i = 0; i < P.n; ++i) maxit = std::max(maxit, P.grids[i].max_iter);
-    const int use_graph = ctx->use_graphs;
-    hipGraphExec_t exec = use_graph ? graph_for(ctx, P, K) : nullptr;
-    if (use_graph && !exec) return WD_ERR_HIP;
+    // profiling mode launches directly, each kernel bracketed by events
+    const int use_graph = ctx->use_graphs && !ctx->profile;
+    CachedGraph *cg = use_graph ? graph_for(ctx, P, K) : nullptr;
+    if (use_graph && !cg) return WD_ERR_HIP;
     states.resize(P.n);
     const long long max_rounds = (maxit + K - 1) / K + 1;
+    int prev_iter = 0;
     for (long long r = 0; r < max_rounds; ++r) {
-        if (exec) {
-            if (hipGraphLaunch(exec, s) != hipSuccess) return fail(WD_ERR_HIP, "hipGraphLaunch failed");
+        if (cg) {
+            if (hipGraphLaunch(cg->exec, s) != hipSuccess) return fail(WD_ERR_HIP, "hipGraphLaunch failed");
         } else {
             for (int k = 0; k < K; ++k) issue_iteration(ctx, P, s);
         }
@@ -720,10 +881,25 @@ int run_plan(wd_ctx *ctx, const Plan &P, int K, std::vector<GridState> &states)
             hipStreamSynchronize(s) != hipSuccess)
             return fail(WD_ERR_HIP, "state read-back failed: %s", hipGetErrorString(hipGetLastError()));
         bool all = true;
+        int max_iter_now = 0;
         for (int i = 0; i < P.n; ++i) {
             states[i] = ctx->pinned_states[i];
             all &= states[i].done != 0;
+            max_iter_now = std::max(max_iter_now, states[i].iter);
         }
+        if (ctx->profile) {
+            // keep only launches of iterations in which some grid was active
+            const int active = std::min(K, max_iter_now - prev_iter);
+            const size_t per_iter = ctx->pending.size() / K;
+            const size_t keep = (size_t)active * per_iter;
+            for (size_t i = keep; i < ctx->pending.size(); ++i) {
+                ctx->ev_pool.push_back(ctx->pending[i].a);
+                ctx->ev_pool.push_back(ctx->pending[i].b);
+            }
+            if (ctx->pending.size() > keep) ctx->pending.resize(keep);
+            prof_collect(ctx);
+        }
+        prev_iter = max_iter_now;
         if (all) return WD_OK;
     }
     return fail(WD_ERR_HIP, "grids did not stop within max_iter");
@@ -901,6 +1077,8 @@ int wd_ctx_destroy(wd_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     ctx_drop_graphs(ctx);
+    prof_collect(ctx);
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (auto &kv : ctx->ops) (void)hipFree(kv.second.mem);
     if (ctx->pinned_states) (void)hipHostFree(ctx->pinned_states);
     (void)hipEventDestroy(ctx->ev_in);
@@ -1047,6 +1225,38 @@ int wd_compute_metrics(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, const 
     }
     (void)hipFree(scratch);
     return rc;
+}
+
+int wd_ctx_profile(wd_ctx *ctx, int enable)
+{
+    if (!ctx) return fail(WD_ERR_INVALID_ARG, "null context");
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    (void)hipStreamSynchronize(ctx->stream);
+    prof_collect(ctx);
+    ctx->kstats.clear();
+    ctx->profile = enable ? 1 : 0;
+    return WD_OK;
+}
+
+int wd_ctx_profile_read(wd_ctx *ctx, wd_kernel_stat *out, int cap, int *n)
+{
+    if (!ctx || (cap > 0 && !out)) return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    (void)hipStreamSynchronize(ctx->stream);
+    prof_collect(ctx);
+    int k = 0;
+    for (auto &kv : ctx->kstats) {
+        if (k < cap) {
+            std::memset(&out[k], 0, sizeof out[k]);
+            std::snprintf(out[k].name, sizeof out[k].name, "%s", kv.first.c_str());
+            out[k].launches = kv.second.launches;
+            out[k].total_ms = kv.second.ms;
+            out[k].alg_bytes = kv.second.bytes;
+        }
+        ++k;
+    }
+    if (n) *n = k;
+    return WD_OK;
 }
 
 int wd_line_solve_host(int kind, int n, int periodic, int scheme, double alpha_f, int fp64,

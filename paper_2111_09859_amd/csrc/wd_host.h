@@ -40,9 +40,14 @@ struct TuneKey {
     }
 };
 
+struct PendingLaunch;
 struct CachedGraph {
     int K = 0;
+    int profile = 0;
     hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> ev;          // event pairs captured per launch
+    std::vector<std::string> ev_name;
+    std::vector<double> ev_bytes;
     GridDev *d_grids = nullptr;
     Item *d_items = nullptr;
     std::vector<unsigned char> grids_bytes, items_bytes;
@@ -51,6 +56,18 @@ struct CachedGraph {
 
 struct ItemList {
     int kind, l, arg, first, count;
+};
+
+// live kernel timing (profiling mode): one record per launch
+struct KStat {
+    long long launches = 0;
+    double ms = 0.0;
+    double bytes = 0.0;    // algorithmic (compulsory) bytes
+};
+struct PendingLaunch {
+    hipEvent_t a, b;
+    std::string name;
+    double bytes;
 };
 
 struct Plan {
@@ -91,7 +108,8 @@ void build_items(Plan &P);
 int upload_plan(wd_ctx *ctx, const Plan &P, hipStream_t s);
 void issue_init(wd_ctx *ctx, const Plan &P, hipStream_t s);
 void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s);
-hipGraphExec_t graph_for(wd_ctx *ctx, const Plan &P, int K);
+CachedGraph *graph_for(wd_ctx *ctx, const Plan &P, int K);
+void prof_collect(wd_ctx *ctx);
 void ctx_drop_graphs(wd_ctx *ctx);
 int run_plan(wd_ctx *ctx, const Plan &P, int K, std::vector<GridState> &states);
 int poisson_convert(wd_ctx *ctx, const Plan &P, int i, int pidx, void *aux, hipStream_t s);
@@ -113,6 +131,10 @@ struct wd_ctx {
     std::map<wd::OpKey, wd::OpEntry> ops;
     std::map<wd::TuneKey, int> tune;
     std::vector<wd::CachedGraph> graphs;
+    int profile = 0;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<wd::PendingLaunch> pending;
+    std::map<std::string, wd::KStat> kstats;
     unsigned long long clock = 0;
     std::recursive_mutex mu;
 };
