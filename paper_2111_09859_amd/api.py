@@ -159,3 +159,47 @@ class Solver:
             out["hist"] = [np.frombuffer(h, dtype=np.float64).reshape(hist_cap, 2)[: min(it, hist_cap)].copy()
                            for h, it in zip(hists, iters)]
         return out
+
+
+class Server:
+    """Continuous-batching request loop (wd_server_*) on a Solver's device.
+    Keeps the tensors of submitted requests alive until they finish."""
+
+    def __init__(self, solver: Solver, budget_bytes: int, max_slots: int = 64):
+        self.solver = solver
+        self.srv = L.wd_server_create(solver.ctx, int(budget_bytes), int(max_slots))
+        self._keep = {}
+
+    def submit(self, prep: Prepared, method: L.wd_method, phi=None, session: int = -1,
+               hist_cap: int = 0) -> int:
+        torch = self.solver.torch
+        if phi is None:
+            phi = torch.zeros(prep.spec.shape, dtype=prep.dtype, device=self.solver.device)
+        torch.cuda.synchronize(self.solver.device)   # phi must be ready before the server reads it
+        rid = L.wd_server_submit(self.srv, prep.desc, method, C.c_void_p(phi.data_ptr()),
+                                 session, hist_cap)
+        self._keep[rid] = (prep, phi)
+        return rid
+
+    def wait(self, rid: int, timeout_s: float = -1.0) -> int:
+        return L.wd_server_wait(self.srv, rid, timeout_s)
+
+    def poll(self, rid: int) -> dict:
+        return L.wd_server_poll(self.srv, rid)
+
+    def result(self, rid: int):
+        return self._keep[rid][1]
+
+    def history(self, rid: int, cap: int):
+        return L.wd_server_history(self.srv, rid, cap)
+
+    def cancel(self, rid: int) -> int:
+        return L.wd_server_cancel(self.srv, rid)
+
+    def stats(self) -> dict:
+        return L.wd_server_stats(self.srv)
+
+    def close(self):
+        if self.srv:
+            L.wd_server_destroy(self.srv)
+            self.srv = None

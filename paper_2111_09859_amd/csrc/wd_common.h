@@ -76,7 +76,8 @@ struct GridDev {
     double *hist;             // [hist_cap][2]
     int hist_cap;
     int nparts;
-    GridState *state;
+    GridState *state;         // in the grid's own region
+    GridState *mirror;        // copy in the batch's contiguous state array
 
     LineOpDev dop[3];         // first-derivative operator per direction
     LineOpDev fop[3];         // filter-correction operator per direction

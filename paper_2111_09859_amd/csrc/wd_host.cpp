@@ -272,8 +272,9 @@ int grid_mode(const wd_grid_desc &d, const wd_method &m)
 
 int hist_dev_cap(const wd_method &m) { return std::min(m.max_iter, 1 << 17); }
 
-// device bytes of one grid's buffers
-static size_t grid_bytes(const wd_grid_desc &d, const wd_method &m)
+// device bytes of one grid's own region: its fields, partial sums,
+// residual partials, history and stopping state
+size_t grid_region_bytes(const wd_grid_desc &d, const wd_method &m)
 {
     const long long N = npoints(d);
     const size_t S = m.precision == WD_FP64 ? 8 : 4;
@@ -283,7 +284,7 @@ static size_t grid_bytes(const wd_grid_desc &d, const wd_method &m)
     if (m.rk == WD_RK4) b += f;                  // acc
     b += f;                                      // dt
     if (grid_mode(d, m) == MODE_GENERAL) b += (size_t)d.ndim * f;  // F_l
-    b += 3 * f;                                  // partial sums
+    b += 3 * f;                                  // partial sums / LAD field
     if (m.equation == WD_EQ_POISSON)
         b += (size_t)(d.ndim + 1) * al256((size_t)N * 8);  // FP64 conversion
     long long parts = N / d.n[d.ndim - 1];
@@ -294,8 +295,9 @@ static size_t grid_bytes(const wd_grid_desc &d, const wd_method &m)
     return b;
 }
 
-// worst-case work items of one grid (tile width 1)
-static long long grid_items(const wd_grid_desc &d)
+// worst-case work items of one grid (tile width 1), plus room for the
+// one-grid FP64 Poisson passes
+long long grid_items(const wd_grid_desc &d)
 {
     const long long N = npoints(d);
     long long lines = 0;
@@ -306,17 +308,22 @@ static long long grid_items(const wd_grid_desc &d)
     return 5 * lines + 3 * chunks + 2 * face + 8;
 }
 
+// batch tables: grid array, state mirrors, two one-grid views, items
+size_t table_bytes(int n, long long items)
+{
+    return al256((size_t)n * sizeof(GridDev)) + 2 * al256(sizeof(GridDev)) +
+           al256((size_t)(n + 1) * sizeof(GridState)) + al256((size_t)items * sizeof(Item)) + 1024;
+}
+
 size_t batch_bytes(int n, const wd_grid_desc *d, const wd_method *m)
 {
-    size_t b = al256((size_t)n * sizeof(GridDev)) + al256(sizeof(GridDev)) * 2;
     long long items = 0;
+    size_t b = 0;
     for (int i = 0; i < n; ++i) {
-        b += grid_bytes(d[i], m[i]);
+        b += grid_region_bytes(d[i], m[i]);
         items += grid_items(d[i]);
     }
-    b += al256((size_t)items * sizeof(Item));
-    b += al256((size_t)(n + 1) * sizeof(GridState));
-    return b + 4096;
+    return b + table_bytes(n, items);
 }
 
 // ---------------------------------------------------------------------
@@ -356,135 +363,171 @@ static double kprime(int scheme)
 }
 
 // ---------------------------------------------------------------------
-// planning of a batch into a caller workspace
-int plan_batch(wd_ctx *ctx, int n, const wd_grid_desc *descs, const wd_method *meths,
-               void *const *phis, void *ws, size_t ws_bytes, Plan &P)
+// planning
+// Describe one grid in `g`, its buffers carved from `region` (at least
+// grid_region_bytes).  The stopping state lives in the region, so a grid
+// keeps its progress when the batch around it changes.
+int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *phi,
+                void *region, GridDev &g, GridHost &h)
 {
-    P = Plan();
-    P.n = n;
-    P.fp64 = meths[0].precision == WD_FP64;
-    P.rk = meths[0].rk;
-    P.stages = P.rk == WD_RK4 ? 4 : 3;
-    P.maxdim = 0;
-    const size_t need = batch_bytes(n, descs, meths);
-    if (!ws || ws_bytes < need)
-        return fail(WD_ERR_NO_MEMORY, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
-    unsigned char *base = static_cast<unsigned char *>(ws);
+    std::memset(&g, 0, sizeof g);
+    h = GridHost();
+    const int fp64 = m.precision == WD_FP64;
+    const long long N = npoints(d);
+    unsigned char *base = static_cast<unsigned char *>(region);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         void *p = base + off;
         off += al256(bytes);
         return p;
     };
+    g.ndim = d.ndim;
+    g.mode = grid_mode(d, m);
+    g.N = N;
+    long long st = 1;
+    for (int l = 0; l < 3; ++l) {
+        g.n[l] = l < d.ndim ? d.n[l] : 1;
+        g.stride[l] = st;
+        st *= g.n[l];
+    }
+    for (int l = 0; l < d.ndim; ++l) {
+        g.periodic[l] = d.bc[l][0] == WD_BC_PERIODIC;
+        g.wall_lo[l] = d.bc[l][0] == WD_BC_WALL;
+        g.wall_hi[l] = d.bc[l][1] == WD_BC_WALL;
+        for (int s = 0; s < 2; ++s) {
+            const int b = d.bc[l][s];
+            g.xbc[2 * l + s] = b == WD_BC_NEUMANN ? XBC_NEUMANN : b == WD_BC_OUTFLOW ? XBC_OUTFLOW : XBC_NONE;
+        }
+    }
+    g.uniform = d.metric_mode == WD_METRIC_UNIFORM;
+    for (int l = 0; l < 3; ++l) g.invh[l] = (g.uniform && l < d.ndim) ? 1.0 / d.h[l] : 0.0;
+    g.met = d.metrics;
+    g.mask = d.mask;
+    g.eq = m.equation;
+    g.lad = m.equation == WD_EQ_HJ && m.gamma == WD_GAMMA_LAD;
+    g.curv = m.equation == WD_EQ_HJ && m.curvature;
+    g.scheme = m.scheme;
+    g.rk = m.rk == WD_RK4;
+    g.stages = g.rk ? 4 : 3;
+    g.need_lap = m.equation != WD_EQ_EIKONAL;
+    g.filter = m.filter;
+    bool has_x = false;
+    for (int f = 0; f < 6; ++f) has_x |= g.xbc[f] != XBC_NONE;
+    g.fused_resid = m.filter && !has_x;
+    g.eps = m.eps;
+    g.C = m.c_lad;
+    g.nu0 = m.nu0;
+    g.eps0 = m.eps0;
+    g.sigma = m.sigma;
+    g.kp = kprime(m.scheme);
+    g.tol = m.tol;
+    g.max_iter = m.max_iter;
+    g.stall = m.stall_window;
+    g.warm = m.warm_start;
+    // filter correction factor -(1 - 2 af)(-1)^N / 4^N
+    for (int N5 = 1; N5 <= 5; ++N5)
+        g.fcoef[N5] = -(1.0 - 2.0 * m.alpha_f) * ((N5 & 1) ? -1.0 : 1.0) / std::ldexp(1.0, 2 * N5);
+    switch (m.scheme) {
+    case WD_E2: g.da = 1.0; g.dradius = 1; break;
+    case WD_E4: g.da = 4.0 / 3.0; g.db = -1.0 / 3.0; g.dradius = 2; break;
+    case WD_E6: g.da = 1.5; g.db = -0.6; g.dc = 0.1; g.dradius = 3; break;
+    case WD_C4: g.da = 1.5; g.dradius = 1; g.compact = 1; break;
+    default: g.da = 14.0 / 9.0; g.db = 1.0 / 9.0; g.dradius = 2; g.compact = 1; break;
+    }
+    const size_t f = (size_t)N * (fp64 ? 8 : 4);
+    g.phi = phi;
+    g.ps = take(f);
+    g.acc = m.rk == WD_RK4 ? take(f) : nullptr;
+    g.dt = take(f);
+    if (g.mode == MODE_GENERAL)
+        for (int l = 0; l < d.ndim; ++l) g.F[l] = take(f);
+    for (int k = 0; k < 3; ++k) g.P[k] = take(f);
+    if (m.equation == WD_EQ_POISSON) {
+        h.pois_phip = take((size_t)N * 8);
+        for (int l = 0; l < d.ndim; ++l) h.pois_F[l] = take((size_t)N * 8);
+    }
+    long long parts = N / d.n[d.ndim - 1];
+    parts = std::max(parts, (N + kChunk - 1) / kChunk);
+    g.rpart = static_cast<double *>(take((size_t)parts * 16));
+    g.hist_cap = hist_dev_cap(m);
+    g.hist = static_cast<double *>(take((size_t)g.hist_cap * 16));
+    g.state = static_cast<GridState *>(take(sizeof(GridState)));
+    for (int l = 0; l < d.ndim; ++l) {
+        const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, d.n[l], g.periodic[l], m.scheme, 0.0, fp64);
+        if (!dop) return WD_ERR_NO_MEMORY;
+        g.dop[l] = *dop;
+        if (m.filter) {
+            const LineOpDev *fop = ctx_lineop(ctx, OP_FILTER, d.n[l], g.periodic[l], m.scheme, m.alpha_f, fp64);
+            if (!fop) return WD_ERR_NO_MEMORY;
+            g.fop[l] = *fop;
+        }
+        g.tw[l] = pick_tile(ctx, d, l, fp64);
+        if (l == 0)
+            g.ntiles[l] = (int)((N / d.n[0] + g.tw[0] - 1) / g.tw[0]);
+        else
+            g.ntiles[l] = (int)((N / ((long long)d.n[0] * d.n[l])) * ((d.n[0] + g.tw[l] - 1) / g.tw[l]));
+    }
+    g.nchunks = (int)((N + kChunk - 1) / kChunk);
+    g.nparts = g.fused_resid ? g.ntiles[d.ndim - 1] : g.nchunks;
+    if (off > grid_region_bytes(d, m)) return fail(WD_ERR_INVALID_ARG, "internal: grid layout overflow");
+    return WD_OK;
+}
+
+// Batch tables in `tables` (table_bytes of the grids' worst-case items);
+// P.grids / P.host must be filled.  Sets mirrors and builds the work lists.
+int plan_tables(Plan &P, void *tables, size_t bytes, long long items_cap)
+{
+    const int n = (int)P.grids.size();
+    P.n = n;
+    if (bytes < table_bytes(n, items_cap)) return fail(WD_ERR_NO_MEMORY, "table space too small");
+    unsigned char *base = static_cast<unsigned char *>(tables);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        void *p = base + off;
+        off += al256(b);
+        return p;
+    };
     P.d_grids = static_cast<GridDev *>(take((size_t)n * sizeof(GridDev)));
     P.d_aux = static_cast<GridDev *>(take(sizeof(GridDev)));
     P.d_aux2 = static_cast<GridDev *>(take(sizeof(GridDev)));
     P.d_states = static_cast<GridState *>(take((size_t)(n + 1) * sizeof(GridState)));
-    long long items_cap = 0;
-    for (int i = 0; i < n; ++i) items_cap += grid_items(descs[i]);
     P.d_items = static_cast<Item *>(take((size_t)items_cap * sizeof(Item)));
-    P.grids.resize(n);
-    const size_t S = P.fp64 ? 8 : 4;
+    P.maxdim = 0;
     for (int i = 0; i < n; ++i) {
-        const wd_grid_desc &d = descs[i];
-        const wd_method &m = meths[i];
-        GridDev &g = P.grids[i];
-        std::memset(&g, 0, sizeof g);
-        const long long N = npoints(d);
-        g.ndim = d.ndim;
-        g.mode = grid_mode(d, m);
-        g.N = N;
-        long long st = 1;
-        for (int l = 0; l < 3; ++l) {
-            g.n[l] = l < d.ndim ? d.n[l] : 1;
-            g.stride[l] = st;
-            st *= g.n[l];
-        }
-        for (int l = 0; l < d.ndim; ++l) {
-            g.periodic[l] = d.bc[l][0] == WD_BC_PERIODIC;
-            g.wall_lo[l] = d.bc[l][0] == WD_BC_WALL;
-            g.wall_hi[l] = d.bc[l][1] == WD_BC_WALL;
-            for (int s = 0; s < 2; ++s) {
-                const int b = d.bc[l][s];
-                g.xbc[2 * l + s] = b == WD_BC_NEUMANN ? XBC_NEUMANN : b == WD_BC_OUTFLOW ? XBC_OUTFLOW : XBC_NONE;
-            }
-        }
-        g.uniform = d.metric_mode == WD_METRIC_UNIFORM;
-        for (int l = 0; l < 3; ++l) g.invh[l] = (g.uniform && l < d.ndim) ? 1.0 / d.h[l] : 0.0;
-        g.met = d.metrics;
-        g.mask = d.mask;
-        g.eq = m.equation;
-        g.lad = m.equation == WD_EQ_HJ && m.gamma == WD_GAMMA_LAD;
-        g.curv = m.equation == WD_EQ_HJ && m.curvature;
-        g.scheme = m.scheme;
-        g.rk = m.rk == WD_RK4;
-        g.stages = P.stages;
-        g.need_lap = m.equation != WD_EQ_EIKONAL;
-        g.filter = m.filter;
-        bool has_x = false;
-        for (int f = 0; f < 6; ++f) has_x |= g.xbc[f] != XBC_NONE;
-        g.fused_resid = m.filter && !has_x;
-        g.eps = m.eps;
-        g.C = m.c_lad;
-        g.nu0 = m.nu0;
-        g.eps0 = m.eps0;
-        g.sigma = m.sigma;
-        g.kp = kprime(m.scheme);
-        g.tol = m.tol;
-        g.max_iter = m.max_iter;
-        g.stall = m.stall_window;
-        g.warm = m.warm_start;
-        // filter correction factor -(1 - 2 af)(-1)^N / 4^N
-        for (int N5 = 1; N5 <= 5; ++N5)
-            g.fcoef[N5] = -(1.0 - 2.0 * m.alpha_f) * ((N5 & 1) ? -1.0 : 1.0) / std::ldexp(1.0, 2 * N5);
-        switch (m.scheme) {
-        case WD_E2: g.da = 1.0; g.dradius = 1; break;
-        case WD_E4: g.da = 4.0 / 3.0; g.db = -1.0 / 3.0; g.dradius = 2; break;
-        case WD_E6: g.da = 1.5; g.db = -0.6; g.dc = 0.1; g.dradius = 3; break;
-        case WD_C4: g.da = 1.5; g.dradius = 1; g.compact = 1; break;
-        default: g.da = 14.0 / 9.0; g.db = 1.0 / 9.0; g.dradius = 2; g.compact = 1; break;
-        }
-        const size_t f = (size_t)N * S;
-        g.phi = phis ? phis[i] : nullptr;
-        g.ps = take(f);
-        g.acc = m.rk == WD_RK4 ? take(f) : nullptr;
-        g.dt = take(f);
-        if (g.mode == MODE_GENERAL)
-            for (int l = 0; l < d.ndim; ++l) g.F[l] = take(f);
-        for (int k = 0; k < 3; ++k) g.P[k] = take(f);
-        if (m.equation == WD_EQ_POISSON) {
-            P.pois_phip.push_back(take((size_t)N * 8));
-            for (int l = 0; l < 3; ++l) P.pois_F.push_back(l < d.ndim ? take((size_t)N * 8) : nullptr);
-        }
-        long long parts = N / d.n[d.ndim - 1];
-        parts = std::max(parts, (N + kChunk - 1) / kChunk);
-        g.rpart = static_cast<double *>(take((size_t)parts * 16));
-        g.hist_cap = hist_dev_cap(m);
-        g.hist = static_cast<double *>(take((size_t)g.hist_cap * 16));
-        g.state = P.d_states + i;
-        for (int l = 0; l < d.ndim; ++l) {
-            const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, d.n[l], g.periodic[l], m.scheme, 0.0, P.fp64);
-            if (!dop) return WD_ERR_NO_MEMORY;
-            g.dop[l] = *dop;
-            if (m.filter) {
-                const LineOpDev *fop = ctx_lineop(ctx, OP_FILTER, d.n[l], g.periodic[l], m.scheme, m.alpha_f, P.fp64);
-                if (!fop) return WD_ERR_NO_MEMORY;
-                g.fop[l] = *fop;
-            }
-            g.tw[l] = pick_tile(ctx, d, l, P.fp64);
-            if (l == 0)
-                g.ntiles[l] = (int)((N / d.n[0] + g.tw[0] - 1) / g.tw[0]);
-            else
-                g.ntiles[l] = (int)((N / ((long long)d.n[0] * d.n[l])) * ((d.n[0] + g.tw[l] - 1) / g.tw[l]));
-        }
-        g.nchunks = (int)((N + kChunk - 1) / kChunk);
-        g.nparts = g.fused_resid ? g.ntiles[d.ndim - 1] : g.nchunks;
-        P.maxdim = std::max(P.maxdim, d.ndim);
+        P.grids[i].mirror = P.d_states + i;
+        P.maxdim = std::max(P.maxdim, P.grids[i].ndim);
     }
-    if (off > ws_bytes) return fail(WD_ERR_NO_MEMORY, "workspace layout overflow");
     build_items(P);
     if ((long long)P.items.size() > items_cap) return fail(WD_ERR_INVALID_ARG, "internal: item overflow");
+    P.items_cap = items_cap;
     return WD_OK;
+}
+
+// one workspace: tables first, then each grid's region
+int plan_batch(wd_ctx *ctx, int n, const wd_grid_desc *descs, const wd_method *meths,
+               void *const *phis, void *ws, size_t ws_bytes, Plan &P)
+{
+    P = Plan();
+    P.fp64 = meths[0].precision == WD_FP64;
+    P.rk = meths[0].rk;
+    P.stages = P.rk == WD_RK4 ? 4 : 3;
+    const size_t need = batch_bytes(n, descs, meths);
+    if (!ws || ws_bytes < need)
+        return fail(WD_ERR_NO_MEMORY, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    long long items_cap = 0;
+    for (int i = 0; i < n; ++i) items_cap += grid_items(descs[i]);
+    const size_t tb = table_bytes(n, items_cap);
+    unsigned char *base = static_cast<unsigned char *>(ws);
+    size_t off = tb;
+    P.grids.resize(n);
+    P.host.resize(n);
+    for (int i = 0; i < n; ++i) {
+        int rc = layout_grid(ctx, descs[i], meths[i], phis ? phis[i] : nullptr, base + off,
+                             P.grids[i], P.host[i]);
+        if (rc) return rc;
+        off += grid_region_bytes(descs[i], meths[i]);
+    }
+    return plan_tables(P, ws, tb, items_cap);
 }
 
 // work lists in launch order
@@ -565,7 +608,8 @@ void build_items(Plan &P)
     }
     {
         ItemList &L = list(PASS_INIT, 0, 0);
-        for (int i = 0; i < n; ++i) add_tiles(L, i, P.grids[i].nchunks);
+        for (int i = 0; i < n; ++i)
+            if (P.host[i].init) add_tiles(L, i, P.grids[i].nchunks);
         P.init = (int)P.lists.size() - 1;
     }
 }
@@ -907,20 +951,21 @@ int run_plan(wd_ctx *ctx, const Plan &P, int K, std::vector<GridState> &states)
 
 // FP64 Poisson conversion of grid i of a plan (after the march): phi' is in
 // g.phi (solve precision); the distance replaces it, phi' goes to aux.
-int poisson_convert(wd_ctx *ctx, const Plan &P, int i, int pidx, void *aux, hipStream_t s)
+int poisson_convert(wd_ctx *ctx, const Plan &P, int i, void *aux, hipStream_t s)
 {
     const GridDev &g = P.grids[i];
+    const GridHost &gh = P.host[i];
     const size_t S = P.fp64 ? 8 : 4;
     if (aux && hipMemcpyAsync(aux, g.phi, (size_t)g.N * S, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return fail(WD_ERR_HIP, "copy of phi' failed");
-    double *phip = static_cast<double *>(P.pois_phip[pidx]);
+    double *phip = static_cast<double *>(gh.pois_phip);
     launch_convert(P.fp64, 1, g.phi, phip, g.N, s);
     // FP64 first derivatives of phi' with a one-grid FP64 view
     GridDev v = g;
     v.phi = phip;
     v.lad = 0;
     for (int l = 0; l < g.ndim; ++l) {
-        v.F[l] = P.pois_F[(size_t)pidx * 3 + l];
+        v.F[l] = gh.pois_F[l];
         const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, g.n[l], g.periodic[l], g.scheme, 0.0, 1);
         if (!dop) return WD_ERR_NO_MEMORY;
         v.dop[l] = *dop;
@@ -937,6 +982,8 @@ int poisson_convert(wd_ctx *ctx, const Plan &P, int i, int pidx, void *aux, hipS
         std::vector<Item> it(nt);
         for (int t = 0; t < nt; ++t) it[t] = Item{0, t};
         Item *d_it = P.d_items + P.items.size();  // spare item space after the plan's lists
+        if ((long long)(P.items.size() + nt) > P.items_cap)
+            return fail(WD_ERR_INVALID_ARG, "internal: no item space for the Poisson passes");
         if (hipMemcpyAsync(d_it, it.data(), nt * sizeof(Item), hipMemcpyHostToDevice, s) != hipSuccess)
             return fail(WD_ERR_HIP, "poisson items upload failed");
         launch_pass(PASS_D1, 1, P.d_aux, d_it, nt, l, 0, nwg_for(ctx, 1, nt), s);
@@ -963,13 +1010,11 @@ int solve_plan(wd_ctx *ctx, Plan &P, void *const *aux, double *const *hists, int
     rc = run_plan(ctx, P, ctx->graph_iters, states);
     if (rc) return rc;
     int worst = WD_OK;
-    int pidx = 0;
     for (int i = 0; i < P.n; ++i) {
         const GridDev &g = P.grids[i];
         int st = states[i].status;
         if (g.eq == 2) {
-            int r2 = poisson_convert(ctx, P, i, pidx, aux ? aux[i] : nullptr, s);
-            ++pidx;
+            int r2 = poisson_convert(ctx, P, i, aux ? aux[i] : nullptr, s);
             if (r2) return r2;
         }
         if (iters) iters[i] = states[i].iter;
@@ -1324,7 +1369,7 @@ int wd_poisson_distance(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, int p
     if (dist != phip &&
         hipMemcpyAsync(dist, phip, (size_t)P.grids[0].N * S, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return fail(WD_ERR_HIP, "copy failed");
-    return poisson_convert(ctx, P, 0, 0, nullptr, s);
+    return poisson_convert(ctx, P, 0, nullptr, s);
 }
 
 }  // extern "C"

@@ -70,9 +70,17 @@ struct PendingLaunch {
     double bytes;
 };
 
+struct GridHost {
+    void *pois_phip = nullptr;   // FP64 phi' (Poisson grids)
+    void *pois_F[3] = {nullptr, nullptr, nullptr};
+    bool init = true;            // issue the initial field for this grid
+};
+
 struct Plan {
     int n = 0, fp64 = 0, rk = 1, stages = 4, maxdim = 0;
     std::vector<GridDev> grids;
+    std::vector<GridHost> host;
+    long long items_cap = 0;
     std::vector<Item> items;
     std::vector<ItemList> lists;
     int cart[3], d1[3], d2[3], filt[3], face[6], lad[3];
@@ -81,8 +89,6 @@ struct Plan {
     GridDev *d_aux = nullptr, *d_aux2 = nullptr;
     GridState *d_states = nullptr;
     Item *d_items = nullptr;
-    std::vector<void *> pois_phip;   // per Poisson grid: FP64 phi'
-    std::vector<void *> pois_F;      // per Poisson grid: 3 FP64 derivative buffers
 };
 
 int fail(int code, const char *fmt, ...);
@@ -102,6 +108,12 @@ int build_line_system(int kind, int n, int periodic, int scheme, double af, int 
                       std::vector<double> &right, std::vector<double> &scale);
 const LineOpDev *ctx_lineop(wd_ctx *ctx, int kind, int n, int periodic, int scheme,
                             double af, int fp64);
+size_t grid_region_bytes(const wd_grid_desc &d, const wd_method &m);
+long long grid_items(const wd_grid_desc &d);
+size_t table_bytes(int n, long long items);
+int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *phi,
+                void *region, GridDev &g, GridHost &h);
+int plan_tables(Plan &P, void *tables, size_t bytes, long long items_cap);
 int plan_batch(wd_ctx *ctx, int n, const wd_grid_desc *descs, const wd_method *meths,
                void *const *phis, void *ws, size_t ws_bytes, Plan &P);
 void build_items(Plan &P);
@@ -112,7 +124,7 @@ CachedGraph *graph_for(wd_ctx *ctx, const Plan &P, int K);
 void prof_collect(wd_ctx *ctx);
 void ctx_drop_graphs(wd_ctx *ctx);
 int run_plan(wd_ctx *ctx, const Plan &P, int K, std::vector<GridState> &states);
-int poisson_convert(wd_ctx *ctx, const Plan &P, int i, int pidx, void *aux, hipStream_t s);
+int poisson_convert(wd_ctx *ctx, const Plan &P, int i, void *aux, hipStream_t s);
 int solve_plan(wd_ctx *ctx, Plan &P, void *const *aux, double *const *hists, int hist_cap,
                int *iters, int *status);
 

@@ -22,6 +22,7 @@ enum PassKind {
 void launch_pass(int kind, int fp64, const GridDev *grids, const Item *items,
                  int nitems, int l, int stage, int nwg, hipStream_t s);
 void launch_finalize(const GridDev *grids, int ngrids, hipStream_t s);
+void launch_mirror(const GridDev *grids, int ngrids, hipStream_t s);
 void launch_convert(int src_fp64, int dst_fp64, const void *src, void *dst,
                     long long n, hipStream_t s);
 void launch_invert(const double *J, void *out, int out_fp64, int d,

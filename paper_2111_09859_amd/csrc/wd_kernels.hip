@@ -946,12 +946,15 @@ k_init(const GridDev *__restrict__ grids, const Item *__restrict__ items,
         const GridDev &g = grids[item.grid];
         T *phi = static_cast<T *>(g.phi);
         if (item.tile == 0 && threadIdx.x == 0) {
-            g.state->done = 0;
-            g.state->iter = 0;
-            g.state->status = 1;
-            g.state->best_iter = 0;
-            g.state->best = INFINITY;
-            g.state->last = INFINITY;
+            GridState st;
+            st.done = 0;
+            st.iter = 0;
+            st.status = 1;
+            st.best_iter = 0;
+            st.best = INFINITY;
+            st.last = INFINITY;
+            *g.state = st;
+            *g.mirror = st;
         }
         const long long q0 = (long long)item.tile * kChunk;
         for (int i = threadIdx.x; i < kChunk; i += kThreads) {
@@ -979,35 +982,44 @@ k_finalize(const GridDev *__restrict__ grids, int ngrids)
     }
     block_reduce(mx, sm, sh);
     if (threadIdx.x != 0) return;
-    GridState *st = g.state;
-    const int it = st->iter;
+    GridState st = *g.state;
+    const int it = st.iter;
     const double l2 = sqrt(sm / (double)g.N);
     if (it < g.hist_cap) {
         g.hist[2 * it] = mx;
         g.hist[2 * it + 1] = l2;
     }
     const int nit = it + 1;
-    st->iter = nit;
-    st->last = mx;
+    st.iter = nit;
+    st.last = mx;
     if (!(fabs(mx) <= 1.0e300) || !(fabs(l2) <= 1.0e300)) {
-        st->status = -3;
-        st->done = 1;
+        st.status = -3;
+        st.done = 1;
     } else if (mx <= g.tol) {
-        st->status = 0;
-        st->done = 1;
+        st.status = 0;
+        st.done = 1;
     } else {
-        if (mx < st->best) {
-            st->best = mx;
-            st->best_iter = nit;
+        if (mx < st.best) {
+            st.best = mx;
+            st.best_iter = nit;
         }
-        if (g.stall > 0 && nit - st->best_iter >= g.stall) {
-            st->status = 2;
-            st->done = 1;
+        if (g.stall > 0 && nit - st.best_iter >= g.stall) {
+            st.status = 2;
+            st.done = 1;
         } else if (nit >= g.max_iter) {
-            st->status = 1;
-            st->done = 1;
+            st.status = 1;
+            st.done = 1;
         }
     }
+    *g.state = st;
+    *g.mirror = st;   // the host reads the contiguous mirrors after each round
+}
+
+// copy every grid's state into the batch mirrors (after a re-plan)
+__global__ void k_mirror(const GridDev *__restrict__ grids, int ngrids)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ngrids) *grids[i].mirror = *grids[i].state;
 }
 
 // ---------------------------------------------------------------------
@@ -1112,6 +1124,12 @@ void launch_pass(int kind, int fp64, const GridDev *g, const Item *it, int nitem
     if (nwg > nitems) nwg = nitems;
     if (fp64) line_launch<double>(kind, g, it, nitems, l, stage, nwg, s);
     else line_launch<float>(kind, g, it, nitems, l, stage, nwg, s);
+}
+
+void launch_mirror(const GridDev *g, int ngrids, hipStream_t s)
+{
+    if (ngrids <= 0) return;
+    hipLaunchKernelGGL(k_mirror, dim3((ngrids + 255) / 256), dim3(256), 0, s, g, ngrids);
 }
 
 void launch_finalize(const GridDev *g, int ngrids, hipStream_t s)
