@@ -172,6 +172,19 @@ int wd_solve_batched(wd_ctx *ctx, int n, const wd_grid_desc *descs,
                      int *iters, int *status, void *ws, size_t ws_bytes,
                      void *stream);
 
+/* Tile autotuning: for each grid direction, time `iters` pseudo iterations
+ * of this grid and method with every candidate tile width (lines per
+ * workgroup tile) and keep the fastest in the context's cache, keyed by the
+ * grid shape, direction and precision; later plans of that shape use it.
+ * Results do not depend on the tile widths (each point's arithmetic is the
+ * same), only the speed does.
+ *   phi   : device scratch field of the grid (overwritten).
+ *   ws    : device workspace of at least wd_workspace_bytes.
+ *   widths: host, receives the chosen width per direction (may be NULL). */
+int wd_autotune(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method,
+                void *phi, void *ws, size_t ws_bytes, int iters, int *widths,
+                void *stream);
+
 /* Eq. Poiss2 on its own: distance = -|grad phi'| + sqrt(|grad phi'|^2 +
  * 2 phi') with the gradient by `scheme` and the metrics, evaluated in FP64.
  *   phip, dist: device, grid layout, `precision` (FP32 or FP64).

@@ -82,6 +82,7 @@ def lib():
         "wd_solve_batched": ([vp, C.c_int, gd, me, C.POINTER(vp), C.POINTER(vp),
                               C.POINTER(dp), C.c_int, ip, ip, vp, C.c_size_t, vp], C.c_int),
         "wd_poisson_distance": ([vp, gd, C.c_int, C.c_int, vp, vp, vp, C.c_size_t, vp], C.c_int),
+        "wd_autotune": ([vp, gd, me, vp, vp, C.c_size_t, C.c_int, ip, vp], C.c_int),
         "wd_ctx_profile": ([vp, C.c_int], C.c_int),
         "wd_ctx_profile_read": ([vp, C.POINTER(wd_kernel_stat), C.c_int, ip], C.c_int),
         "wd_line_solve_host": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, dp,
@@ -194,6 +195,13 @@ def wd_poisson_distance(ctx, desc, scheme, precision, phip_ptr, dist_ptr, ws_ptr
     return _check(lib().wd_poisson_distance(ctx, C.byref(desc), scheme, precision, phip_ptr,
                                             dist_ptr, ws_ptr, ws_bytes, stream),
                   "wd_poisson_distance")
+
+
+def wd_autotune(ctx, desc, method, phi_ptr, ws_ptr, ws_bytes, iters=20, stream=None):
+    w = (C.c_int * 3)()
+    _check(lib().wd_autotune(ctx, C.byref(desc), C.byref(method), phi_ptr, ws_ptr, ws_bytes,
+                             iters, w, stream), "wd_autotune", ok=(WD_OK,))
+    return list(w)[: desc.ndim]
 
 
 def wd_ctx_profile(ctx, enable: bool) -> None:

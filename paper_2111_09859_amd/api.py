@@ -141,6 +141,14 @@ class Solver:
             out["aux"] = auxt
         return out
 
+    def autotune(self, prep: Prepared, method: L.wd_method, iters: int = 20):
+        """Pick and cache the fastest tile width per direction for this grid."""
+        torch = self.torch
+        phi = torch.zeros(prep.spec.shape, dtype=prep.dtype, device=self.device)
+        ws = self.workspace(L.wd_workspace_bytes(self.ctx, [prep.desc], [method]))
+        return L.wd_autotune(self.ctx, prep.desc, method, C.c_void_p(phi.data_ptr()),
+                             C.c_void_p(ws.data_ptr()), ws.numel(), iters, self.stream())
+
     def solve_batched(self, preps, methods, phis=None, hist_cap=0, check=True):
         torch = self.torch
         if phis is None:

@@ -1272,6 +1272,71 @@ int wd_compute_metrics(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, const 
     return rc;
 }
 
+int wd_autotune(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method, void *phi,
+                void *ws, size_t ws_bytes, int iters, int *widths, void *stream)
+{
+    if (!ctx || !desc || !method || !phi || iters < 1) return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    int rc = check_desc(desc);
+    if (!rc) rc = check_method(method);
+    if (rc) return rc;
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    StreamJoin join(ctx, stream);
+    hipStream_t s = ctx->stream;
+    wd_method m = *method;
+    m.tol = 0.0;                 // run exactly `iters` iterations
+    m.max_iter = iters;
+    m.stall_window = 0;
+    m.warm_start = 0;
+    const int fp64 = m.precision == WD_FP64;
+    const int prof = ctx->profile;
+    ctx->profile = 0;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    void *phis[1] = {phi};
+    const wd_grid_desc &d = *desc;
+    for (int l = 0; l < d.ndim && !rc; ++l) {
+        TuneKey key{d.ndim, d.n[0], d.n[1], d.n[2], l, fp64};
+        const int n = d.n[l];
+        const int wmax = l == 0 ? std::max(1, kTileMax / n) : std::max(1, std::min(64, kTileMax / n));
+        int best_w = pick_tile(ctx, d, l, fp64);
+        float best_ms = 1e30f;
+        for (int w = 1; w <= wmax && !rc; w *= 2) {
+            ctx->tune[key] = w;
+            Plan P;
+            rc = plan_batch(ctx, 1, desc, &m, phis, ws, ws_bytes, P);
+            if (rc) break;
+            rc = upload_plan(ctx, P, s);
+            if (rc) break;
+            issue_init(ctx, P, s);
+            CachedGraph *cg = graph_for(ctx, P, iters);
+            if (!cg) { rc = WD_ERR_HIP; break; }
+            float ms = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {   // first replay warms caches
+                issue_init(ctx, P, s);
+                (void)hipEventRecord(e0, s);
+                (void)hipGraphLaunch(cg->exec, s);
+                (void)hipEventRecord(e1, s);
+                if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(WD_ERR_HIP, "autotune run failed"); break; }
+                float t = 0.f;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                ms = std::min(ms, t);
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_w = w;
+            }
+        }
+        ctx->tune[key] = best_w;
+        if (widths) widths[l] = best_w;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->profile = prof;
+    return rc;
+}
+
 int wd_ctx_profile(wd_ctx *ctx, int enable)
 {
     if (!ctx) return fail(WD_ERR_INVALID_ARG, "null context");

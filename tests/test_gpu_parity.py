@@ -257,3 +257,21 @@ def test_batched_equals_alone_bitwise(solver):
             b = b.cpu().numpy()
             say(f"[batched {prec}] grid {i} max|diff|={np.abs(a - b).max():.3e}")
             assert np.array_equal(a, b)
+
+
+def test_autotune_keeps_results_bitwise(solver):
+    """Tile widths change speed only: a solve after autotuning gives bitwise
+    the field of the untuned solve."""
+    from paper_2111_09859_amd import api
+    spec = G.cylinder(96, 64, rout=6.0, dr1=1e-2, ratio=1.08)
+    m = gmethod(eq="HJ", gamma="LAD", curv=1, scheme="C6", tol=0.0, max_iter=40, precision="fp32")
+    fresh = api.Solver(0)
+    try:
+        prep = fresh.prepare(spec, "C6", "fp32")
+        before = fresh.solve(prep, m)["phi"].cpu().numpy()
+        widths = fresh.autotune(prep, m, iters=8)
+        say(f"[autotune] widths={widths}")
+        after = fresh.solve(prep, m)["phi"].cpu().numpy()
+        assert np.array_equal(before, after)
+    finally:
+        fresh.close()
