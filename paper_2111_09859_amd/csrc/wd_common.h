@@ -24,10 +24,13 @@ struct LineOpDev {
     int n;
     int periodic;
     int nlev;                 // 0: no solve (explicit scheme), scale == 1
-    int pad;
+    int uniform;              // 1: every row has the same multipliers
+                              //    (periodic lines): use lr / usc below
     int smod[kMaxLev];        // neighbour distance of each level (mod n)
     const void *tab;          // T2 [nlev][n]: (left, right) multipliers
     const void *scale;        // T [n]
+    double lr[kMaxLev][2];    // uniform multipliers per level
+    double usc;               // uniform final scale
 };
 
 enum GridMode { MODE_CART = 0, MODE_GENERAL = 1 };
@@ -60,6 +63,8 @@ struct GridDev {
 
     // method
     int eq, lad, curv, scheme, rk, need_lap, filter, fused_resid;
+    int fuse_faces;           // extrapolated faces all normal to the last
+                              // direction: applied inside its passes
     int stages;
     double eps, C, nu0, eps0, sigma, kp, tol;
     int max_iter, stall;

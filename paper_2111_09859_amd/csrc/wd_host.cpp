@@ -165,6 +165,22 @@ const LineOpDev *ctx_lineop(wd_ctx *ctx, int kind, int n, int periodic, int sche
     }
     e.dev.nlev = nlev;
     for (int k = 0; k < nlev; ++k) e.dev.smod[k] = smod[k];
+    // periodic constant-coefficient lines reduce to the same multipliers on
+    // every row: keep them as per-level scalars
+    bool uniform = true;
+    for (int k = 0; k < nlev && uniform; ++k)
+        for (int i = 1; i < n && uniform; ++i)
+            uniform = left[(size_t)k * n + i] == left[(size_t)k * n] &&
+                      right[(size_t)k * n + i] == right[(size_t)k * n];
+    for (int i = 1; i < n && uniform; ++i) uniform = scale[i] == scale[0];
+    e.dev.uniform = uniform ? 1 : 0;
+    if (uniform) {
+        for (int k = 0; k < nlev; ++k) {
+            e.dev.lr[k][0] = left[(size_t)k * n];
+            e.dev.lr[k][1] = right[(size_t)k * n];
+        }
+        e.dev.usc = scale[0];
+    }
     const size_t es = fp64 ? 8 : 4;
     const size_t tab_bytes = (size_t)nlev * n * 2 * es;
     const size_t bytes = tab_bytes + (size_t)n * es + 256;
@@ -411,9 +427,16 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     g.stages = g.rk ? 4 : 3;
     g.need_lap = m.equation != WD_EQ_EIKONAL;
     g.filter = m.filter;
-    bool has_x = false;
-    for (int f = 0; f < 6; ++f) has_x |= g.xbc[f] != XBC_NONE;
-    g.fused_resid = m.filter && !has_x;
+    bool has_x = false, only_last = true;
+    for (int f = 0; f < 6; ++f)
+        if (g.xbc[f] != XBC_NONE) {
+            has_x = true;
+            only_last &= (f >> 1) == d.ndim - 1;
+        }
+    // faces normal to the last direction are applied inside its passes
+    // (that direction's tiles hold whole lines); otherwise face kernels
+    g.fuse_faces = has_x && only_last && !(g.mode == MODE_GENERAL && !g.need_lap);
+    g.fused_resid = m.filter && (!has_x || g.fuse_faces);
     g.eps = m.eps;
     g.C = m.c_lad;
     g.nu0 = m.nu0;
@@ -594,18 +617,20 @@ void build_items(Plan &P)
             if (!P.grids[i].fused_resid) add_tiles(L, i, P.grids[i].nchunks);
         P.resid = (int)P.lists.size() - 1;
     }
-    for (int f = 0; f < 6; ++f) {
-        ItemList &L = list(PASS_FACE, f, 1);
-        for (int i = 0; i < n; ++i) {
-            const GridDev &g = P.grids[i];
-            const int l = f >> 1;
-            if (l < g.ndim && g.xbc[f] != XBC_NONE) {
+    for (int target = 0; target < 2; ++target)
+        for (int f = 0; f < 6; ++f) {
+            ItemList &L = list(PASS_FACE, f, target);
+            for (int i = 0; i < n; ++i) {
+                const GridDev &g = P.grids[i];
+                const int l = f >> 1;
+                if (l >= g.ndim || g.xbc[f] == XBC_NONE) continue;
+                if (target == 1 && g.fuse_faces) continue;   // done inside the passes
+                if (target == 0 && !P.host[i].init) continue;
                 const long long nf = g.N / g.n[l];
                 add_tiles(L, i, (int)((nf + kChunk - 1) / kChunk));
             }
+            (target ? P.face : P.face_init)[f] = (int)P.lists.size() - 1;
         }
-        P.face[f] = (int)P.lists.size() - 1;
-    }
     {
         ItemList &L = list(PASS_INIT, 0, 0);
         for (int i = 0; i < n; ++i)
@@ -772,7 +797,7 @@ void issue_list(wd_ctx *ctx, const Plan &P, int li, int stage, hipStream_t s)
 void issue_faces(wd_ctx *ctx, const Plan &P, int target, hipStream_t s)
 {
     for (int f = 0; f < 6; ++f) {
-        const ItemList &L = P.lists[P.face[f]];
+        const ItemList &L = P.lists[target ? P.face[f] : P.face_init[f]];
         if (L.count == 0) continue;
         PendingLaunch pl;
         if (ctx->profile) prof_begin(ctx, pl, "k_face", 0.0, s);

@@ -83,7 +83,7 @@ struct Plan {
     long long items_cap = 0;
     std::vector<Item> items;
     std::vector<ItemList> lists;
-    int cart[3], d1[3], d2[3], filt[3], face[6], lad[3];
+    int cart[3], d1[3], d2[3], filt[3], face[6], face_init[6], lad[3];
     int fin = 0, resid = 0, init = 0;
     GridDev *d_grids = nullptr;
     GridDev *d_aux = nullptr, *d_aux2 = nullptr;

@@ -97,7 +97,6 @@ __device__ inline Tile decode_tile(const GridDev &g, int l, int t)
 
 struct Pts {
     int J[kPPT];    // position along the line
-    int Wl[kPPT];   // line within the tile
     int Q[kPPT];    // global offset within the grid
 };
 
@@ -116,7 +115,6 @@ __device__ inline void tile_points(const Tile &tl, int l, Pts &pt)
             w = p - j * tl.wa;
         }
         pt.J[k] = j;
-        pt.Wl[k] = w;
         pt.Q[k] = (int)(tl.base + w * tl.gw + j * tl.gj);
     }
 }
@@ -126,10 +124,12 @@ __device__ inline bool pvalid(const Tile &tl, int k)
     return (int)threadIdx.x + k * kThreads < tl.P;
 }
 
-// grid indices of a tile point
+// grid indices of point k of this thread in a tile
 __device__ inline void tile_index(const GridDev &g, const Tile &tl, int l,
-                                  int w, int j, int *idx)
+                                  int k, int j, int *idx)
 {
+    const int p = (int)threadIdx.x + k * kThreads;
+    const int w = l == 0 ? p / tl.n : p - j * tl.wa;
     if (l == 0) {
         const long long line = tl.rest + w;
         idx[0] = j;
@@ -257,17 +257,23 @@ __device__ T filter_rhs(const GridDev &g, const T *X, int p, int j, int n,
         if (d == 0) return (T)0;
         N = min(d, 5);
     }
-    // signed binomial weights of the 2N-th central difference
-    constexpr int w1[3] = {1, -2, 1};
-    constexpr int w2[5] = {1, -4, 6, -4, 1};
-    constexpr int w3[7] = {1, -6, 15, -20, 15, -6, 1};
-    constexpr int w4[9] = {1, -8, 28, -56, 70, -56, 28, -8, 1};
-    constexpr int w5[11] = {1, -10, 45, -120, 210, -252, 210, -120, 45, -10, 1};
-    const int *w = N == 5 ? w5 : N == 4 ? w4 : N == 3 ? w3 : N == 2 ? w2 : w1;
-    T s = (T)0;
-    for (int i = -N; i <= N; ++i) {
-        T v = periodic ? pval(X, p, j, i, n, lj, (T)0) : X[p + i * lj];
-        s += (T)w[i + N] * v;
+    T s;
+    if (N == 5) {
+        // tenth central difference, symmetric pairs
+        T v[11];
+#pragma unroll
+        for (int o = -5; o <= 5; ++o)
+            v[o + 5] = periodic ? pval(X, p, j, o, n, lj, (T)0) : X[p + o * lj];
+        s = (v[0] + v[10]) - (T)10 * (v[1] + v[9]) + (T)45 * (v[2] + v[8])
+            - (T)120 * (v[3] + v[7]) + (T)210 * (v[4] + v[6]) - (T)252 * v[5];
+    } else {
+        // sum_k (-1)^k C(2N, k) f_{j-N+k}, binomials built as we go
+        s = (T)0;
+        int c = 1;
+        for (int k = 0; k <= 2 * N; ++k) {
+            s += (T)((k & 1) ? -c : c) * X[p + (k - N) * lj];
+            c = c * (2 * N - k) / (k + 1);
+        }
     }
     return (T)g.fcoef[N] * s;
 }
@@ -288,32 +294,70 @@ __device__ T fourth_diff(const T *X, int p, int j, int n, int lj, int periodic)
 }
 
 // ---------------------------------------------------------------------
-// Parallel cyclic reduction with precomputed multipliers.  On entry v holds
-// the right-hand side of this thread's points; on exit the solution.  The
+// Parallel cyclic reduction with precomputed multipliers, for g <= G
+// right-hand sides of the same line system at once (field f uses LDS
+// segment f of A and B, each tl.P long).  On entry v[f] holds this thread's
+// right-hand sides, on exit the solutions.  One barrier per level serves
+// all fields; periodic lines use per-level scalar multipliers, other lines
+// read the next level's multipliers while the current one is applied.  The
 // caller must have finished every read of A and B.
-template <typename T>
-__device__ void pcr_solve(T (&v)[kPPT], const Pts &pt, const Tile &tl,
-                          const LineOpDev &op, T *A, T *B)
+template <typename T, int G>
+__device__ void pcr_multi(T (&v)[G][kPPT], int g, const Pts &pt, const Tile &tl,
+                          const LineOpDev &op, T *A, T *B, bool in_lds = false)
 {
     using T2 = typename V2<T>::t;
     const int nlev = op.nlev;
-    if (nlev == 0) return;
     const int tid = threadIdx.x;
-    const int n = tl.n, lj = tl.lj;
+    const int n = tl.n, lj = tl.lj, P = tl.P;
+    if (in_lds) {
+        // right-hand sides were written to A by the caller (after a barrier)
 #pragma unroll
-    for (int k = 0; k < kPPT; ++k)
-        if (pvalid(tl, k)) A[tid + k * kThreads] = v[k];
-    __syncthreads();
+        for (int f = 0; f < G; ++f) {
+            if (f >= g) break;
+#pragma unroll
+            for (int k = 0; k < kPPT; ++k)
+                if (pvalid(tl, k)) v[f][k] = A[f * P + tid + k * kThreads];
+        }
+    }
+    if (nlev == 0) {
+        if (in_lds) __syncthreads();
+        return;
+    }
+    if (!in_lds) {
+#pragma unroll
+        for (int f = 0; f < G; ++f) {
+            if (f >= g) break;
+#pragma unroll
+            for (int k = 0; k < kPPT; ++k)
+                if (pvalid(tl, k)) A[f * P + tid + k * kThreads] = v[f][k];
+        }
+        __syncthreads();
+    }
     T *cur = A, *nxt = B;
     const T2 *tab = static_cast<const T2 *>(op.tab);
+    const bool uni = op.uniform;
+    T2 cn[kPPT];
+    if (!uni) {
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k)
+            if (pvalid(tl, k)) cn[k] = tab[pt.J[k]];
+    }
     for (int lev = 0; lev < nlev; ++lev) {
         const int s = op.smod[lev];
-        const T2 *row = tab + (long long)lev * n;
         const bool more = lev + 1 < nlev;
+        T2 cu;
+        cu.x = (T)op.lr[lev][0];
+        cu.y = (T)op.lr[lev][1];
+        const T2 *nrow = tab + (long long)(lev + 1) * n;
 #pragma unroll
         for (int k = 0; k < kPPT; ++k) {
             if (!pvalid(tl, k)) continue;
             const int j = pt.J[k];
+            T2 c = cu;
+            if (!uni) {
+                c = cn[k];
+                if (more) cn[k] = nrow[j];   // next level, in flight meanwhile
+            }
             const int p = tid + k * kThreads;
             int jm = j - s, jp = j + s;
             if (op.periodic) {
@@ -323,11 +367,13 @@ __device__ void pcr_solve(T (&v)[kPPT], const Pts &pt, const Tile &tl,
                 jm = max(jm, 0);
                 jp = min(jp, n - 1);
             }
-            const T2 c = row[j];
-            const T lft = cur[p + (jm - j) * lj];
-            const T rgt = cur[p + (jp - j) * lj];
-            v[k] = v[k] + c.x * lft + c.y * rgt;
-            if (more) nxt[p] = v[k];
+            const int om = p + (jm - j) * lj, opp = p + (jp - j) * lj;
+#pragma unroll
+            for (int f = 0; f < G; ++f) {
+                if (f >= g) break;
+                v[f][k] = v[f][k] + c.x * cur[f * P + om] + c.y * cur[f * P + opp];
+                if (more) nxt[f * P + p] = v[f][k];
+            }
         }
         if (more) {
             __syncthreads();
@@ -336,19 +382,52 @@ __device__ void pcr_solve(T (&v)[kPPT], const Pts &pt, const Tile &tl,
     }
     const T *sc = static_cast<const T *>(op.scale);
 #pragma unroll
-    for (int k = 0; k < kPPT; ++k)
-        if (pvalid(tl, k)) v[k] *= sc[pt.J[k]];
+    for (int k = 0; k < kPPT; ++k) {
+        if (!pvalid(tl, k)) continue;
+        const T m = uni ? (T)op.usc : sc[pt.J[k]];
+#pragma unroll
+        for (int f = 0; f < G; ++f)
+            if (f < g) v[f][k] *= m;
+    }
     __syncthreads();
+}
+
+template <typename T>
+__device__ inline void pcr_solve(T (&v)[kPPT], const Pts &pt, const Tile &tl,
+                                 const LineOpDev &op, T *A, T *B)
+{
+    pcr_multi<T, 1>(reinterpret_cast<T(&)[1][kPPT]>(v), 1, pt, tl, op, A, B);
+}
+
+// Extrapolated faces normal to direction l, applied inside a line tile
+// whose new values sit in LDS X: points j = 0 / n-1 of each line take
+// (4 f_1 - f_2)/3 (Neumann) or 2 f_1 - f_2 (outflow) from their inward
+// neighbours, unless they are wall or solid points.
+template <typename T>
+__device__ inline T face_value(const GridDev &g, int l, const T *X, int p, int j, int n,
+                               int lj, T v, bool zero)
+{
+    int code = XBC_NONE, in = 0;
+    if (j == 0) {
+        code = g.xbc[2 * l];
+        in = lj;
+    } else if (j == n - 1) {
+        code = g.xbc[2 * l + 1];
+        in = -lj;
+    }
+    if (code == XBC_NONE || zero) return v;
+    const T a = X[p + in], b = X[p + 2 * in];
+    return code == XBC_NEUMANN ? ((T)4 * a - b) / (T)3 : (T)2 * a - b;
 }
 
 // ---------------------------------------------------------------------
 // Pseudo-time update of one point (Sec. 3.3): residual of the chosen
-// equation, local time step at stage 0, RK stage combination, walls/solids.
+// equation, local time step at stage 0, RK stage combination, walls/solids;
+// returns the new stage value (the caller stores it).
 template <typename T>
-__device__ void finish_point(const GridDev &g, int stage, int q, bool zero,
-                             T phis, T g2, T lap, T kap, T lads, T S1, T S2)
+__device__ T finish_point(const GridDev &g, int stage, int q, bool zero,
+                          T phis, T g2, T lap, T kap, T lads, T S1, T S2)
 {
-    T *ps = static_cast<T *>(g.ps);
     T *dtp = static_cast<T *>(g.dt);
     const T gm = sqrt(g2);
     T gam = (T)0, nu = (T)0, R;
@@ -408,7 +487,7 @@ __device__ void finish_point(const GridDev &g, int stage, int q, bool zero,
         else
             out = pn / (T)3 + (T)2 / (T)3 * (phis + dt * R);
     }
-    ps[q] = zero ? (T)0 : out;
+    return zero ? (T)0 : out;
 }
 
 template <typename T>
@@ -425,6 +504,31 @@ __device__ inline void metric_sums(const GridDev &g, int q, T &S1, T &S2)
         S1 += sqrt(s2);
         S2 += s2;
     }
+}
+
+// Store a tile's new stage values (last pass of an RK stage), applying
+// the extrapolated faces of this direction inside the tile when the grid
+// keeps all of them here.
+template <typename T>
+__device__ void store_stage(const GridDev &g, const Tile &tl, const Pts &pt, int l,
+                            T (&v)[kPPT], const bool (&zero)[kPPT], T *X)
+{
+    T *ps = static_cast<T *>(g.ps);
+    if (g.fuse_faces) {
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k)
+            if (pvalid(tl, k)) X[threadIdx.x + k * kThreads] = v[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k)
+            if (pvalid(tl, k))
+                v[k] = face_value(g, l, X, threadIdx.x + k * kThreads, pt.J[k], tl.n, tl.lj,
+                                  v[k], zero[k]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kPPT; ++k)
+        if (pvalid(tl, k)) ps[pt.Q[k]] = v[k];
 }
 
 // ---------------------------------------------------------------------
@@ -504,18 +608,21 @@ k_cart(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                 S1 += (T)g.invh[d];
                 S2 += (T)g.invh[d] * (T)g.invh[d];
             }
+            bool zero[kPPT];
 #pragma unroll
             for (int k = 0; k < kPPT; ++k) {
+                zero[k] = true;
                 if (!pvalid(tl, k)) continue;
                 const int q = pt.Q[k];
                 int idx[3];
-                tile_index(g, tl, l, pt.Wl[k], pt.J[k], idx);
-                const bool zero = wall_point(g, idx) || (g.mask && g.mask[q]);
+                tile_index(g, tl, l, k, pt.J[k], idx);
+                zero[k] = wall_point(g, idx) || (g.mask && g.mask[q]);
                 const T g2 = P0[q] + g2c[k];
                 const T lap = g.need_lap ? P1[q] + lapc[k] : (T)0;
                 const T lads = g.lad ? P2[q] : (T)0;
-                finish_point<T>(g, stage, q, zero, v0[k], g2, lap, (T)0, lads, S1, S2);
+                v0[k] = finish_point<T>(g, stage, q, zero[k], v0[k], g2, lap, (T)0, lads, S1, S2);
             }
+            store_stage(g, tl, pt, l, v0, zero, A);
         }
     }
 }
@@ -562,10 +669,16 @@ template <typename T>
 __device__ inline void grad_at(const GridDev &g, int q, T *U, T &g2)
 {
     g2 = (T)0;
-    for (int m = 0; m < g.ndim; ++m) {
+    U[2] = (T)0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        if (m >= g.ndim) break;
         T u = (T)0;
-        for (int l = 0; l < g.ndim; ++l)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            if (l >= g.ndim) break;
             u += metric<T>(g, l, m, q) * static_cast<const T *>(g.F[l])[q];
+        }
         U[m] = u;
         g2 += u * u;
     }
@@ -581,6 +694,7 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
 {
     __shared__ T A[kTileMax];
     __shared__ T B[kTileMax];
+    constexpr int GM = sizeof(T) == 4 ? 4 : 2;   // fields per reduction sweep
     int step, end;
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
@@ -591,72 +705,122 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
         tile_points(tl, l, pt);
         const int per = g.periodic[l];
         const int d = g.ndim;
-        T gg[kPPT], lapc[kPPT], kapc[kPPT];
+        const int P = tl.P;
+        // fields differentiated along l: U_m (and n_m), weighted by xi_{l,m};
+        // field f is coded in bits 3f..3f+2 of `code` (component m, n-flag)
+        int code = 0, nf = 0;
+        for (int f = 0; f < (g.curv ? 2 * d : d); ++f) {
+            const int m = f % d;
+            if (g.uniform && m != l) continue;
+            code |= (m | ((f >= d) << 2)) << (3 * nf);
+            ++nf;
+        }
+        const int G = min(GM, max(1, kTileMax / P));
+        T lapc[kPPT], kapc[kPPT];
 #pragma unroll
         for (int k = 0; k < kPPT; ++k) {
             lapc[k] = (T)0;
             kapc[k] = (T)0;
-            if (pvalid(tl, k)) {
-                T U[3];
-                grad_at<T>(g, pt.Q[k], U, gg[k]);
-            }
         }
-        const int nf = g.curv ? 2 * d : d;
-        for (int f = 0; f < nf; ++f) {
-            const int m = f % d;
-            const bool isn = f >= d;
-            if (g.uniform && m != l) continue;
-            T v[kPPT];
-#pragma unroll
-            for (int k = 0; k < kPPT; ++k)
-                if (pvalid(tl, k)) {
-                    const int q = pt.Q[k];
-                    T u = (T)0;
-                    for (int l2 = 0; l2 < d; ++l2)
-                        u += metric<T>(g, l2, m, q) * static_cast<const T *>(g.F[l2])[q];
-                    A[threadIdx.x + k * kThreads] =
-                        isn ? u / (sqrt(gg[k]) + (T)g.eps0) : u;
+        for (int f0 = 0; f0 < nf; f0 += G) {
+            const int gcount = min(G, nf - f0);
+            // field values of this group into B, point by point
+#pragma unroll 1
+            for (int k = 0; k < kPPT; ++k) {
+                if (!pvalid(tl, k)) break;
+                const int q = pt.Q[k];
+                T U[3], g2;
+                grad_at<T>(g, q, U, g2);
+                const T inv = (T)1 / (sqrt(g2) + (T)g.eps0);
+                for (int f = 0; f < gcount; ++f) {
+                    const int c = code >> (3 * (f0 + f));
+                    const int m = c & 3;
+                    const T u = m == 0 ? U[0] : (m == 1 ? U[1] : U[2]);
+                    B[f * P + threadIdx.x + k * kThreads] = (c & 4) ? u * inv : u;
+                }
+            }
+            __syncthreads();
+            // right-hand sides from B into A
+            for (int f = 0; f < gcount; ++f)
+#pragma unroll 1
+                for (int k = 0; k < kPPT; ++k) {
+                    if (!pvalid(tl, k)) break;
+                    const int p = threadIdx.x + k * kThreads;
+                    A[f * P + p] = deriv_rhs(g, B + f * P, p, pt.J[k], tl.n, tl.lj, per, (T)0);
                 }
             __syncthreads();
+            T v[GM][kPPT];
+            pcr_multi<T, GM>(v, gcount, pt, tl, g.dop[l], A, B, true);
 #pragma unroll
-            for (int k = 0; k < kPPT; ++k)
-                if (pvalid(tl, k))
-                    v[k] = deriv_rhs(g, A, threadIdx.x + k * kThreads, pt.J[k], tl.n,
-                                     tl.lj, per, (T)0);
-            __syncthreads();
-            pcr_solve(v, pt, tl, g.dop[l], A, B);
+            for (int f = 0; f < GM; ++f) {
+                if (f >= gcount) break;
+                const int c = code >> (3 * (f0 + f));
+                const int m = c & 3;
+                const bool isn = (c & 4) != 0;
 #pragma unroll
-            for (int k = 0; k < kPPT; ++k) {
-                if (!pvalid(tl, k)) continue;
-                const T wgt = metric<T>(g, l, m, pt.Q[k]);
-                if (isn) kapc[k] += wgt * v[k];
-                else lapc[k] += wgt * v[k];
+                for (int k = 0; k < kPPT; ++k) {
+                    if (!pvalid(tl, k)) continue;
+                    const T wgt = metric<T>(g, l, m, pt.Q[k]);
+                    if (isn) kapc[k] += wgt * v[f][k];
+                    else lapc[k] += wgt * v[f][k];
+                }
             }
         }
         T *P0 = static_cast<T *>(g.P[0]);
         T *P1 = static_cast<T *>(g.P[1]);
         T *P2 = static_cast<T *>(g.P[2]);
         const bool last = l == d - 1;
+        if (!last) {
 #pragma unroll
-        for (int k = 0; k < kPPT; ++k) {
-            if (!pvalid(tl, k)) continue;
-            const int q = pt.Q[k];
-            if (!last) {
+            for (int k = 0; k < kPPT; ++k) {
+                if (!pvalid(tl, k)) continue;
+                const int q = pt.Q[k];
                 P0[q] = l == 0 ? lapc[k] : P0[q] + lapc[k];
                 if (g.curv) P1[q] = l == 0 ? kapc[k] : P1[q] + kapc[k];
-            } else {
-                const T lap = l == 0 ? lapc[k] : P0[q] + lapc[k];
-                const T kap = g.curv ? (l == 0 ? kapc[k] : P1[q] + kapc[k]) : (T)0;
-                const T lads = g.lad ? P2[q] : (T)0;
-                int idx[3];
-                tile_index(g, tl, l, pt.Wl[k], pt.J[k], idx);
-                const bool zero = wall_point(g, idx) || (g.mask && g.mask[q]);
-                const T phis = static_cast<const T *>(stage == 0 ? g.phi : g.ps)[q];
-                T S1, S2;
-                metric_sums<T>(g, q, S1, S2);
-                finish_point<T>(g, stage, q, zero, phis, gg[k], lap, kap, lads, S1, S2);
+            }
+            continue;
+        }
+        // park the partial sums in LDS (own points only) and finish the
+        // stage point by point, keeping the unrolled state small
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k)
+            if (pvalid(tl, k)) {
+                A[threadIdx.x + k * kThreads] = lapc[k];
+                B[threadIdx.x + k * kThreads] = kapc[k];
+            }
+        T *ps = static_cast<T *>(g.ps);
+        const T *src = static_cast<const T *>(stage == 0 ? g.phi : g.ps);
+#pragma unroll 1
+        for (int k = 0; k < kPPT; ++k) {
+            if (!pvalid(tl, k)) break;
+            const int p = threadIdx.x + k * kThreads;
+            const int q = pt.Q[k];
+            const int j = pt.J[k];
+            const T lap = l == 0 ? A[p] : P0[q] + A[p];
+            const T kap = g.curv ? (l == 0 ? B[p] : P1[q] + B[p]) : (T)0;
+            const T lads = g.lad ? P2[q] : (T)0;
+            int idx[3];
+            tile_index(g, tl, l, k, j, idx);
+            const bool zero = wall_point(g, idx) || (g.mask && g.mask[q]);
+            T U[3], g2;
+            grad_at<T>(g, q, U, g2);
+            T S1, S2;
+            metric_sums<T>(g, q, S1, S2);
+            const T nv = finish_point<T>(g, stage, q, zero, src[q], g2, lap, kap, lads, S1, S2);
+            B[p] = zero ? (T)1 : (T)0;   // wall flag for the face step
+            A[p] = nv;
+            if (!g.fuse_faces) ps[q] = nv;
+        }
+        if (g.fuse_faces) {
+            __syncthreads();
+#pragma unroll 1
+            for (int k = 0; k < kPPT; ++k) {
+                if (!pvalid(tl, k)) break;
+                const int p = threadIdx.x + k * kThreads;
+                ps[pt.Q[k]] = face_value(g, l, A, p, pt.J[k], tl.n, tl.lj, A[p], B[p] != (T)0);
             }
         }
+        __syncthreads();
     }
 }
 
@@ -746,7 +910,8 @@ k_final(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             const T phis = static_cast<const T *>(stage == 0 ? g.phi : g.ps)[q];
             T S1, S2;
             metric_sums<T>(g, q, S1, S2);
-            finish_point<T>(g, stage, q, zero, phis, g2, (T)0, (T)0, (T)0, S1, S2);
+            static_cast<T *>(g.ps)[q] =
+                finish_point<T>(g, stage, q, zero, phis, g2, (T)0, (T)0, (T)0, S1, S2);
         }
     }
 }
@@ -824,14 +989,33 @@ k_filter(const GridDev *__restrict__ grids, const Item *__restrict__ items,
         }
         T *phi = static_cast<T *>(g.phi);
         double mx = 0.0, sm = 0.0;
+        bool zr[kPPT];
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k) {
+            zr[k] = true;
+            if (!pvalid(tl, k)) continue;
+            int idx[3];
+            tile_index(g, tl, l, k, pt.J[k], idx);
+            zr[k] = wall_point(g, idx) || (g.mask && g.mask[pt.Q[k]]);
+            v0[k] = zr[k] ? (T)0 : v0[k] + r[k];
+        }
+        if (g.fuse_faces) {
+#pragma unroll
+            for (int k = 0; k < kPPT; ++k)
+                if (pvalid(tl, k)) A[threadIdx.x + k * kThreads] = v0[k];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kPPT; ++k)
+                if (pvalid(tl, k))
+                    v0[k] = face_value(g, l, A, threadIdx.x + k * kThreads, pt.J[k], tl.n, tl.lj,
+                                       v0[k], zr[k]);
+            __syncthreads();
+        }
 #pragma unroll
         for (int k = 0; k < kPPT; ++k) {
             if (!pvalid(tl, k)) continue;
             const int q = pt.Q[k];
-            int idx[3];
-            tile_index(g, tl, l, pt.Wl[k], pt.J[k], idx);
-            const bool zero = wall_point(g, idx) || (g.mask && g.mask[q]);
-            const T nv = zero ? (T)0 : v0[k] + r[k];
+            const T nv = v0[k];
             if (g.fused_resid) {
                 const double e = fabs((double)nv - (double)phi[q]);
                 mx = nanmax(mx, e);
