@@ -136,6 +136,155 @@ def run_cpu_baseline(spec, kw, sample_iters):
     return spec.npoints * sample_iters / dt, dt
 
 
+def method_for(spec, scheme, prec, **over):
+    from paper_2111_09859_amd import api
+    kw = dict(equation="HJ", gamma="LAD", eps=0.2, scheme=scheme, rk="RK4",
+              curvature=spec.coords is not None, precision=prec)
+    if prec == "fp32":
+        kw.update(tol=1e-6, stall_window=1000, max_iter=20000)
+    else:
+        kw.update(tol=1e-10, stall_window=2000, max_iter=20000)
+    kw.update(over)
+    return api.make_method(**kw)
+
+
+def run_batch(args):
+    """Config 4: 64 seeded 2D grids (channel / cylinder / ellipse O-grids,
+    E6 / C6, LAD pseudo-HJ + curvature on O-grids) solved as ONE FP32 batch
+    versus the same grids solved one at a time in FP64."""
+    import torch
+    from paper_2111_09859_amd import api, grids as G
+    mix = G.batch_mix(args.batch_count)
+    s = api.Solver(0)
+    p32 = [s.prepare(spec, sch, "fp32") for spec, sch in mix]
+    m32 = [method_for(spec, sch, "fp32") for spec, sch in mix]
+    # warm-up: tile autotuning per distinct shape (cached in the context)
+    seen = set()
+    for p, m in zip(p32, m32):
+        key = p.spec.n
+        if key not in seen:
+            seen.add(key)
+            s.autotune(p, m, iters=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = s.solve_batched(p32, m32, check=False)
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
+    e32 = [float(np.abs(ph.double().cpu().numpy() - sp.exact).max()) for ph, (sp, _) in zip(out["phi"], mix)]
+    t64, e64, it64, st64 = 0.0, [], [], []
+    for spec, sch in mix:
+        p = s.prepare(spec, sch, "fp64")
+        m = method_for(spec, sch, "fp64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve(p, m, check=False)
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t0
+        e64.append(float(np.abs(r["phi"].cpu().numpy() - spec.exact).max()))
+        it64.append(r["iters"])
+        st64.append(r["status"])
+    pts = sum(sp.npoints for sp, _ in mix)
+    # "same stated accuracy": both runs finished (no divergence) and their
+    # L-inf errors against the exact distance agree within 1 %
+    ok = [i for i in range(len(mix)) if out["status"][i] >= 0 and st64[i] >= 0
+          and abs(e32[i] - e64[i]) <= 0.01 * max(e64[i], 1e-12)]
+    return {
+        "metric": "solves/s (FP32 batched)", "value": len(mix) / t32, "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * t32,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(mix)} seeded 2D grids (channel/cylinder/ellipse, E6/C6, "
+                               "LAD pseudo-HJ + curvature on O-grids), 65x33..1025x513",
+                   "points": pts, "batched_fp32_s": t32, "plain_fp64_s": t64,
+                   "plain_fp64_solves_per_s": len(mix) / t64,
+                   "speedup_fp32_batched_vs_fp64_plain": t64 / t32,
+                   "fp32_iters": out["iters"], "fp64_iters": it64,
+                   "fp32_status": out["status"], "fp64_status": st64,
+                   "linf_err_fp32": e32, "linf_err_fp64": e64,
+                   "grids_same_accuracy": len(ok),
+                   "linf_err_median_same_accuracy": float(np.median([e64[i] for i in ok])) if ok else None}}
+
+
+def run_serve(args):
+    """Config 5 (bounded sample): open-loop Poisson arrivals (200 req/s) of
+    2D grids 129^2..2049^2 and 3D ducts 64^3..192^3 into the continuous-
+    batching server, beside 4 closed-loop warm-started star-grain sessions.
+    FP32, LAD pseudo-HJ, stop at max change <= 1e-5 (the paper's criterion)."""
+    import threading
+    import torch
+    from paper_2111_09859_amd import api, grids as G
+    s = api.Solver(0)
+    srv = api.Server(s, budget_bytes=args.serve_budget << 20, max_slots=64)
+    stream = G.serving_stream(count=args.serve_count)
+    over = dict(tol=1e-5, stall_window=500, max_iter=20000)
+    ids = []
+    sess_lat = []
+
+    def sessions():
+        ss = api.Solver(0)
+        phis = {}
+        for k in range(args.serve_steps):
+            rids = []
+            for sid in range(4):
+                spec = G.star_grain(512, step=k + 5 * sid)
+                p = ss.prepare(spec, "E6", "fp32")
+                if sid not in phis:
+                    phis[sid] = torch.zeros(spec.shape, dtype=torch.float32, device=ss.device)
+                m = method_for(spec, "E6", "fp32", eps=0.15, warm_start=k > 0, **over)
+                rids.append((srv.submit(p, m, phi=phis[sid], session=100 + sid), p))
+            for rid, p in rids:
+                srv.wait(rid, 600.0)
+                info = srv.poll(rid)
+                sess_lat.append((info["t_done"] - info["t_submit"], info["iters"], k))
+        ss.close()
+
+    th = threading.Thread(target=sessions)
+    t0 = time.perf_counter()
+    th.start()
+    for req in stream:
+        delay = req["t"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        spec = G.build_request(req)
+        p = s.prepare(spec, req["scheme"], "fp32")
+        ids.append((srv.submit(p, method_for(spec, req["scheme"], "fp32", **over)), spec))
+    for rid, _ in ids:
+        srv.wait(rid, 1200.0)
+    th.join()
+    wall = time.perf_counter() - t0
+    lat, qwait, its, pts = [], [], [], 0
+    for rid, spec in ids:
+        info = srv.poll(rid)
+        lat.append(info["t_done"] - info["t_submit"])
+        qwait.append(info["t_admit"] - info["t_submit"])
+        its.append(info["iters"])
+        pts += spec.npoints * info["iters"]
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    cold = [l for l, it, k in sess_lat if k == 0]
+    warm = [l for l, it, k in sess_lat if k > 0]
+    warm_it = [it for l, it, k in sess_lat if k > 0]
+    cold_it = [it for l, it, k in sess_lat if k == 0]
+    n = len(ids) + len(sess_lat)
+    return {
+        "metric": "served solves/s", "value": n / wall, "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": 1e3 * wall, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(ids)} Poisson-arrival requests (200/s) + 4 warm-started "
+                               f"star-grain sessions x {args.serve_steps} steps",
+                   "p50_latency_s": float(np.percentile(lat, 50)),
+                   "p99_latency_s": float(np.percentile(lat, 99)),
+                   "p50_queue_wait_s": float(np.percentile(qwait, 50)),
+                   "point_updates_per_s": pts / wall,
+                   "session_cold_latency_s": float(np.mean(cold)) if cold else None,
+                   "session_warm_latency_s": float(np.mean(warm)) if warm else None,
+                   "session_cold_iters": float(np.mean(cold_it)) if cold_it else None,
+                   "session_warm_iters": float(np.mean(warm_it)) if warm_it else None,
+                   "peak_arena_bytes": st["peak_bytes"], "peak_active": st["peak_active"],
+                   "budget_bytes": args.serve_budget << 20}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,12 +299,22 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="no per-kernel event timing (roofline is then null)")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--serve-count", type=int, default=200)
+    ap.add_argument("--serve-steps", type=int, default=10)
+    ap.add_argument("--serve-budget", type=int, default=4096, help="arena MiB")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(grids are independent; see the multi-GPU design notes)", file=sys.stderr)
         raise SystemExit(2)
 
+    if args.workload == "batch":
+        print(json.dumps(run_batch(args)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args)), flush=True)
+        return
     spec, kw, desc = workload(args.workload)
     r = run_gpu(args, spec, kw, args.precision, profile=not args.no_profile)
     ups = spec.npoints * r["iters"] / r["time"]

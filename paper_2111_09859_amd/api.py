@@ -183,7 +183,8 @@ class Server:
         torch = self.solver.torch
         if phi is None:
             phi = torch.zeros(prep.spec.shape, dtype=prep.dtype, device=self.solver.device)
-        torch.cuda.synchronize(self.solver.device)   # phi must be ready before the server reads it
+        # phi (and the grid's metrics) must be ready before the server reads them
+        torch.cuda.current_stream(self.solver.device).synchronize()
         rid = L.wd_server_submit(self.srv, prep.desc, method, C.c_void_p(phi.data_ptr()),
                                  session, hist_cap)
         self._keep[rid] = (prep, phi)

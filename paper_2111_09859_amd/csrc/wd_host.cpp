@@ -874,7 +874,9 @@ CachedGraph *graph_for(wd_ctx *ctx, const Plan &P, int K)
         }
     prof_collect(ctx);
     hipStream_t s = ctx->stream;
-    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    // relaxed: other threads (the caller's, a server's) keep full use of
+    // the runtime while this context's stream is being captured
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
         fail(WD_ERR_HIP, "hipStreamBeginCapture failed");
         return nullptr;
     }

@@ -225,13 +225,11 @@ static int run_group(wd_server *srv, const std::vector<long long> &ids, bool sam
     if (rc) return rc;
     launch_mirror(P.d_grids, P.n, s);
     issue_init(ctx, P, s);
+    // direct launches: the set changes at round boundaries and capture would
+    // serialise with the clients' runtime calls
     const int K = srv->round_iters;
-    CachedGraph *cg = (same_set && ctx->use_graphs) ? graph_for(ctx, P, K) : nullptr;
-    if (cg) {
-        if (hipGraphLaunch(cg->exec, s) != hipSuccess) return fail(WD_ERR_HIP, "hipGraphLaunch failed");
-    } else {
-        for (int k = 0; k < K; ++k) issue_iteration(ctx, P, s);
-    }
+    (void)same_set;
+    for (int k = 0; k < K; ++k) issue_iteration(ctx, P, s);
     if (hipMemcpyAsync(ctx->pinned_states, P.d_states, P.n * sizeof(GridState),
                        hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
