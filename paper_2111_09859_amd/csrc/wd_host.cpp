@@ -553,90 +553,102 @@ int plan_batch(wd_ctx *ctx, int n, const wd_grid_desc *descs, const wd_method *m
     return plan_tables(P, ws, tb, items_cap);
 }
 
-// work lists in launch order
+// points-per-thread variant of grid g's tiles along direction l
+int tile_np(const GridDev &g, int l)
+{
+    const long long pts = (long long)g.tw[l] * g.n[l];
+    int np = 1;
+    while (np < 8 && (long long)kThreads * np < pts) np *= 2;
+    return np;
+}
+
+// work lists in launch order; a line pass gets one list per tile variant
+// present among its grids
 void build_items(Plan &P)
 {
     P.items.clear();
     P.lists.clear();
-    auto list = [&](int kind, int l, int stage_arg) -> ItemList & {
+    const int n = P.n;
+    auto add_list = [&](int kind, int l, int arg, int np) {
         ItemList L;
         L.kind = kind;
         L.l = l;
-        L.arg = stage_arg;
+        L.arg = arg;
+        L.np = np;
         L.first = (int)P.items.size();
         L.count = 0;
         P.lists.push_back(L);
-        return P.lists.back();
+        return (int)P.lists.size() - 1;
     };
-    auto add_tiles = [&](ItemList &L, int gi, int nt) {
-        for (int t = 0; t < nt; ++t) P.items.push_back(Item{gi, t});
-        L.count += nt;
-    };
-    const int n = P.n;
-    // directional passes
-    for (int l = 0; l < 3; ++l) {
-        ItemList &L = list(PASS_CART, l, 0);
-        for (int i = 0; i < n; ++i)
-            if (P.grids[i].mode == MODE_CART && l < P.grids[i].ndim) add_tiles(L, i, P.grids[i].ntiles[l]);
-        P.cart[l] = (int)P.lists.size() - 1;
-    }
-    for (int l = 0; l < 3; ++l) {
-        ItemList &L = list(PASS_D1, l, 0);
-        for (int i = 0; i < n; ++i)
-            if (P.grids[i].mode == MODE_GENERAL && l < P.grids[i].ndim) add_tiles(L, i, P.grids[i].ntiles[l]);
-        P.d1[l] = (int)P.lists.size() - 1;
-    }
-    for (int l = 0; l < 3; ++l) {
-        ItemList &L = list(PASS_D2, l, 0);
-        for (int i = 0; i < n; ++i)
-            if (P.grids[i].mode == MODE_GENERAL && P.grids[i].need_lap && l < P.grids[i].ndim)
-                add_tiles(L, i, P.grids[i].ntiles[l]);
-        P.d2[l] = (int)P.lists.size() - 1;
-    }
-    {
-        ItemList &L = list(PASS_FINAL, 0, 0);
-        for (int i = 0; i < n; ++i)
-            if (P.grids[i].mode == MODE_GENERAL && !P.grids[i].need_lap) add_tiles(L, i, P.grids[i].nchunks);
-        P.fin = (int)P.lists.size() - 1;
-    }
-    for (int l = 0; l < 3; ++l) {
-        ItemList &L = list(PASS_LAD, l, 0);
-        for (int i = 0; i < n; ++i)
-            if (P.grids[i].lad && l < P.grids[i].ndim) add_tiles(L, i, P.grids[i].ntiles[l]);
-        P.lad[l] = (int)P.lists.size() - 1;
-    }
-    for (int l = 0; l < 3; ++l) {
-        ItemList &L = list(PASS_FILTER, l, 0);
-        for (int i = 0; i < n; ++i)
-            if (P.grids[i].filter && l < P.grids[i].ndim) add_tiles(L, i, P.grids[i].ntiles[l]);
-        P.filt[l] = (int)P.lists.size() - 1;
-    }
-    {
-        ItemList &L = list(PASS_RESID, 0, 0);
-        for (int i = 0; i < n; ++i)
-            if (!P.grids[i].fused_resid) add_tiles(L, i, P.grids[i].nchunks);
-        P.resid = (int)P.lists.size() - 1;
-    }
-    for (int target = 0; target < 2; ++target)
-        for (int f = 0; f < 6; ++f) {
-            ItemList &L = list(PASS_FACE, f, target);
+    // one line pass: tiles of the grids selected by `use`, grouped by variant
+    auto line_slot = [&](Slot &S, int kind, int l, int arg, auto use) {
+        for (int c = 0; c < 4; ++c) {
+            S.list[c] = -1;
+            const int np = 1 << c;
+            int li = -1;
             for (int i = 0; i < n; ++i) {
                 const GridDev &g = P.grids[i];
-                const int l = f >> 1;
-                if (l >= g.ndim || g.xbc[f] == XBC_NONE) continue;
-                if (target == 1 && g.fuse_faces) continue;   // done inside the passes
-                if (target == 0 && !P.host[i].init) continue;
-                const long long nf = g.N / g.n[l];
-                add_tiles(L, i, (int)((nf + kChunk - 1) / kChunk));
+                if (l >= g.ndim || !use(g) || tile_np(g, l) != np) continue;
+                if (li < 0) li = add_list(kind, l, arg, np);
+                for (int t = 0; t < g.ntiles[l]; ++t) P.items.push_back(Item{i, t});
+                P.lists[li].count += g.ntiles[l];
             }
-            (target ? P.face : P.face_init)[f] = (int)P.lists.size() - 1;
+            S.list[c] = li;
         }
-    {
-        ItemList &L = list(PASS_INIT, 0, 0);
-        for (int i = 0; i < n; ++i)
-            if (P.host[i].init) add_tiles(L, i, P.grids[i].nchunks);
-        P.init = (int)P.lists.size() - 1;
-    }
+    };
+    auto point_list = [&](int kind, int l, int arg, auto count) {
+        const int li = add_list(kind, l, arg, 1);
+        for (int i = 0; i < n; ++i) {
+            const int nt = count(i);
+            for (int t = 0; t < nt; ++t) P.items.push_back(Item{i, t});
+            P.lists[li].count += nt;
+        }
+        return li;
+    };
+    auto cart = [](const GridDev &g) { return g.mode == MODE_CART; };
+    auto gen_lap = [](const GridDev &g) { return g.mode == MODE_GENERAL && g.need_lap; };
+    auto gen_eik = [](const GridDev &g) { return g.mode == MODE_GENERAL && !g.need_lap; };
+    auto gen = [](const GridDev &g) { return g.mode == MODE_GENERAL; };
+    for (int l = 0; l < 3; ++l) line_slot(P.cart[l], PASS_CART, l, 0, cart);
+    // general grids: F_l for l >= 1 first (all l for the Eikonal), then the
+    // fused pass along 0, then pass 2 along l >= 1 (the last one finishes)
+    line_slot(P.d1[0], PASS_D1, 0, 0, gen_eik);
+    for (int l = 1; l < 3; ++l) line_slot(P.d1[l], PASS_D1, l, 0, gen);
+    line_slot(P.d12, PASS_D12, 0, 0, gen_lap);
+    P.d2[0] = Slot();
+    for (int l = 1; l < 3; ++l) line_slot(P.d2[l], PASS_D2, l, 0, gen_lap);
+    P.fin = point_list(PASS_FINAL, 0, 0, [&](int i) {
+        return gen_eik(P.grids[i]) ? P.grids[i].nchunks : 0;
+    });
+    // LAD: sensor per direction (the last also smooths along itself), then
+    // smoothing along the other directions
+    for (int l = 0; l < 3; ++l)
+        line_slot(P.lad0[l], PASS_LAD, l, 0, [](const GridDev &g) { return g.lad != 0; });
+    for (int l = 0; l < 3; ++l)
+        line_slot(P.lad1[l], PASS_LAD, l, 1, [l](const GridDev &g) {
+            return g.lad != 0 && l < g.ndim - 1;
+        });
+    for (int l = 0; l < 3; ++l)
+        line_slot(P.filt[l], PASS_FILTER, l, 0, [](const GridDev &g) { return g.filter != 0; });
+    P.resid = point_list(PASS_RESID, 0, 0, [&](int i) {
+        return P.grids[i].fused_resid ? 0 : P.grids[i].nchunks;
+    });
+    for (int target = 0; target < 2; ++target)
+        for (int f = 0; f < 6; ++f) {
+            const int li = point_list(PASS_FACE, f, target, [&](int i) {
+                const GridDev &g = P.grids[i];
+                const int l = f >> 1;
+                if (l >= g.ndim || g.xbc[f] == XBC_NONE) return 0;
+                if (target == 1 && g.fuse_faces) return 0;   // done inside the passes
+                if (target == 0 && !P.host[i].init) return 0;
+                const long long nf = g.N / g.n[l];
+                return (int)((nf + kChunk - 1) / kChunk);
+            });
+            (target ? P.face : P.face_init)[f] = li;
+        }
+    P.init = point_list(PASS_INIT, 0, 0, [&](int i) {
+        return P.host[i].init ? P.grids[i].nchunks : 0;
+    });
 }
 
 // ---------------------------------------------------------------------
@@ -647,6 +659,7 @@ static const char *kind_name(int kind)
     case PASS_CART: return "k_cart";
     case PASS_D1: return "k_d1";
     case PASS_D2: return "k_d2";
+    case PASS_D12: return "k_d12";
     case PASS_FILTER: return "k_filter";
     case PASS_FINAL: return "k_final";
     case PASS_RESID: return "k_resid";
@@ -696,6 +709,9 @@ static double point_accesses(const GridDev &g, int kind, int l, int stage)
         else a += finish(0);
         return a;
     }
+    case PASS_D12:
+        // phi in, F_0 out, the other F and the metrics in, partial sums out
+        return 2 + (d - 1) + met + (1 + g.curv);
     case PASS_FINAL:
         return d + met + finish(0);
     case PASS_FILTER:
@@ -789,9 +805,15 @@ void issue_list(wd_ctx *ctx, const Plan &P, int li, int stage, hipStream_t s)
     const int arg = (L.kind == PASS_FACE || L.kind == PASS_INIT) ? L.arg : stage;
     PendingLaunch pl;
     if (ctx->profile) prof_begin(ctx, pl, kind_name(L.kind), launch_bytes(P, L, stage), s);
-    launch_pass(L.kind, P.fp64, P.d_grids, P.d_items + L.first, L.count, L.l, arg,
+    launch_pass(L.kind, P.fp64, L.np, P.d_grids, P.d_items + L.first, L.count, L.l, arg,
                 nwg_for(ctx, P.fp64, L.count), s);
     if (ctx->profile) prof_end(ctx, pl, s);
+}
+
+void issue_slot(wd_ctx *ctx, const Plan &P, const Slot &S, int stage, hipStream_t s)
+{
+    for (int c = 0; c < 4; ++c)
+        if (S.list[c] >= 0) issue_list(ctx, P, S.list[c], stage, s);
 }
 
 void issue_faces(wd_ctx *ctx, const Plan &P, int target, hipStream_t s)
@@ -801,7 +823,7 @@ void issue_faces(wd_ctx *ctx, const Plan &P, int target, hipStream_t s)
         if (L.count == 0) continue;
         PendingLaunch pl;
         if (ctx->profile) prof_begin(ctx, pl, "k_face", 0.0, s);
-        launch_pass(PASS_FACE, P.fp64, P.d_grids, P.d_items + L.first, L.count, f, target,
+        launch_pass(PASS_FACE, P.fp64, 1, P.d_grids, P.d_items + L.first, L.count, f, target,
                     nwg_for(ctx, P.fp64, L.count), s);
         if (ctx->profile) prof_end(ctx, pl, s);
     }
@@ -809,19 +831,19 @@ void issue_faces(wd_ctx *ctx, const Plan &P, int target, hipStream_t s)
 
 void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s)
 {
-    // LAD diffusivity from phi^n: sensor, then smoothing, per direction
-    for (int mode = 0; mode < 2; ++mode)
-        for (int l = 0; l < P.maxdim; ++l) issue_list(ctx, P, P.lad[l], mode, s);
+    // LAD diffusivity from phi^n: sensor per direction (the last one also
+    // smooths along itself), then smoothing along the other directions
+    for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.lad0[l], 0, s);
+    for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.lad1[l], 1, s);
     for (int st = 0; st < P.stages; ++st) {
-        for (int l = 0; l < P.maxdim; ++l) {
-            issue_list(ctx, P, P.cart[l], st, s);
-            issue_list(ctx, P, P.d1[l], st, s);
-        }
-        for (int l = 0; l < P.maxdim; ++l) issue_list(ctx, P, P.d2[l], st, s);
+        for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.cart[l], st, s);
+        for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.d1[l], st, s);
+        issue_slot(ctx, P, P.d12, st, s);
+        for (int l = 1; l < P.maxdim; ++l) issue_slot(ctx, P, P.d2[l], st, s);
         issue_list(ctx, P, P.fin, st, s);
         issue_faces(ctx, P, 1, s);
     }
-    for (int l = 0; l < P.maxdim; ++l) issue_list(ctx, P, P.filt[l], 0, s);
+    for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.filt[l], 0, s);
     issue_faces(ctx, P, 1, s);
     issue_list(ctx, P, P.resid, 0, s);
     PendingLaunch pl;
@@ -1013,7 +1035,7 @@ int poisson_convert(wd_ctx *ctx, const Plan &P, int i, void *aux, hipStream_t s)
             return fail(WD_ERR_INVALID_ARG, "internal: no item space for the Poisson passes");
         if (hipMemcpyAsync(d_it, it.data(), nt * sizeof(Item), hipMemcpyHostToDevice, s) != hipSuccess)
             return fail(WD_ERR_HIP, "poisson items upload failed");
-        launch_pass(PASS_D1, 1, P.d_aux, d_it, nt, l, 0, nwg_for(ctx, 1, nt), s);
+        launch_pass(PASS_D1, 1, tile_np(g, l), P.d_aux, d_it, nt, l, 0, nwg_for(ctx, 1, nt), s);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(WD_ERR_HIP, "poisson pass failed");
     }
     GridDev w = g;  // metrics in the solve precision, F in FP64
@@ -1287,7 +1309,8 @@ int wd_compute_metrics(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, const 
                 rc = fail(WD_ERR_HIP, "metric view upload failed");
                 break;
             }
-            launch_pass(PASS_D1, 1, dg, ditems, g.ntiles[l], l, 0, nwg_for(ctx, 1, g.ntiles[l]), s);
+            launch_pass(PASS_D1, 1, tile_np(g, l), dg, ditems, g.ntiles[l], l, 0,
+                        nwg_for(ctx, 1, g.ntiles[l]), s);
             if (hipStreamSynchronize(s) != hipSuccess) rc = fail(WD_ERR_HIP, "metric pass failed");
         }
     }

@@ -55,7 +55,12 @@ struct CachedGraph {
 };
 
 struct ItemList {
-    int kind, l, arg, first, count;
+    int kind, l, arg, np, first, count;
+};
+
+// one line pass: its lists per tile variant (np = 1, 2, 4, 8), -1 if none
+struct Slot {
+    int list[4] = {-1, -1, -1, -1};
 };
 
 // live kernel timing (profiling mode): one record per launch
@@ -83,7 +88,8 @@ struct Plan {
     long long items_cap = 0;
     std::vector<Item> items;
     std::vector<ItemList> lists;
-    int cart[3], d1[3], d2[3], filt[3], face[6], face_init[6], lad[3];
+    Slot cart[3], d1[3], d12, d2[3], filt[3], lad0[3], lad1[3];
+    int face[6], face_init[6];
     int fin = 0, resid = 0, init = 0;
     GridDev *d_grids = nullptr;
     GridDev *d_aux = nullptr, *d_aux2 = nullptr;
@@ -116,6 +122,7 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
 int plan_tables(Plan &P, void *tables, size_t bytes, long long items_cap);
 int plan_batch(wd_ctx *ctx, int n, const wd_grid_desc *descs, const wd_method *meths,
                void *const *phis, void *ws, size_t ws_bytes, Plan &P);
+int tile_np(const GridDev &g, int l);
 void build_items(Plan &P);
 int upload_plan(wd_ctx *ctx, const Plan &P, hipStream_t s);
 void issue_init(wd_ctx *ctx, const Plan &P, hipStream_t s);

@@ -14,13 +14,30 @@ enum PassKind {
     PASS_RESID = 5,   // pointwise pseudo-step change
     PASS_FACE = 6,    // extrapolated face; l = face, stage = target buffer
     PASS_INIT = 7,    // initial field; stage = unused
-    PASS_LAD = 8,     // LAD diffusivity along l; stage = 0 sensor, 1 smoothing
+    PASS_LAD = 8,     // LAD diffusivity along l; stage = phase (0 sensor,
+                      // 1 smoothing)
+    PASS_D12 = 9,     // pass 2 along direction 0 that also forms F_0
 };
 
 // One launch of a pass over `nitems` work items with at most `nwg`
-// workgroups (a persistent loop covers the rest).
-void launch_pass(int kind, int fp64, const GridDev *grids, const Item *items,
+// workgroups (a persistent loop covers the rest).  Line passes run the
+// variant whose tiles hold up to kThreads*np points (np = 1, 2, 4, 8).
+void launch_pass(int kind, int fp64, int np, const GridDev *grids, const Item *items,
                  int nitems, int l, int stage, int nwg, hipStream_t s);
+
+// line-pass launchers, one per value type and points per thread
+#define WD_LINE_LAUNCHER(name)                                                    \
+    void name(int kind, const GridDev *grids, const Item *items, int nitems, int l, \
+              int stage, int nwg, hipStream_t s);
+WD_LINE_LAUNCHER(line_launch_f32_1)
+WD_LINE_LAUNCHER(line_launch_f32_2)
+WD_LINE_LAUNCHER(line_launch_f32_4)
+WD_LINE_LAUNCHER(line_launch_f32_8)
+WD_LINE_LAUNCHER(line_launch_f64_1)
+WD_LINE_LAUNCHER(line_launch_f64_2)
+WD_LINE_LAUNCHER(line_launch_f64_4)
+WD_LINE_LAUNCHER(line_launch_f64_8)
+#undef WD_LINE_LAUNCHER
 void launch_finalize(const GridDev *grids, int ngrids, hipStream_t s);
 void launch_mirror(const GridDev *grids, int ngrids, hipStream_t s);
 void launch_convert(int src_fp64, int dst_fp64, const void *src, void *dst,

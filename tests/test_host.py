@@ -93,3 +93,15 @@ def test_line_reduction_matches_dense(L, n, periodic):
 def test_line_reduction_rejects_bad_sizes(L):
     with pytest.raises(L.WDError):
         L.wd_line_solve_host(0, np.zeros(4), 0, "C6", 0.495, True)
+
+
+def test_tile_quotient_by_reciprocal_is_exact():
+    """The line kernels split an in-tile index a < 2^13 by a line length or
+    band width b <= 4096 as int((a + 1/2) * fl(1/b)) in float32; check that
+    this equals floor(a / b) for every such pair."""
+    a = np.arange(0, 8192, dtype=np.float32)
+    ai = np.arange(0, 8192)
+    for b in range(1, 4097):
+        rb = np.float32(1.0) / np.float32(b)
+        q = ((a + np.float32(0.5)) * rb).astype(np.int64)
+        assert np.array_equal(q, ai // b), b
