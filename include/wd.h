@@ -99,9 +99,11 @@ typedef struct wd_method {
     double tol;           /* stop when max |phi - phi_o| <= tol (Eq.
                              Con-criter, L_ref = 1)                         */
     int max_iter;         /* iteration limit                                */
-    int stall_window;     /* > 0: stop (WD_STAGNATED) when the max change has
-                             not reached a new minimum for this many
-                             iterations; 0 disables                         */
+    int stall_window;     /* > 0: stop (WD_STAGNATED) when the max change,
+                             already within 10 * tol, has not reached a new
+                             minimum for this many iterations (the rounding
+                             floor of FP32); plateaus while the front still
+                             crosses the grid do not count; 0 disables      */
     int precision;        /* wd_precision of fields and arithmetic; the
                              convergence reductions are always FP64         */
     int warm_start;       /* 1: phi holds the initial guess; 0: phi = 0     */
@@ -117,7 +119,7 @@ const char *wd_version(void);
 const char *wd_last_error(void);
 
 /* Fill *m with the defaults: HJ, LAD, no curvature, eps 0.2, C 0.1,
- * nu0 1e-3, eps0 1e-6, C6, filter on, alpha_f 0.495, RK4, sigma 1,
+ * nu0 1e-3, eps0 1e-6, C6, filter on, alpha_f 0.48, RK4, sigma 1,
  * tol 1e-10, max_iter 100000, stall_window 0, FP64, cold start. */
 int wd_method_default(wd_method *m);
 
@@ -184,6 +186,19 @@ int wd_solve_batched(wd_ctx *ctx, int n, const wd_grid_desc *descs,
 int wd_autotune(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method,
                 void *phi, void *ws, size_t ws_bytes, int iters, int *widths,
                 void *stream);
+
+/* The tile widths this context uses for grids of desc's shape at
+ * `precision`: the cached choice (wd_autotune or wd_tune_set) or the
+ * default.  widths: host, receives desc->ndim values.  No device work. */
+int wd_tune_get(wd_ctx *ctx, const wd_grid_desc *desc, int precision, int *widths);
+
+/* Store tile widths for grids of desc's shape at `precision` (for example
+ * a saved autotuning result).  Direction 0 tiles hold widths[0] whole rows
+ * (at most the number of rows); direction l >= 1 tiles hold widths[l]
+ * consecutive x-columns (at most n[0]); every tile must fit 4096 points.
+ * Returns WD_ERR_INVALID_ARG for a width outside these bounds (nothing is
+ * stored then).  No device work. */
+int wd_tune_set(wd_ctx *ctx, const wd_grid_desc *desc, int precision, const int *widths);
 
 /* Eq. Poiss2 on its own: distance = -|grad phi'| + sqrt(|grad phi'|^2 +
  * 2 phi') with the gradient by `scheme` and the metrics, evaluated in FP64.

@@ -83,6 +83,8 @@ def lib():
                               C.POINTER(dp), C.c_int, ip, ip, vp, C.c_size_t, vp], C.c_int),
         "wd_poisson_distance": ([vp, gd, C.c_int, C.c_int, vp, vp, vp, C.c_size_t, vp], C.c_int),
         "wd_autotune": ([vp, gd, me, vp, vp, C.c_size_t, C.c_int, ip, vp], C.c_int),
+        "wd_tune_get": ([vp, gd, C.c_int, ip], C.c_int),
+        "wd_tune_set": ([vp, gd, C.c_int, ip], C.c_int),
         "wd_ctx_profile": ([vp, C.c_int], C.c_int),
         "wd_ctx_profile_read": ([vp, C.POINTER(wd_kernel_stat), C.c_int, ip], C.c_int),
         "wd_line_solve_host": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, dp,
@@ -202,6 +204,17 @@ def wd_autotune(ctx, desc, method, phi_ptr, ws_ptr, ws_bytes, iters=20, stream=N
     _check(lib().wd_autotune(ctx, C.byref(desc), C.byref(method), phi_ptr, ws_ptr, ws_bytes,
                              iters, w, stream), "wd_autotune", ok=(WD_OK,))
     return list(w)[: desc.ndim]
+
+
+def wd_tune_get(ctx, desc, precision):
+    w = (C.c_int * 3)()
+    _check(lib().wd_tune_get(ctx, C.byref(desc), precision, w), "wd_tune_get", ok=(WD_OK,))
+    return list(w)[: desc.ndim]
+
+
+def wd_tune_set(ctx, desc, precision, widths):
+    w = (C.c_int * 3)(*(list(widths) + [1] * (3 - len(widths))))
+    _check(lib().wd_tune_set(ctx, C.byref(desc), precision, w), "wd_tune_set", ok=(WD_OK,))
 
 
 def wd_ctx_profile(ctx, enable: bool) -> None:

@@ -27,7 +27,7 @@ def _torch():
 
 
 def make_method(equation="HJ", gamma="LAD", curvature=False, eps=0.2, c_lad=0.1,
-                nu0=1e-3, eps0=1e-6, scheme="C6", filter=True, alpha_f=0.495, rk="RK4",
+                nu0=1e-3, eps0=1e-6, scheme="C6", filter=True, alpha_f=0.48, rk="RK4",
                 sigma=1.0, tol=1e-10, max_iter=100000, stall_window=0, precision="fp64",
                 warm_start=False) -> L.wd_method:
     m = L.wd_method()
@@ -148,6 +148,16 @@ class Solver:
         ws = self.workspace(L.wd_workspace_bytes(self.ctx, [prep.desc], [method]))
         return L.wd_autotune(self.ctx, prep.desc, method, C.c_void_p(phi.data_ptr()),
                              C.c_void_p(ws.data_ptr()), ws.numel(), iters, self.stream())
+
+    def tiles(self, prep: Prepared):
+        """Tile widths used for this grid's shape and precision."""
+        return L.wd_tune_get(self.ctx, prep.desc, PRECISIONS["fp64" if prep.dtype == self.torch.float64
+                                                             else "fp32"])
+
+    def set_tiles(self, prep: Prepared, widths):
+        """Use these tile widths for this grid's shape and precision."""
+        L.wd_tune_set(self.ctx, prep.desc, PRECISIONS["fp64" if prep.dtype == self.torch.float64
+                                                      else "fp32"], widths)
 
     def solve_batched(self, preps, methods, phis=None, hist_cap=0, check=True):
         torch = self.torch

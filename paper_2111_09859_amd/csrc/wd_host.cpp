@@ -1122,7 +1122,7 @@ int wd_method_default(wd_method *m)
     m->eps0 = 1e-6;
     m->scheme = WD_C6;
     m->filter = 1;
-    m->alpha_f = 0.495;
+    m->alpha_f = 0.48;   // strong end of Sec. 3.4's 0.48-0.495: stable with corners
     m->rk = WD_RK4;
     m->sigma = 1.0;
     m->tol = 1e-10;
@@ -1385,6 +1385,37 @@ int wd_autotune(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method, 
     (void)hipEventDestroy(e1);
     ctx->profile = prof;
     return rc;
+}
+
+int wd_tune_get(wd_ctx *ctx, const wd_grid_desc *desc, int precision, int *widths)
+{
+    if (!ctx || !desc || !widths) return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (precision != WD_FP32 && precision != WD_FP64) return fail(WD_ERR_INVALID_ARG, "bad precision");
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    for (int l = 0; l < desc->ndim; ++l) widths[l] = pick_tile(ctx, *desc, l, precision == WD_FP64);
+    return WD_OK;
+}
+
+int wd_tune_set(wd_ctx *ctx, const wd_grid_desc *desc, int precision, const int *widths)
+{
+    if (!ctx || !desc || !widths) return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (precision != WD_FP32 && precision != WD_FP64) return fail(WD_ERR_INVALID_ARG, "bad precision");
+    const wd_grid_desc &d = *desc;
+    const long long N = npoints(d);
+    for (int l = 0; l < d.ndim; ++l) {
+        const long long w = widths[l];
+        const long long cap = l == 0 ? N / d.n[0] : d.n[0];
+        if (w < 1 || w > cap || w * d.n[l] > kTileMax)
+            return fail(WD_ERR_INVALID_ARG, "tile width %lld out of range for direction %d", w, l);
+    }
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    for (int l = 0; l < d.ndim; ++l)
+        ctx->tune[TuneKey{d.ndim, d.n[0], d.n[1], d.n[2], l, precision == WD_FP64}] = widths[l];
+    return WD_OK;
 }
 
 int wd_ctx_profile(wd_ctx *ctx, int enable)

@@ -197,7 +197,10 @@ k_finalize(const GridDev *__restrict__ grids, int ngrids)
             st.best = mx;
             st.best_iter = nit;
         }
-        if (g.stall > 0 && nit - st.best_iter >= g.stall) {
+        // the stall window is the rounding floor's: it counts only once the
+        // change has come within 10 tol (a moving front keeps the change
+        // level for a long time without being stuck)
+        if (g.stall > 0 && mx <= 10.0 * g.tol && nit - st.best_iter >= g.stall) {
             st.status = 2;
             st.done = 1;
         } else if (nit >= g.max_iter) {

@@ -41,16 +41,21 @@ enum { SCH_E2 = 0, SCH_E4 = 1, SCH_E6 = 2, SCH_C4 = 3, SCH_C6 = 4 };
 
 // ---------------------------------------------------------------------
 // work distribution
+// Workgroups are dealt round-robin to the eight XCDs (workgroup b runs on
+// XCD b mod 8), each with its own L2.  Every XCD gets one contiguous range
+// of the items, so neighbouring tiles -- which share cache lines when a
+// tile holds only a few x-columns -- are fetched into one L2, and its
+// workgroups stride through that range.
 __device__ inline int item_begin(int nitems, int &step, int &end)
 {
     const int b = blockIdx.x, nb = gridDim.x;
-    if (nb >= nitems || nb < 8 || (nb & 7)) {
+    if (nb < 8) {
         step = nb;
         end = nitems;
         return b;
     }
-    // contiguous item range per XCD (workgroups go round-robin to XCDs)
-    const int xcd = b & 7, slot = b >> 3, wpx = nb >> 3;
+    const int xcd = b & 7, slot = b >> 3;
+    const int wpx = (nb - xcd + 7) >> 3;      // workgroups on this XCD
     const int ipx = (nitems + 7) >> 3;
     const int lo = xcd * ipx;
     end = min(nitems, lo + ipx);

@@ -69,7 +69,7 @@ def test_server_results_equal_solo(solver):
             say(f"[server] req {i} {cases[i][0].name} status={st} iters={info['iters']} "
                 f"solo_iters={it} max|diff|={np.abs(a - b).max():.3e}")
             assert st == s0 and info["iters"] == it
-            assert np.array_equal(a, b)
+            assert np.array_equal(a, b, equal_nan=True)
             h = srv.history(rid, 4000)
             assert len(h) == it
         stats = srv.stats()

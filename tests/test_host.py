@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(L):
 def test_version_and_defaults(L):
     assert "gfx950" in L.wd_version()
     m = L.wd_method_default()
-    assert m.equation == L.WD_EQ_HJ and m.scheme == L.WD_C6 and m.alpha_f == 0.495
+    assert m.equation == L.WD_EQ_HJ and m.scheme == L.WD_C6 and m.alpha_f == 0.48
 
 
 def dense_deriv(n, periodic, scheme):
