@@ -620,13 +620,16 @@ void build_items(Plan &P)
     P.fin = point_list(PASS_FINAL, 0, 0, [&](int i) {
         return gen_eik(P.grids[i]) ? P.grids[i].nchunks : 0;
     });
-    // LAD: sensor per direction (the last also smooths along itself), then
-    // smoothing along the other directions
+    // LAD on Cartesian grids: sensor per direction (the last also smooths
+    // along itself), then smoothing along the other directions.  General
+    // grids form the field inside their stage-0 passes.
     for (int l = 0; l < 3; ++l)
-        line_slot(P.lad0[l], PASS_LAD, l, 0, [](const GridDev &g) { return g.lad != 0; });
+        line_slot(P.lad0[l], PASS_LAD, l, 0, [](const GridDev &g) {
+            return g.lad != 0 && g.mode == MODE_CART;
+        });
     for (int l = 0; l < 3; ++l)
         line_slot(P.lad1[l], PASS_LAD, l, 1, [l](const GridDev &g) {
-            return g.lad != 0 && l < g.ndim - 1;
+            return g.lad != 0 && g.mode == MODE_CART && l < g.ndim - 1;
         });
     for (int l = 0; l < 3; ++l)
         line_slot(P.filt[l], PASS_FILTER, l, 0, [](const GridDev &g) { return g.filter != 0; });
@@ -700,18 +703,22 @@ static double point_accesses(const GridDev &g, int kind, int l, int stage)
         return a;
     }
     case PASS_D1:
-        return 2;                                  // phi in, F_l out
+        // phi in, F_l out; at stage 0 of an LAD grid the sensor part:
+        // metrics in, sensor sum in (after the first direction) and out
+        return 2 + ((stage == 0 && g.lad) ? (met / d) + (l > 1 ? 1 : 0) + 1 : 0);
     case PASS_D2: {
         const int np = 1 + g.curv;
         double a = d + met;                        // F and metrics
         if (l > 0) a += np;
         if (!last) a += np;
         else a += finish(0);
+        if (stage == 0 && g.lad) a += last ? 1 : 2;   // LAD field smoothed in place
         return a;
     }
     case PASS_D12:
         // phi in, F_0 out, the other F and the metrics in, partial sums out
-        return 2 + (d - 1) + met + (1 + g.curv);
+        // (+ the LAD sensor sum in and the smoothed field out at stage 0)
+        return 2 + (d - 1) + met + (1 + g.curv) + ((stage == 0 && g.lad) ? 2 : 0);
     case PASS_FINAL:
         return d + met + finish(0);
     case PASS_FILTER:

@@ -381,13 +381,13 @@ __device__ T gauss9(const T *X, int p, int j, int n, int lj, int periodic)
 // ---------------------------------------------------------------------
 // Parallel cyclic reduction with precomputed multipliers.
 //
-// Pcr holds this thread's multipliers of one line operator when the tile
-// is small (NP * sizeof(T) <= 8 bytes): the pair of every level and the
-// final scale, loaded when the tile starts, so the reduction never waits
-// on memory.  Larger tiles hold only the level in use (the next one is
-// loaded while the current one is applied).  Periodic (circulant) lines
-// use per-level scalars and need none.
-template <typename T, int NP, bool ALL = (NP * sizeof(T) <= 8)>
+// Pcr holds this thread's multipliers of one line operator when the
+// thread has one point: the pair of every level and the final scale,
+// loaded when the tile starts, so the reduction never waits on memory.
+// With more points only the level in use is held (the next one is loaded
+// while the current one is applied).  Periodic (circulant) lines use
+// per-level scalars and need none.
+template <typename T, int NP, bool ALL = (NP == 1)>
 struct Pcr {
     using T2 = typename V2<T>::t;
     static constexpr bool kAll = true;
@@ -705,6 +705,20 @@ __device__ inline void grad_from(int d, const T *m, const T *F, T *U, T &g2)
     }
 }
 
+// |grad xi_l| at point q (the LAD sensor's metric factor)
+template <typename T>
+__device__ inline T grad_xi(const GridDev &g, int l, int q)
+{
+    T s2 = (T)0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+        if (m < g.ndim) {
+            const T e = metric<T>(g, l, m, q);
+            s2 += e * e;
+        }
+    return sqrt(s2);
+}
+
 // a[i] for a runtime i in 0..2 without indexing a register array
 template <typename T>
 __device__ inline T sel3(const T *a, int i)
@@ -849,7 +863,10 @@ k_cart(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     }
 }
 
-// General pass 1 along direction l: F_l = D_l phi.
+// General pass 1 along direction l: F_l = D_l phi.  At stage 0 of an LAD
+// grid it also adds this direction's part of the LAD sensor of phi^n
+// (Eq. Gamma_form2), |grad xi_l| d4_l phi, to the sensor field; the first
+// such direction (l = 1) starts the sum.
 template <typename T, int NP>
 __global__ void __launch_bounds__(kThreads)
 k_d1(const GridDev *__restrict__ grids, const Item *__restrict__ items,
@@ -880,6 +897,17 @@ k_d1(const GridDev *__restrict__ grids, const Item *__restrict__ items,
         for (int k = 0; k < NP; ++k)
             if (pvalid(tl, k))
                 r[k] = deriv_rhs(g, A, threadIdx.x + k * kThreads, pt.J[k], tl.n, tl.lj, per, jump);
+        if (stage == 0 && g.lad) {
+            T *S = static_cast<T *>(g.P[2]);
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                if (!pvalid(tl, k)) continue;
+                const int q = pt.Q[k];
+                const T t = grad_xi<T>(g, l, q) *
+                            fourth_diff(A, threadIdx.x + k * kThreads, pt.J[k], tl.n, tl.lj, per);
+                S[q] = l == 1 ? t : S[q] + t;
+            }
+        }
         __syncthreads();
         pcr_solve<T, NP>(r, pt, tl, g.dop[l], pc, A, B);
         T *F = static_cast<T *>(g.F[l]);
@@ -894,6 +922,10 @@ k_d1(const GridDev *__restrict__ grids, const Item *__restrict__ items,
 // Ham_Jac_trans and kappa = div n.  Direction 0 runs first and, with
 // FUSED, also computes F_0 = D_0 phi in the same tile (its line is already
 // there) before forming U; the last direction finishes the stage.
+// At stage 0 of an LAD grid these passes also complete the LAD diffusivity
+// of phi^n: direction 0 adds its sensor part, takes C |S| and smooths it
+// along 0; every later direction smooths it along itself (the nine-point
+// truncated Gaussian, directions in order), the last one before using it.
 template <typename T, int NP, bool FUSED>
 __global__ void __launch_bounds__(kThreads)
 k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
@@ -943,6 +975,8 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
         T pl[NP], pk[NP], plad[NP];
         bool zr[NP];
         FinIn<T> fin[kPre ? NP : 1];
+        const bool ladst = stage == 0 && g.lad;   // this pass updates the LAD field
+        T *Sl = static_cast<T *>(g.P[2]);
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             zr[k] = true;
@@ -956,12 +990,30 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                 metric_load<T>(g, q, Mv[k]);
                 pl[k] = l > 0 ? P0[q] : (T)0;
                 pk[k] = (l > 0 && g.curv) ? P1[q] : (T)0;
+                if (last || ladst) plad[k] = g.lad ? P2[q] : (T)0;
                 if (last) {
-                    plad[k] = g.lad ? P2[q] : (T)0;
                     zr[k] = zero_point(g, tl, l, pt, k);
                     fin[k] = fin_load<T>(g, stage, q, sv[k]);
                 }
             }
+        }
+        if (ladst && !FUSED) {
+            // smooth the LAD field along l (tile lines) before it is used
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                if (pvalid(tl, k)) {
+                    if constexpr (kPre) A[threadIdx.x + k * kThreads] = plad[k];
+                    else A[threadIdx.x + k * kThreads] = P2[pt.Q[k]];
+                }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                if (!pvalid(tl, k)) continue;
+                const T sm = gauss9(A, threadIdx.x + k * kThreads, pt.J[k], tl.n, tl.lj, per);
+                Sl[pt.Q[k]] = sm;
+                plad[k] = sm;
+            }
+            // A is next written after the barrier that follows the field phase
         }
         if constexpr (FUSED) {
             // F_l = D_l phi on the tile's lines
@@ -973,14 +1025,40 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                 }
             __syncthreads();
             const T jump = (T)g.jump[l];
-            T fl[NP];
+            T fl[NP], lv[NP];
 #pragma unroll
             for (int k = 0; k < NP; ++k)
                 if (pvalid(tl, k))
                     fl[k] = deriv_rhs(g, A, threadIdx.x + k * kThreads, pt.J[k], tl.n, tl.lj,
                                       per, jump);
+            if (ladst) {
+                // sensor part of direction 0 added to the others, then C |S|
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    if (!pvalid(tl, k)) continue;
+                    const int q = pt.Q[k];
+                    const T t = grad_xi<T>(g, l, q) *
+                                fourth_diff(A, threadIdx.x + k * kThreads, pt.J[k], tl.n, tl.lj, per);
+                    T rest;
+                    if constexpr (kPre) rest = plad[k];
+                    else rest = P2[q];
+                    lv[k] = (T)g.C * fabs(d > 1 ? t + rest : t);
+                }
+            }
             __syncthreads();
             pcr_solve<T, NP>(fl, pt, tl, g.dop[l], pc, A, B);
+            if (ladst) {
+                // smoothing along 0 (A and B are free after the solve)
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    if (pvalid(tl, k)) A[threadIdx.x + k * kThreads] = lv[k];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    if (pvalid(tl, k))
+                        Sl[pt.Q[k]] = gauss9(A, threadIdx.x + k * kThreads, pt.J[k], tl.n, tl.lj, per);
+                // A is next written after the barrier that follows the field phase
+            }
             T *Fl = static_cast<T *>(g.F[l]);
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
