@@ -21,9 +21,9 @@ LIB_PATH = os.path.join(HERE, "libwdoracle.so")
 WALL, NEUMANN, OUTFLOW, PERIODIC = 0, 1, 2, 3
 EIKONAL, HJ, POISSON = 0, 1, 2
 GAMMA_LINEAR, GAMMA_LAD = 0, 1
-E2, E4, E6, C4, C6 = 0, 1, 2, 3, 4
+E2, E4, E6, C4, C6, UW = 0, 1, 2, 3, 4, 5
 RK3, RK4 = 0, 1
-SCHEMES = {"E2": E2, "E4": E4, "E6": E6, "C4": C4, "C6": C6}
+SCHEMES = {"E2": E2, "E4": E4, "E6": E6, "C4": C4, "C6": C6, "UW": UW}
 
 
 def build(force: bool = True) -> str:
@@ -53,7 +53,8 @@ class _Method(C.Structure):
                 ("scheme", C.c_int), ("filter", C.c_int),
                 ("alpha_f", C.c_double), ("rk", C.c_int),
                 ("sigma", C.c_double), ("tol", C.c_double),
-                ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("lad_raw", C.c_int)]
+                ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("lad_raw", C.c_int),
+                ("uw_printed", C.c_int)]
 
 
 _lib = None
@@ -123,7 +124,8 @@ class OracleGrid:
 
 def make_method(equation=HJ, gamma=GAMMA_LINEAR, curvature=0, eps=0.1, C_lad=0.1,
                 nu0=1e-3, eps0=1e-6, scheme=E4, filter=1, alpha_f=0.495,
-                rk=RK4, sigma=1.0, tol=1e-10, max_iter=100000, fixed_iters=0, lad_raw=0):
+                rk=RK4, sigma=1.0, tol=1e-10, max_iter=100000, fixed_iters=0, lad_raw=0,
+                uw_printed=0):
     m = _Method()
     m.equation, m.gamma, m.curvature = equation, gamma, curvature
     m.eps, m.C, m.nu0, m.eps0 = eps, C_lad, nu0, eps0
@@ -131,6 +133,7 @@ def make_method(equation=HJ, gamma=GAMMA_LINEAR, curvature=0, eps=0.1, C_lad=0.1
     m.filter, m.alpha_f, m.rk = filter, alpha_f, rk
     m.sigma, m.tol, m.max_iter, m.fixed_iters = sigma, tol, max_iter, fixed_iters
     m.lad_raw = lad_raw
+    m.uw_printed = uw_printed
     return m
 
 

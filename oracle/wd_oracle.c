@@ -49,7 +49,8 @@ static scheme_t scheme_of(int s)
     scheme_t r;
     memset(&r, 0, sizeof r);
     switch (s) {
-    case WDO_E2: r.a = 1.0; r.radius = 1; break;
+    case WDO_E2:
+    case WDO_UW: r.a = 1.0; r.radius = 1; break;   /* UW: central parts are E2 */
     case WDO_E4: r.a = 4.0 / 3.0; r.b = -1.0 / 3.0; r.radius = 2; break;
     case WDO_E6: r.a = 1.5; r.b = -0.6; r.c = 0.1; r.radius = 3; break;
     case WDO_C4: r.al = 0.25; r.a = 1.5; r.radius = 1; r.compact = 1; break;
@@ -65,6 +66,7 @@ static double kprime_of(int s)
 {
     switch (s) {
     case WDO_E2: return 1.0;
+    case WDO_UW: return 1.0;    /* diffusive part (E2); the upwind term uses 2 */
     case WDO_E4: return 1.372;
     case WDO_E6: return 1.586;
     case WDO_C4: return 1.732;
@@ -162,6 +164,8 @@ static double central_rhs(const scheme_t *s, const double *f, int n,
 int wdo_deriv_line(int n, int periodic, int scheme, double jump,
                    const double *f, double *df)
 {
+    if (scheme == WDO_UW)
+        scheme = WDO_E2;   /* the upwind baseline's central derivatives */
     scheme_t s = scheme_of(scheme);
     if (n < 8 || scheme < WDO_E2 || scheme > WDO_C6)
         return -1;
@@ -581,6 +585,64 @@ int wdo_lad_field(const wdo_grid *g, const wdo_method *m, const double *met,
     return 0;
 }
 
+/* Advective term of the upwind baseline (Sec. 3.2.1).  Along each grid
+ * direction l, with unit index spacing, B = phi_i - phi_{i-1} and
+ * F = phi_{i+1} - phi_i (periodic lines wrap; at the two ends of a
+ * non-periodic line the missing one equals the other).  The derivative that
+ * enters the contravariant velocity (Eq. UW3) takes the switch weights of
+ * Eqs. UW4-UW5, SIGN(1, x) = +1 for x >= 0 and -1 otherwise:
+ *   n_{i-1} = (1 + SIGN(1, F+B)) (1 + SIGN(1, B)) / 4,
+ *   n_{i+1} = (1 - SIGN(1, F+B)) (1 - SIGN(1, F)) / 4,
+ *   phi_l ~ n_{i-1} B + n_{i+1} F   (reading: n_{i-1} weighs the i-1 side;
+ *   uw_printed = 1 pairs them as printed, n_{i-1} F + n_{i+1} B),
+ * so a rising line uses B, a falling one F, a minimum 0 and a ridge the
+ * steeper side.  U_m = sum_l xi_{l,m} phi_l, Uh_l = sum_m xi_{l,m} U_m and
+ * (Eq. UW1) U.grad(phi) = sum_l [(Uh_l + |Uh_l|) B + (Uh_l - |Uh_l|) F] / 2.
+ * adv receives U.grad(phi), g2 receives |U|^2. */
+static void uw_advection(const wdo_grid *g, const wdo_method *m, const double *met,
+                         const double *phi, double *adv, double *g2)
+{
+    int d = g->ndim;
+    long N = npoints(g);
+    for (long q = 0; q < N; ++q) {
+        int idx[3];
+        index_of(g, q, idx);
+        double B[3], F[3], D[3];
+        for (int l = 0; l < d; ++l) {
+            int n = g->n[l], i = idx[l];
+            long s = stride_of(g, l);
+            int periodic = g->bc[l][0] == WDO_PERIODIC;
+            int has_m = i > 0 || periodic, has_p = i < n - 1 || periodic;
+            long qm = i > 0 ? q - s : q + (long)(n - 1) * s;
+            long qp = i < n - 1 ? q + s : q - (long)(n - 1) * s;
+            double b = has_m ? phi[q] - phi[qm] : 0.0;
+            double f = has_p ? phi[qp] - phi[q] : 0.0;
+            if (!has_m) b = f;
+            if (!has_p) f = b;
+            double sfb = (f + b) >= 0.0 ? 1.0 : -1.0;
+            double sb = b >= 0.0 ? 1.0 : -1.0, sf = f >= 0.0 ? 1.0 : -1.0;
+            double nm = 0.25 * (1.0 + sfb) * (1.0 + sb);
+            double np = 0.25 * (1.0 - sfb) * (1.0 - sf);
+            B[l] = b;
+            F[l] = f;
+            D[l] = m->uw_printed ? nm * f + np * b : nm * b + np * f;
+        }
+        double Um[3] = {0.0, 0.0, 0.0}, s2 = 0.0;
+        for (int mm = 0; mm < d; ++mm) {
+            for (int l = 0; l < d; ++l) Um[mm] += met[(l * d + mm) * N + q] * D[l];
+            s2 += Um[mm] * Um[mm];
+        }
+        double a = 0.0;
+        for (int l = 0; l < d; ++l) {
+            double uh = 0.0;
+            for (int mm = 0; mm < d; ++mm) uh += met[(l * d + mm) * N + q] * Um[mm];
+            a += 0.5 * (uh + fabs(uh)) * B[l] + 0.5 * (uh - fabs(uh)) * F[l];
+        }
+        adv[q] = a;
+        g2[q] = s2;
+    }
+}
+
 /* Right-hand side of the pseudo-time equation at phi (Sec. 3.3):
  *   Eikonal (USeq1):  R = 1 - U.grad(phi) = 1 - |grad phi|^2
  *   HJ      (USeq3):  R = 1 + Gamma lap(phi) - |grad phi|^2
@@ -620,6 +682,18 @@ int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
         double s = 0.0;
         for (int mm = 0; mm < d; ++mm) s += U[mm * N + q] * U[mm * N + q];
         G[q] = sqrt(s);
+    }
+    int uw = m->scheme == WDO_UW && m->equation != WDO_POISSON;
+    double *Adv = NULL, *G2 = NULL;
+    if (uw) {
+        if (m->equation == WDO_HJ && m->curvature) {
+            free(F); free(U); free(tmp); free(L); free(K); free(G);
+            return -1;   /* the baseline has no curvature correction */
+        }
+        Adv = malloc(sizeof(double) * N);
+        G2 = malloc(sizeof(double) * N);
+        uw_advection(g, m, met, phi, Adv, G2);
+        for (long q = 0; q < N; ++q) G[q] = sqrt(G2[q]);
     }
     int need_lap = m->equation != WDO_EIKONAL;
     int curv = m->equation == WDO_HJ && m->curvature;
@@ -662,9 +736,12 @@ int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
         free(S);
     }
     double kp = kprime_of(m->scheme);
+    /* the upwind term's largest modified wavenumber: |1 - e^{-i w}| <= 2 */
+    double kadv = m->scheme == WDO_UW ? 2.0 : kp;
     for (long q = 0; q < N; ++q) {
         double g2 = 0.0;
         for (int mm = 0; mm < d; ++mm) g2 += U[mm * N + q] * U[mm * N + q];
+        if (uw) g2 = Adv[q];    /* U.grad(phi) by Eqs. UW1-UW5 */
         double nu = curv ? m->nu0 * (1.0 - G[q]) * (1.0 - G[q]) : 0.0;
         double r;
         if (m->equation == WDO_EIKONAL)
@@ -695,15 +772,16 @@ int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
             double gm = G[q] > 1.0 ? G[q] : 1.0;
             double den;
             if (m->equation == WDO_EIKONAL)
-                den = 2.0 * kp * S1 * gm;
+                den = 2.0 * kadv * S1 * gm;
             else if (m->equation == WDO_POISSON)
                 den = kp * kp * S2;
             else
-                den = 2.0 * kp * S1 * gm + kp * kp * (Gam[q] + nu) * S2;
+                den = 2.0 * kadv * S1 * gm + kp * kp * (Gam[q] + nu) * S2;
             dt[q] = m->sigma / den;
         }
     }
     free(F); free(U); free(tmp); free(L); free(K); free(G); free(Gam);
+    free(Adv); free(G2);
     return rc;
 }
 

@@ -25,7 +25,7 @@ extern "C" {
 enum { WDO_WALL = 0, WDO_NEUMANN = 1, WDO_OUTFLOW = 2, WDO_PERIODIC = 3 };
 enum { WDO_EIKONAL = 0, WDO_HJ = 1, WDO_POISSON = 2 };
 enum { WDO_GAMMA_LINEAR = 0, WDO_GAMMA_LAD = 1 };
-enum { WDO_E2 = 0, WDO_E4 = 1, WDO_E6 = 2, WDO_C4 = 3, WDO_C6 = 4 };
+enum { WDO_E2 = 0, WDO_E4 = 1, WDO_E6 = 2, WDO_C4 = 3, WDO_C6 = 4, WDO_UW = 5 };
 enum { WDO_RK3 = 0, WDO_RK4 = 1 };
 
 typedef struct {
@@ -47,7 +47,10 @@ typedef struct {
     double C;                  /* LAD constant                            */
     double nu0;                /* curvature stabiliser coefficient        */
     double eps0;               /* regulariser of the unit normal          */
-    int scheme;                /* WDO_E2 .. WDO_C6                        */
+    int scheme;                /* WDO_E2 .. WDO_C6, or WDO_UW: the paper's
+                                  first-order upwind baseline (Sec. 3.2.1,
+                                  Eqs. UW1-UW5) with 2nd-order central
+                                  Laplacian and metrics                   */
     int filter;                /* 1: implicit filter after each step      */
     double alpha_f;
     int rk;                    /* WDO_RK3 (SSP) / WDO_RK4                 */
@@ -61,6 +64,10 @@ typedef struct {
                                   direction; 1 = unsmoothed, recomputed from
                                   each stage value (kept to document its
                                   instability)                           */
+    int uw_printed;            /* UW switch weights: 0 (default) = n_{i-1}
+                                  weighs the backward difference B and
+                                  n_{i+1} the forward one F; 1 = the
+                                  pairing as printed (n_{i-1} with F)      */
 } wdo_method;
 
 /* 1-D operators in index space (unit spacing).  jump: f(i+n) = f(i)+jump

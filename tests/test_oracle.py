@@ -339,3 +339,70 @@ def test_lad_reading_keeps_rounding_at_rounding_level(oracle):
     kw = dict(equation=oracle.HJ, gamma=oracle.GAMMA_LAD, scheme="E6", eps=0.2)
     assert _perturbation_growth(oracle, spec, 20, lad_raw=0, **kw) < 1e-12
     assert _perturbation_growth(oracle, spec, 20, lad_raw=1, **kw) > 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Upwind baseline (Sec. 3.2.1, Eqs. UW1-UW5)
+
+def test_uw_eikonal_channel_is_exact(oracle):
+    """First-order upwind Eikonal in the channel: d = min(y, 1-y) is
+    piecewise linear, its one-sided differences are exactly +-h, and the
+    switch picks the steeper side on the ridge, so the march stops on the
+    exact distance."""
+    for ny in (29, 30):
+        spec = G.channel(37, ny)
+        m = oracle.make_method(equation=oracle.EIKONAL, scheme="UW", filter=0, tol=1e-12,
+                               max_iter=20000)
+        phi, st, it, h = oracle.solve(spec, m)
+        assert st == 0
+        assert np.abs(phi - spec.exact).max() < 1e-10
+
+
+def test_uw_switch_pairing_as_printed_fails(oracle):
+    """Eq. UW3 pairs n_{i-1} with F as printed; with that pairing a rising
+    line takes its downwind difference and the channel march does not
+    settle, while the pairing n_{i-1} B + n_{i+1} F (Godunov's choice:
+    B rising, F falling, 0 at a minimum, the steeper side on a ridge)
+    reaches the exact distance (test above)."""
+    spec = G.channel(37, 29)
+    m = oracle.make_method(equation=oracle.EIKONAL, scheme="UW", filter=0, tol=1e-12,
+                           max_iter=3000, uw_printed=1)
+    phi, st, it, h = oracle.solve(spec, m)
+    assert st != 0
+    assert not (np.abs(phi - spec.exact).max() < 1e-2)
+
+
+def test_uw_hj_channel_first_order(oracle):
+    """Standard HJ (eps 0.1) with the upwind term and the 2nd-order central
+    Laplacian converges to the 1-D ODE profile at first order."""
+    sol = _hj_ode(0.1)
+    errs = []
+    for ny in (33, 65, 129):
+        spec = G.channel(16, ny)
+        m = oracle.make_method(equation=oracle.HJ, eps=0.1, scheme="UW", filter=0, tol=1e-12,
+                               max_iter=200000)
+        phi, st, it, h = oracle.solve(spec, m)
+        assert st == 0
+        y = np.arange(ny) / (ny - 1)
+        yy = np.minimum(y, 1 - y)
+        ref = np.array([sol.sol(v)[0] if v > sol.t_events[0][0] else 0.0 for v in yy])
+        errs.append(np.abs(phi[:, 5] - ref).max())
+        assert np.abs(phi - phi[:, :1]).max() == 0.0
+        assert np.abs(phi - phi[::-1]).max() < 1e-14
+    assert 1.6 < errs[0] / errs[1] < 2.4 and 1.6 < errs[1] / errs[2] < 2.4
+
+
+def test_uw_eikonal_box_first_order(oracle):
+    """Upwind Eikonal in the 2-D box: error against min(x, 1-x, y, 1-y)
+    halves with the spacing (the kinks on the diagonals limit it to first
+    order) and the field keeps the box's x <-> y symmetry exactly."""
+    errs = []
+    for n in (33, 65):
+        spec = G.box2d(n)
+        m = oracle.make_method(equation=oracle.EIKONAL, scheme="UW", filter=0, tol=1e-12,
+                               max_iter=200000)
+        phi, st, it, h = oracle.solve(spec, m)
+        assert st == 0
+        errs.append(np.abs(phi - spec.exact).max())
+        assert np.abs(phi - phi.T).max() == 0.0
+    assert 1.7 < errs[0] / errs[1] < 2.3
