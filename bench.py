@@ -327,6 +327,57 @@ def run_batch(args):
                    "linf_err_median_same_accuracy": float(np.median([e64[i] for i in ok])) if ok else None}}
 
 
+def run_ratios(args):
+    """GPU counterpart of the paper's timing comparisons (Sec. 5.2, 5.3):
+    time per 100 pseudo iterations of the first-order upwind baseline (no
+    filter) and of the central schemes (with the filter, alpha_f 0.48), and
+    time / iterations / error to the paper's criterion (max change <= 1e-5),
+    FP64, default tiles: the 129x65 channel with standard HJ (eps 0.1) and
+    with LAD HJ, and a 129x129 2-D box with the Eikonal equation."""
+    import torch
+    from paper_2111_09859_amd import api, grids as G
+    s = api.Solver(0)
+    cases = [("channel129x65_hj", G.channel(129, 65), dict(equation="HJ", gamma="LINEAR", eps=0.1)),
+             ("channel129x65_lad", G.channel(129, 65), dict(equation="HJ", gamma="LAD", eps=0.2)),
+             ("box129_eikonal", G.box2d(129), dict(equation="EIKONAL"))]
+    out = {}
+    for name, spec, kw in cases:
+        row = {}
+        for sch in ("UW", "E2", "E4", "C4", "C6"):
+            filt = sch != "UW"
+            prep = s.prepare(spec, sch, "fp64")
+            m = api.make_method(scheme=sch, filter=filt, alpha_f=0.48, tol=0.0, max_iter=300,
+                                precision="fp64", rk="RK4", **kw)
+            s.solve(prep, m, check=False)               # warm-up (graphs, tables)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.solve(prep, m, check=False)
+            torch.cuda.synchronize()
+            per100 = (time.perf_counter() - t0) / 3.0
+            mc = api.make_method(scheme=sch, filter=filt, alpha_f=0.48, tol=1e-5, max_iter=50000,
+                                 precision="fp64", rk="RK4", **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = s.solve(prep, mc, check=False)
+            torch.cuda.synchronize()
+            tc = time.perf_counter() - t0
+            row[sch] = {"ms_per_100_iters": 1e3 * per100, "iters_to_1e-5": r["iters"],
+                        "status": r["status"], "s_to_1e-5": tc,
+                        "linf_err": float(np.abs(r["phi"].cpu().numpy() - spec.exact).max())}
+            print(f"[ratios] {name} {sch}: {1e3 * per100:.2f} ms/100 its, {r['iters']} its, "
+                  f"{tc:.3f} s to 1e-5", file=sys.stderr, flush=True)
+        for sch in row:
+            row[sch]["uw_time_per_iter_over_this"] = (row["UW"]["ms_per_100_iters"]
+                                                      / row[sch]["ms_per_100_iters"])
+        out[name] = row
+    return {"metric": "time per 100 pseudo iterations, central vs upwind", "value": None,
+            "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
+            "data": "synthetic", "vs_baseline": None,
+            "config": {"workload": "channel 129x65 (HJ standard, HJ LAD), box 129x129 (Eikonal); "
+                                   "UW without filter, E2/E4/C4/C6 with F10 alpha_f 0.48, RK4",
+                       "results": out}}
+
+
 def run_serve(args):
     """Config 5 (bounded sample): open-loop Poisson arrivals (200 req/s) of
     2D grids 129^2..2049^2 and 3D ducts 64^3..192^3 into the continuous-
@@ -451,6 +502,9 @@ def main():
         return
     if args.workload == "copy":
         print(json.dumps(run_copy(args)), flush=True)
+        return
+    if args.workload == "ratios":
+        print(json.dumps(run_ratios(args)), flush=True)
         return
     if args.workload == "batch":
         print(json.dumps(run_batch(args)), flush=True)

@@ -63,7 +63,13 @@ enum wd_equation { WD_EQ_EIKONAL = 0, WD_EQ_HJ = 1, WD_EQ_POISSON = 2 };
 enum wd_gamma { WD_GAMMA_LINEAR = 0, WD_GAMMA_LAD = 1 };
 /* Sec. 3.2 schemes; E6 is the sixth-order explicit member of the same
  * family (third term c (f_{i+3} - f_{i-3})/6). */
-enum wd_scheme { WD_E2 = 0, WD_E4 = 1, WD_E6 = 2, WD_C4 = 3, WD_C6 = 4 };
+enum wd_scheme { WD_E2 = 0, WD_E4 = 1, WD_E6 = 2, WD_C4 = 3, WD_C6 = 4,
+                 /* the paper's first-order upwind baseline (Sec. 3.2.1,
+                  * Eqs. UW1-UW5): the advective term from switched
+                  * one-sided differences, 2nd-order central (E2) Laplacian
+                  * and metrics; no curvature correction (WD_ERR_UNSUPPORTED),
+                  * usually run without the filter */
+                 WD_UW = 5 };
 enum wd_rk { WD_RK3_SSP = 0, WD_RK4 = 1 };
 enum wd_precision { WD_FP32 = 0, WD_FP64 = 1 };
 

@@ -22,11 +22,11 @@ WD_BC_WALL, WD_BC_NEUMANN, WD_BC_OUTFLOW, WD_BC_PERIODIC = 0, 1, 2, 3
 WD_METRIC_UNIFORM, WD_METRIC_FIELDS = 0, 1
 WD_EQ_EIKONAL, WD_EQ_HJ, WD_EQ_POISSON = 0, 1, 2
 WD_GAMMA_LINEAR, WD_GAMMA_LAD = 0, 1
-WD_E2, WD_E4, WD_E6, WD_C4, WD_C6 = 0, 1, 2, 3, 4
+WD_E2, WD_E4, WD_E6, WD_C4, WD_C6, WD_UW = 0, 1, 2, 3, 4, 5
 WD_RK3_SSP, WD_RK4 = 0, 1
 WD_FP32, WD_FP64 = 0, 1
 
-SCHEMES = {"E2": WD_E2, "E4": WD_E4, "E6": WD_E6, "C4": WD_C4, "C6": WD_C6}
+SCHEMES = {"E2": WD_E2, "E4": WD_E4, "E6": WD_E6, "C4": WD_C4, "C6": WD_C6, "UW": WD_UW}
 
 
 class wd_grid_desc(C.Structure):

@@ -66,7 +66,9 @@ struct GridDev {
     int fuse_faces;           // extrapolated faces all normal to the last
                               // direction: applied inside its passes
     int stages;
-    double eps, C, nu0, eps0, sigma, kp, tol;
+    int uw;                   // first-order upwind advective term (Eqs. UW1-UW5)
+    double eps, C, nu0, eps0, sigma, tol;
+    double kp, kp2;           // largest modified wavenumbers: advective, diffusive
     int max_iter, stall;
     int warm;                 // initial field given by the caller
     double fcoef[6];          // filter correction factor for N = 1..5
@@ -77,6 +79,8 @@ struct GridDev {
     void *phi, *ps, *acc, *dt;
     void *F[3];
     void *P[3];               // partial sums carried between passes
+    void *uw2;                // upwind baseline: |U|^2 of the stage (its
+                              // advective term is carried in P[1])
     double *rpart;            // [nparts][2] residual partials
     double *hist;             // [hist_cap][2]
     int hist_cap;

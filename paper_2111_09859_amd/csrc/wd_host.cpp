@@ -257,7 +257,9 @@ int check_method(const wd_method *m)
     if (!m) return fail(WD_ERR_INVALID_ARG, "null method");
     if (m->equation < WD_EQ_EIKONAL || m->equation > WD_EQ_POISSON) return fail(WD_ERR_INVALID_ARG, "bad equation");
     if (m->gamma != WD_GAMMA_LINEAR && m->gamma != WD_GAMMA_LAD) return fail(WD_ERR_INVALID_ARG, "bad gamma");
-    if (m->scheme < WD_E2 || m->scheme > WD_C6) return fail(WD_ERR_INVALID_ARG, "bad scheme");
+    if (m->scheme < WD_E2 || m->scheme > WD_UW) return fail(WD_ERR_INVALID_ARG, "bad scheme");
+    if (m->scheme == WD_UW && m->equation == WD_EQ_HJ && m->curvature)
+        return fail(WD_ERR_UNSUPPORTED, "the upwind baseline has no curvature correction");
     if (m->rk != WD_RK3_SSP && m->rk != WD_RK4) return fail(WD_ERR_INVALID_ARG, "bad rk");
     if (m->precision != WD_FP32 && m->precision != WD_FP64) return fail(WD_ERR_INVALID_ARG, "bad precision");
     if (m->filter && !(m->alpha_f >= 0.0 && m->alpha_f < 0.5))
@@ -283,7 +285,8 @@ static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 int grid_mode(const wd_grid_desc &d, const wd_method &m)
 {
     const bool curv = m.equation == WD_EQ_HJ && m.curvature;
-    return (d.metric_mode == WD_METRIC_UNIFORM && !curv) ? MODE_CART : MODE_GENERAL;
+    const bool uw = m.scheme == WD_UW && m.equation != WD_EQ_POISSON;
+    return (d.metric_mode == WD_METRIC_UNIFORM && !curv && !uw) ? MODE_CART : MODE_GENERAL;
 }
 
 int hist_dev_cap(const wd_method &m) { return std::min(m.max_iter, 1 << 17); }
@@ -301,6 +304,7 @@ size_t grid_region_bytes(const wd_grid_desc &d, const wd_method &m)
     b += f;                                      // dt
     if (grid_mode(d, m) == MODE_GENERAL) b += (size_t)d.ndim * f;  // F_l
     b += 3 * f;                                  // partial sums / LAD field
+    if (m.scheme == WD_UW && m.equation != WD_EQ_POISSON) b += f;   // upwind |U|^2
     if (m.equation == WD_EQ_POISSON)
         b += (size_t)(d.ndim + 1) * al256((size_t)N * 8);  // FP64 conversion
     long long parts = N / d.n[d.ndim - 1];
@@ -321,7 +325,7 @@ long long grid_items(const wd_grid_desc &d)
     const long long chunks = (N + kChunk - 1) / kChunk;
     long long face = 0;
     for (int l = 0; l < d.ndim; ++l) face += 2 * ((N / d.n[l] + kChunk - 1) / kChunk);
-    return 5 * lines + 3 * chunks + 2 * face + 8;
+    return 5 * lines + 4 * chunks + 2 * face + 8;
 }
 
 // batch tables: grid array, state mirrors, two one-grid views, items
@@ -370,6 +374,7 @@ int pick_tile(wd_ctx *ctx, const wd_grid_desc &d, int l, int fp64)
 static double kprime(int scheme)
 {
     switch (scheme) {
+    case WD_UW: return 2.0;    // |1 - e^{-iw}| <= 2 of the one-sided differences
     case WD_E2: return 1.0;
     case WD_E4: return 1.372;
     case WD_E6: return 1.586;
@@ -422,7 +427,11 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     g.eq = m.equation;
     g.lad = m.equation == WD_EQ_HJ && m.gamma == WD_GAMMA_LAD;
     g.curv = m.equation == WD_EQ_HJ && m.curvature;
-    g.scheme = m.scheme;
+    // the upwind baseline evaluates its advective term pointwise and all its
+    // central derivatives (Laplacian, Poisson) with E2
+    g.uw = m.scheme == WD_UW && m.equation != WD_EQ_POISSON;
+    const int dscheme = m.scheme == WD_UW ? WD_E2 : m.scheme;
+    g.scheme = dscheme;
     g.rk = m.rk == WD_RK4;
     g.stages = g.rk ? 4 : 3;
     g.need_lap = m.equation != WD_EQ_EIKONAL;
@@ -442,7 +451,8 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     g.nu0 = m.nu0;
     g.eps0 = m.eps0;
     g.sigma = m.sigma;
-    g.kp = kprime(m.scheme);
+    g.kp = kprime(g.uw ? WD_UW : dscheme);   // advective term
+    g.kp2 = kprime(dscheme);                  // diffusive term
     g.tol = m.tol;
     g.max_iter = m.max_iter;
     g.stall = m.stall_window;
@@ -450,7 +460,7 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     // filter correction factor -(1 - 2 af)(-1)^N / 4^N
     for (int N5 = 1; N5 <= 5; ++N5)
         g.fcoef[N5] = -(1.0 - 2.0 * m.alpha_f) * ((N5 & 1) ? -1.0 : 1.0) / std::ldexp(1.0, 2 * N5);
-    switch (m.scheme) {
+    switch (dscheme) {
     case WD_E2: g.da = 1.0; g.dradius = 1; break;
     case WD_E4: g.da = 4.0 / 3.0; g.db = -1.0 / 3.0; g.dradius = 2; break;
     case WD_E6: g.da = 1.5; g.db = -0.6; g.dc = 0.1; g.dradius = 3; break;
@@ -465,6 +475,7 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     if (g.mode == MODE_GENERAL)
         for (int l = 0; l < d.ndim; ++l) g.F[l] = take(f);
     for (int k = 0; k < 3; ++k) g.P[k] = take(f);
+    if (g.uw) g.uw2 = take(f);
     if (m.equation == WD_EQ_POISSON) {
         h.pois_phip = take((size_t)N * 8);
         for (int l = 0; l < d.ndim; ++l) h.pois_F[l] = take((size_t)N * 8);
@@ -476,11 +487,11 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     g.hist = static_cast<double *>(take((size_t)g.hist_cap * 16));
     g.state = static_cast<GridState *>(take(sizeof(GridState)));
     for (int l = 0; l < d.ndim; ++l) {
-        const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, d.n[l], g.periodic[l], m.scheme, 0.0, fp64);
+        const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, d.n[l], g.periodic[l], dscheme, 0.0, fp64);
         if (!dop) return WD_ERR_NO_MEMORY;
         g.dop[l] = *dop;
         if (m.filter) {
-            const LineOpDev *fop = ctx_lineop(ctx, OP_FILTER, d.n[l], g.periodic[l], m.scheme, m.alpha_f, fp64);
+            const LineOpDev *fop = ctx_lineop(ctx, OP_FILTER, d.n[l], g.periodic[l], dscheme, m.alpha_f, fp64);
             if (!fop) return WD_ERR_NO_MEMORY;
             g.fop[l] = *fop;
         }
@@ -608,15 +619,21 @@ void build_items(Plan &P)
     auto cart = [](const GridDev &g) { return g.mode == MODE_CART; };
     auto gen_lap = [](const GridDev &g) { return g.mode == MODE_GENERAL && g.need_lap; };
     auto gen_eik = [](const GridDev &g) { return g.mode == MODE_GENERAL && !g.need_lap; };
-    auto gen = [](const GridDev &g) { return g.mode == MODE_GENERAL; };
+    // first-derivative fields: every general grid but the upwind Eikonal
+    // (its stage finish takes one-sided differences of phi itself)
+    auto gen_f = [](const GridDev &g) { return g.mode == MODE_GENERAL && (g.need_lap || !g.uw); };
+    auto gen_eik_f = [](const GridDev &g) { return g.mode == MODE_GENERAL && !g.need_lap && !g.uw; };
     for (int l = 0; l < 3; ++l) line_slot(P.cart[l], PASS_CART, l, 0, cart);
     // general grids: F_l for l >= 1 first (all l for the Eikonal), then the
     // fused pass along 0, then pass 2 along l >= 1 (the last one finishes)
-    line_slot(P.d1[0], PASS_D1, 0, 0, gen_eik);
-    for (int l = 1; l < 3; ++l) line_slot(P.d1[l], PASS_D1, l, 0, gen);
+    line_slot(P.d1[0], PASS_D1, 0, 0, gen_eik_f);
+    for (int l = 1; l < 3; ++l) line_slot(P.d1[l], PASS_D1, l, 0, gen_f);
     line_slot(P.d12, PASS_D12, 0, 0, gen_lap);
     P.d2[0] = Slot();
     for (int l = 1; l < 3; ++l) line_slot(P.d2[l], PASS_D2, l, 0, gen_lap);
+    P.uwadv = point_list(PASS_UWADV, 0, 0, [&](int i) {
+        return (gen_eik(P.grids[i]) && P.grids[i].uw) ? P.grids[i].nchunks : 0;
+    });
     P.fin = point_list(PASS_FINAL, 0, 0, [&](int i) {
         return gen_eik(P.grids[i]) ? P.grids[i].nchunks : 0;
     });
@@ -663,6 +680,7 @@ static const char *kind_name(int kind)
     case PASS_D1: return "k_d1";
     case PASS_D2: return "k_d2";
     case PASS_D12: return "k_d12";
+    case PASS_UWADV: return "k_uwadv";
     case PASS_FILTER: return "k_filter";
     case PASS_FINAL: return "k_final";
     case PASS_RESID: return "k_resid";
@@ -720,7 +738,9 @@ static double point_accesses(const GridDev &g, int kind, int l, int stage)
         // (+ the LAD sensor sum in and the smoothed field out at stage 0)
         return 2 + (d - 1) + met + (1 + g.curv) + ((stage == 0 && g.lad) ? 2 : 0);
     case PASS_FINAL:
-        return d + met + finish(0);
+        return (g.uw ? 2 : d) + met + finish(0);
+    case PASS_UWADV:
+        return 1 + met + 2;                        // phi (and neighbours), metrics in; adv, |U|^2 out
     case PASS_FILTER:
         return last && g.fused_resid ? 3 : 2;      // (+ phi read/write when fused)
     case PASS_RESID:
@@ -847,6 +867,7 @@ void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s)
         for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.d1[l], st, s);
         issue_slot(ctx, P, P.d12, st, s);
         for (int l = 1; l < P.maxdim; ++l) issue_slot(ctx, P, P.d2[l], st, s);
+        issue_list(ctx, P, P.uwadv, st, s);
         issue_list(ctx, P, P.fin, st, s);
         issue_faces(ctx, P, 1, s);
     }
@@ -1249,7 +1270,8 @@ int wd_compute_metrics(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, const 
     d.metrics = nullptr;
     int rc = check_desc(&d);
     if (rc) return rc;
-    if (scheme < WD_E2 || scheme > WD_C6) return fail(WD_ERR_INVALID_ARG, "bad scheme");
+    if (scheme < WD_E2 || scheme > WD_UW) return fail(WD_ERR_INVALID_ARG, "bad scheme");
+    if (scheme == WD_UW) scheme = WD_E2;   // the upwind baseline's metrics are central E2
     std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     (void)hipSetDevice(ctx->device);
     StreamJoin join(ctx, stream);

@@ -90,7 +90,7 @@ struct Plan {
     std::vector<ItemList> lists;
     Slot cart[3], d1[3], d12, d2[3], filt[3], lad0[3], lad1[3];
     int face[6], face_init[6];
-    int fin = 0, resid = 0, init = 0;
+    int fin = 0, resid = 0, init = 0, uwadv = 0;
     GridDev *d_grids = nullptr;
     GridDev *d_aux = nullptr, *d_aux2 = nullptr;
     GridState *d_states = nullptr;

@@ -17,6 +17,7 @@ enum PassKind {
     PASS_LAD = 8,     // LAD diffusivity along l; stage = phase (0 sensor,
                       // 1 smoothing)
     PASS_D12 = 9,     // pass 2 along direction 0 that also forms F_0
+    PASS_UWADV = 10,  // pointwise upwind advective term (Eikonal grids)
 };
 
 // One launch of a pass over `nitems` work items with at most `nwg`

@@ -11,7 +11,7 @@
 namespace wd {
 
 // Pointwise stage finish for general grids without a second derivative
-// level (Eikonal).
+// level (Eikonal; for the upwind baseline also its advective term).
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_final(const GridDev *__restrict__ grids, const Item *__restrict__ items,
@@ -27,21 +27,63 @@ k_final(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             const long long qq = q0 + i;
             if (qq >= g.N) break;
             const int q = (int)qq;
-            T m9[9], F3[3], U[3], g2;
+            const T *src = static_cast<const T *>(stage == 0 ? g.phi : g.ps);
+            T m9[9], g2, adv;
             metric_load<T>(g, q, m9);
-#pragma unroll
-            for (int m = 0; m < 3; ++m)
-                if (m < g.ndim) F3[m] = static_cast<const T *>(g.F[m])[q];
-            grad_from<T>(g.ndim, m9, F3, U, g2);
             int idx[3];
             index_of(g, q, idx);
+            if (g.uw) {
+                // the upwind baseline's advective term, formed by k_uwadv
+                // (this pass overwrites the stage value its stencil reads)
+                adv = static_cast<const T *>(g.P[1])[q];
+                g2 = static_cast<const T *>(g.uw2)[q];
+            } else {
+                T F3[3], U[3];
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    if (m < g.ndim) F3[m] = static_cast<const T *>(g.F[m])[q];
+                grad_from<T>(g.ndim, m9, F3, U, g2);
+                adv = g2;
+            }
             const bool zero = wall_point(g, idx) || (g.mask && g.mask[q]);
-            const T phis = static_cast<const T *>(stage == 0 ? g.phi : g.ps)[q];
+            const T phis = src[q];
             T S1, S2;
             metric_sums<T>(g.ndim, m9, S1, S2);
             static_cast<T *>(g.ps)[q] =
-                finish_point<T>(g, stage, q, zero, phis, g2, (T)0, (T)0, (T)0, S1, S2,
+                finish_point<T>(g, stage, q, zero, phis, g2, adv, (T)0, (T)0, (T)0, S1, S2,
                                 fin_load<T>(g, stage, q, phis));
+        }
+    }
+}
+
+// Advective term of the upwind baseline for grids whose stage finish is
+// pointwise (Eikonal): P[1] <- U.grad(phi) of Eqs. UW1-UW5, uw2 <- |U|^2,
+// from the stage value, before the finish overwrites it.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_uwadv(const GridDev *__restrict__ grids, const Item *__restrict__ items,
+        int nitems, int stage)
+{
+    int step, end;
+    for (int it = item_begin(nitems, step, end); it < end; it += step) {
+        const Item item = items[it];
+        const GridDev &g = grids[item.grid];
+        if (g.state->done) continue;
+        const T *src = static_cast<const T *>(stage == 0 ? g.phi : g.ps);
+        T *adv = static_cast<T *>(g.P[1]);
+        T *u2 = static_cast<T *>(g.uw2);
+        const long long q0 = (long long)item.tile * kChunk;
+        for (int i = threadIdx.x; i < kChunk; i += kThreads) {
+            const long long qq = q0 + i;
+            if (qq >= g.N) break;
+            const int q = (int)qq;
+            T m9[9], a, g2;
+            metric_load<T>(g, q, m9);
+            int idx[3];
+            index_of(g, q, idx);
+            uw_term<T>(g, src, q, idx, m9, a, g2);
+            adv[q] = a;
+            u2[q] = g2;
         }
     }
 }
@@ -302,6 +344,7 @@ static void point_launch(int kind, const GridDev *g, const Item *it, int nitems,
     dim3 grid(nwg), block(kThreads);
     switch (kind) {
     case PASS_FINAL: hipLaunchKernelGGL(k_final<T>, grid, block, 0, s, g, it, nitems, stage); break;
+    case PASS_UWADV: hipLaunchKernelGGL(k_uwadv<T>, grid, block, 0, s, g, it, nitems, stage); break;
     case PASS_RESID: hipLaunchKernelGGL(k_resid<T>, grid, block, 0, s, g, it, nitems); break;
     case PASS_FACE: hipLaunchKernelGGL(k_face<T>, grid, block, 0, s, g, it, nitems, l, stage); break;
     case PASS_INIT: hipLaunchKernelGGL(k_init<T>, grid, block, 0, s, g, it, nitems, stage); break;
@@ -316,6 +359,7 @@ void launch_pass(int kind, int fp64, int np, const GridDev *g, const Item *it, i
     if (nwg > nitems) nwg = nitems;
     switch (kind) {
     case PASS_FINAL:
+    case PASS_UWADV:
     case PASS_RESID:
     case PASS_FACE:
     case PASS_INIT:

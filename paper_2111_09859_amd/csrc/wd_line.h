@@ -582,10 +582,11 @@ __device__ inline FinIn<T> fin_load(const GridDev &g, int stage, int q, T phis)
 
 // Residual of the chosen equation, local time step at stage 0 (stored),
 // RK stage combination (accumulator stored), walls/solids; returns the new
-// stage value (the caller stores it).
+// stage value (the caller stores it).  g2 = |U|^2, adv = U.grad(phi)
+// (= g2 for the central schemes; the upwind product for the baseline).
 template <typename T>
 __device__ T finish_point(const GridDev &g, int stage, int q, bool zero, T phis,
-                          T g2, T lap, T kap, T lads, T S1, T S2, const FinIn<T> &in)
+                          T g2, T adv, T lap, T kap, T lads, T S1, T S2, const FinIn<T> &in)
 {
     const T gm = sqrt(g2);
     T gam = (T)0, nu = (T)0, R;
@@ -596,26 +597,26 @@ __device__ T finish_point(const GridDev &g, int stage, int q, bool zero, T phis,
         if (g.curv) {
             nu = (T)g.nu0 * ((T)1 - gm) * ((T)1 - gm);
             const T gk = gm * kap;
-            R = (T)1 + (gam + nu) * (lap - (gk > (T)0 ? gk : (T)0)) - g2;
+            R = (T)1 + (gam + nu) * (lap - (gk > (T)0 ? gk : (T)0)) - adv;
         } else {
-            R = (T)1 + gam * lap - g2;
+            R = (T)1 + gam * lap - adv;
         }
     } else if (g.eq == EQ_EIK) {
-        R = (T)1 - g2;
+        R = (T)1 - adv;
     } else {
         R = (T)1 + lap;
     }
     T dt;
     if (stage == 0) {
-        const T kp = (T)g.kp;
+        const T kp = (T)g.kp, kp2 = (T)g.kp2;
         const T gmx = gm > (T)1 ? gm : (T)1;
         T den;
         if (g.eq == EQ_EIK)
             den = (T)2 * kp * S1 * gmx;
         else if (g.eq == EQ_POIS)
-            den = kp * kp * S2;
+            den = kp2 * kp2 * S2;
         else
-            den = (T)2 * kp * S1 * gmx + kp * kp * (gam + nu) * S2;
+            den = (T)2 * kp * S1 * gmx + kp2 * kp2 * (gam + nu) * S2;
         dt = (T)g.sigma / den;
         static_cast<T *>(g.dt)[q] = dt;
     } else {
@@ -702,6 +703,65 @@ __device__ inline void grad_from(int d, const T *m, const T *F, T *U, T &g2)
             U[c] = u;
             g2 += u * u;
         }
+    }
+}
+
+// Advective term of the upwind baseline at point q (Sec. 3.2.1): along
+// each direction the one-sided differences B = phi_i - phi_{i-1},
+// F = phi_{i+1} - phi_i of the stage value (periodic lines wrap; at a
+// non-periodic end the missing one equals the other); the switch of Eqs.
+// UW4-UW5, with n_{i-1} weighing B and n_{i+1} weighing F (B on a rising
+// line, F on a falling one, 0 at a minimum, the steeper side on a ridge),
+// gives the derivative of Eq. UW3; U_m = sum_l xi_{l,m} phi_l,
+// Uh_l = sum_m xi_{l,m} U_m and Eq. UW1 gives
+// adv = sum_l [(Uh_l + |Uh_l|) B + (Uh_l - |Uh_l|) F] / 2; g2 = |U|^2.
+// m holds the point's metrics as m[3 l + c].
+template <typename T>
+__device__ void uw_term(const GridDev &g, const T *src, int q, const int *idx, const T *m,
+                        T &adv, T &g2)
+{
+    const int d = g.ndim;
+    const T p0 = src[q];
+    T Bv[3], Fv[3], D[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        Bv[l] = Fv[l] = D[l] = (T)0;
+        if (l >= d) continue;
+        const int n = g.n[l], i = idx[l], s = (int)g.stride[l];
+        const bool per = g.periodic[l] != 0;
+        const bool hm = i > 0 || per, hp = i < n - 1 || per;
+        T b = (T)0, f = (T)0;
+        if (hm) b = p0 - src[i > 0 ? q - s : q + (n - 1) * s];
+        if (hp) f = src[i < n - 1 ? q + s : q - (n - 1) * s] - p0;
+        if (!hm) b = f;
+        if (!hp) f = b;
+        const T sfb = (f + b) >= (T)0 ? (T)1 : (T)-1;
+        const T sb = b >= (T)0 ? (T)1 : (T)-1, sf = f >= (T)0 ? (T)1 : (T)-1;
+        const T wm = (T)0.25 * ((T)1 + sfb) * ((T)1 + sb);
+        const T wp = (T)0.25 * ((T)1 - sfb) * ((T)1 - sf);
+        Bv[l] = b;
+        Fv[l] = f;
+        D[l] = wm * b + wp * f;
+    }
+    T U[3] = {(T)0, (T)0, (T)0};
+    g2 = (T)0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (c >= d) continue;
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+            if (l < d) U[c] += m[3 * l + c] * D[l];
+        g2 += U[c] * U[c];
+    }
+    adv = (T)0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (l >= d) continue;
+        T uh = (T)0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (c < d) uh += m[3 * l + c] * U[c];
+        adv += (T)0.5 * (uh + fabs(uh)) * Bv[l] + (T)0.5 * (uh - fabs(uh)) * Fv[l];
     }
 }
 
@@ -842,7 +902,7 @@ k_cart(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             zero[k] = zero_point(g, tl, l, pt, k);
             const T g2 = pg2[k] + g2c[k];
             const T lap = g.need_lap ? plap[k] + lapc[k] : (T)0;
-            v0[k] = finish_point<T>(g, stage, q, zero[k], v0[k], g2, lap, (T)0, plad[k], S1, S2,
+            v0[k] = finish_point<T>(g, stage, q, zero[k], v0[k], g2, g2, lap, (T)0, plad[k], S1, S2,
                                     fin[k]);
         }
         if (g.fuse_faces) {
@@ -995,6 +1055,31 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                     zr[k] = zero_point(g, tl, l, pt, k);
                     fin[k] = fin_load<T>(g, stage, q, sv[k]);
                 }
+            }
+        }
+        if (FUSED && g.uw) {
+            // upwind advective term of the stage value (Eqs. UW1-UW5): its
+            // stencil reaches across tiles, so it is formed here, in a pass
+            // that does not write the stage value, for the last pass's finish
+            T *adv = static_cast<T *>(g.P[1]);
+            T *u2 = static_cast<T *>(g.uw2);
+#pragma unroll UR
+            for (int k = 0; k < NP; ++k) {
+                if (!pvalid(tl, k)) continue;
+                int j, q;
+                JQ(k, j, q);
+                int idx[3];
+                tile_index(g, tl, l, k, j, idx);
+                T m9[9], a, g2;
+                if constexpr (kPre) {
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) m9[c] = Mv[k][c];
+                } else {
+                    metric_load<T>(g, q, m9);
+                }
+                uw_term<T>(g, src, q, idx, m9, a, g2);
+                adv[q] = a;
+                u2[q] = g2;
             }
         }
         if (ladst && !FUSED) {
@@ -1181,7 +1266,12 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                 const T kap = g.curv ? pk[k] + kapc[k] : (T)0;
                 T S1, S2;
                 metric_sums<T>(d, Mv[k], S1, S2);
-                nv[k] = finish_point<T>(g, stage, pt.Q[k], zr[k], sv[k], g2s[k], lap, kap,
+                T g2 = g2s[k], adv = g2s[k];
+                if (g.uw) {   // formed by the fused pass along 0
+                    adv = static_cast<const T *>(g.P[1])[pt.Q[k]];
+                    g2 = static_cast<const T *>(g.uw2)[pt.Q[k]];
+                }
+                nv[k] = finish_point<T>(g, stage, pt.Q[k], zr[k], sv[k], g2, adv, lap, kap,
                                         plad[k], S1, S2, fin[k]);
             }
             if (g.fuse_faces) {
@@ -1223,11 +1313,17 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                 for (int m = 0; m < 3; ++m)
                     if (m < d) F3[m] = static_cast<const T *>(g.F[m])[q];
                 grad_from<T>(d, m9, F3, U, g2);
+                T adv = g2;
+                if (g.uw) {   // formed by the fused pass along 0
+                    adv = static_cast<const T *>(g.P[1])[q];
+                    g2 = static_cast<const T *>(g.uw2)[q];
+                }
                 T S1, S2;
                 metric_sums<T>(d, m9, S1, S2);
                 const T phis = src[q];
                 const FinIn<T> fi = fin_load<T>(g, stage, q, phis);
-                const T nv = finish_point<T>(g, stage, q, zero, phis, g2, lap, kap, lads, S1, S2, fi);
+                const T nv = finish_point<T>(g, stage, q, zero, phis, g2, adv, lap, kap, lads, S1,
+                                             S2, fi);
                 B[p] = zero ? (T)1 : (T)0;   // wall flag for the face step
                 A[p] = nv;
                 if (!g.fuse_faces) ps[q] = nv;

@@ -91,6 +91,18 @@ CASES = [
     ("duct17x17x12_C6_lad", lambda: G.duct(17, nx=12), dict(eq="HJ", gamma="LAD", scheme="C6"), 25),
     ("duct17x17x12_E4_poisson", lambda: G.duct(17, nx=12), dict(eq="POISSON", scheme="E4"), 25),
     ("duct17x17x12_C4_curv", lambda: G.duct(17, nx=12), dict(eq="HJ", curv=1, scheme="C4"), 3),
+    # the upwind baseline (Eqs. UW1-UW5), run without the filter as the paper's
+    ("channel37x29_UW_eik", lambda: G.channel(37, 29), dict(eq="EIKONAL", scheme="UW", filt=0), 40),
+    ("channel37x29_UW_hj_rk3", lambda: G.channel(37, 29),
+     dict(eq="HJ", scheme="UW", eps=0.1, rk="RK3", filt=0), 40),
+    ("box33_UW_lad", lambda: G.box2d(33), dict(eq="HJ", gamma="LAD", scheme="UW", filt=0), 40),
+    ("cyl48x40_UW_hj_neumann", lambda: G.cylinder(48, 40, rout=6.0, dr1=1e-2, ratio=1.12,
+                                                   far=G.NEUMANN),
+     dict(eq="HJ", scheme="UW", filt=0), 40),
+    ("ell40x33_UW_eik", lambda: G.ellipse(40, 33, axis_ratio=2.0, ratio=1.15, rout=5.0, dr1=1e-2),
+     dict(eq="EIKONAL", scheme="UW", filt=0), 40),
+    ("star64_UW_eik_mask", lambda: G.star_grain(64), dict(eq="EIKONAL", scheme="UW", filt=0), 40),
+    ("duct17x17x12_UW_lad", lambda: G.duct(17, nx=12), dict(eq="HJ", gamma="LAD", scheme="UW", filt=0), 25),
 ]
 
 

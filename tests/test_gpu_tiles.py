@@ -34,6 +34,9 @@ CASES = [
     ("duct17x17x12_C6_lad", lambda: G.duct(17, nx=12),
      dict(eq="HJ", gamma="LAD", scheme="C6"), 20,
      [(1, 4, 4), (43, 12, 12), (86, 8, 8), (172, 12, 12)]),
+    ("cyl64x40_UW_lad", lambda: G.cylinder(64, 40, rout=6.0, dr1=1e-2, ratio=1.12, far=G.NEUMANN),
+     dict(eq="HJ", gamma="LAD", scheme="UW", filt=0), 30,
+     [(1, 4), (9, 13), (17, 26), (40, 64)]),
 ]
 
 
@@ -88,6 +91,15 @@ def test_tile_variants_match_oracle(fresh_solver, oracle, precision, name, build
         d = rel(g, results[0])
         say(f"   rel_linf vs first variant={d:.3e}")
         assert d <= (1e-13 if precision == "fp64" else 1e-6)
+
+
+def test_upwind_with_curvature_is_rejected(fresh_solver):
+    from paper_2111_09859_amd import _lib as L
+    spec = G.cylinder(48, 40, rout=6.0, dr1=1e-2, ratio=1.12)
+    prep = fresh_solver.prepare(spec, "UW", "fp64")
+    with pytest.raises(L.WDError):
+        fresh_solver.solve(prep, gmethod(eq="HJ", curv=1, scheme="UW", filt=0, tol=0.0,
+                                         max_iter=5))
 
 
 def test_tile_widths_out_of_range_are_rejected(fresh_solver):
