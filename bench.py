@@ -340,13 +340,18 @@ def run_ratios(args):
     cases = [("channel129x65_hj", G.channel(129, 65), dict(equation="HJ", gamma="LINEAR", eps=0.1)),
              ("channel129x65_lad", G.channel(129, 65), dict(equation="HJ", gamma="LAD", eps=0.2)),
              ("box129_eikonal", G.box2d(129), dict(equation="EIKONAL"))]
+    # the central Eikonal on the four-wall box grows without bound from its
+    # corners at alpha_f >= 0.48 with Courant number 1 (the oracle does the
+    # same); a stronger filter, alpha_f 0.45, keeps every scheme stable there
+    alpha = {"box129_eikonal": 0.45}
     out = {}
     for name, spec, kw in cases:
         row = {}
         for sch in ("UW", "E2", "E4", "C4", "C6"):
             filt = sch != "UW"
             prep = s.prepare(spec, sch, "fp64")
-            m = api.make_method(scheme=sch, filter=filt, alpha_f=0.48, tol=0.0, max_iter=300,
+            af = alpha.get(name, 0.48)
+            m = api.make_method(scheme=sch, filter=filt, alpha_f=af, tol=0.0, max_iter=300,
                                 precision="fp64", rk="RK4", **kw)
             s.solve(prep, m, check=False)               # warm-up (graphs, tables)
             torch.cuda.synchronize()
@@ -354,7 +359,7 @@ def run_ratios(args):
             s.solve(prep, m, check=False)
             torch.cuda.synchronize()
             per100 = (time.perf_counter() - t0) / 3.0
-            mc = api.make_method(scheme=sch, filter=filt, alpha_f=0.48, tol=1e-5, max_iter=50000,
+            mc = api.make_method(scheme=sch, filter=filt, alpha_f=af, tol=1e-5, max_iter=50000,
                                  precision="fp64", rk="RK4", **kw)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -374,7 +379,8 @@ def run_ratios(args):
             "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
             "data": "synthetic", "vs_baseline": None,
             "config": {"workload": "channel 129x65 (HJ standard, HJ LAD), box 129x129 (Eikonal); "
-                                   "UW without filter, E2/E4/C4/C6 with F10 alpha_f 0.48, RK4",
+                                   "UW without filter, E2/E4/C4/C6 with F10 alpha_f 0.48 "
+                                   "(0.45 on the Eikonal box), RK4",
                        "results": out}}
 
 
@@ -423,10 +429,15 @@ def run_serve(args):
         spec = G.build_request(req)
         p = s.prepare(spec, req["scheme"], "fp32")
         ids.append((srv.submit(p, method_for(spec, req["scheme"], "fp32", **over)), spec))
-    for k, (rid, _) in enumerate(ids):
-        srv.wait(rid, 1200.0)
-        print(f"[serve] request {k + 1}/{len(ids)} done at {time.perf_counter() - t0:.1f} s",
-              file=sys.stderr, flush=True)
+    # requests finish out of order (smallest first): report the count done
+    pending = [rid for rid, _ in ids]
+    while pending:
+        srv.wait(pending[0], 10.0)
+        pending = [rid for rid in pending if srv.poll(rid)["status"] == api.L.WD_PENDING]
+        print(f"[serve] {len(ids) - len(pending)}/{len(ids)} requests done at "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        if time.perf_counter() - t0 > 3600:
+            raise RuntimeError("serving run did not finish")
     th.join()
     wall = time.perf_counter() - t0
     lat, qwait, its, pts = [], [], [], 0

@@ -247,11 +247,16 @@ int wd_line_solve_host(int kind, int n, int periodic, int scheme,
 
 /* ---- serving (continuous batching) ---------------------------------- */
 /* A host thread owns a stream and a device arena of `budget_bytes`.  It
- * admits queued requests while their workspace fits in the arena and a slot
- * (of max_slots) is free, advances every admitted grid together, and
- * retires each one as soon as it stops.  Requests admitted while others run
- * join at the next iteration boundary.  Results do not depend on what else
- * runs (bitwise equal to wd_solve). */
+ * admits queued requests while a slot (of max_slots) is free, their
+ * workspace fits in the arena and the grid points iterated together stay
+ * within a point budget (8M points, environment WD_SERVER_POINTS; a lone
+ * request always runs).  Among the waiting requests that are free to run,
+ * one that has waited longer than 30 s (environment WD_SERVER_AGE) goes
+ * first, in arrival order, otherwise the smallest grid does.  Every admitted grid is advanced
+ * together and retired as soon as it stops; requests admitted while others
+ * run join at the next round boundary (16 iterations, environment
+ * WD_SERVER_ROUND).  Results do not depend on what else runs (bitwise
+ * equal to wd_solve). */
 int wd_server_create(wd_ctx *ctx, size_t budget_bytes, int max_slots,
                      wd_server **out);
 

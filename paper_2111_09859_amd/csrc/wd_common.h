@@ -11,7 +11,7 @@ constexpr int kThreads = 512;             // threads per workgroup (8 waves)
 constexpr int kPPT = 8;                   // max points per thread in a tile
 constexpr int kTileMax = kThreads * kPPT; // max points held by one tile
 constexpr int kMaxLev = 14;               // max PCR levels of a line system
-constexpr int kChunk = 4096;              // points per pointwise work item
+constexpr int kChunk = 1024;              // points per pointwise work item
 constexpr int kMaxLine = kTileMax;        // longest grid line supported
 
 // A tridiagonal line system whose matrix does not depend on the data

@@ -21,13 +21,13 @@ k_final(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
         const GridDev &g = grids[item.grid];
-        if (g.state->done) continue;
+        if (gmem(g.state)->done) continue;
         const long long q0 = (long long)item.tile * kChunk;
         for (int i = threadIdx.x; i < kChunk; i += kThreads) {
             const long long qq = q0 + i;
             if (qq >= g.N) break;
             const int q = (int)qq;
-            const T *src = static_cast<const T *>(stage == 0 ? g.phi : g.ps);
+            gptr<const T> src = gcast<const T>(stage == 0 ? g.phi : g.ps);
             T m9[9], g2, adv;
             metric_load<T>(g, q, m9);
             int idx[3];
@@ -35,21 +35,21 @@ k_final(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             if (g.uw) {
                 // the upwind baseline's advective term, formed by k_uwadv
                 // (this pass overwrites the stage value its stencil reads)
-                adv = static_cast<const T *>(g.P[1])[q];
-                g2 = static_cast<const T *>(g.uw2)[q];
+                adv = gcast<const T>(g.P[1])[q];
+                g2 = gcast<const T>(g.uw2)[q];
             } else {
                 T F3[3], U[3];
 #pragma unroll
                 for (int m = 0; m < 3; ++m)
-                    if (m < g.ndim) F3[m] = static_cast<const T *>(g.F[m])[q];
+                    if (m < g.ndim) F3[m] = gcast<const T>(g.F[m])[q];
                 grad_from<T>(g.ndim, m9, F3, U, g2);
                 adv = g2;
             }
-            const bool zero = wall_point(g, idx) || (g.mask && g.mask[q]);
+            const bool zero = wall_point(g, idx) || (g.mask && gmem(g.mask)[q]);
             const T phis = src[q];
             T S1, S2;
             metric_sums<T>(g.ndim, m9, S1, S2);
-            static_cast<T *>(g.ps)[q] =
+            gcast<T>(g.ps)[q] =
                 finish_point<T>(g, stage, q, zero, phis, g2, adv, (T)0, (T)0, (T)0, S1, S2,
                                 fin_load<T>(g, stage, q, phis));
         }
@@ -68,10 +68,10 @@ k_uwadv(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
         const GridDev &g = grids[item.grid];
-        if (g.state->done) continue;
-        const T *src = static_cast<const T *>(stage == 0 ? g.phi : g.ps);
-        T *adv = static_cast<T *>(g.P[1]);
-        T *u2 = static_cast<T *>(g.uw2);
+        if (gmem(g.state)->done) continue;
+        gptr<const T> src = gcast<const T>(stage == 0 ? g.phi : g.ps);
+        gptr<T> adv = gcast<T>(g.P[1]);
+        gptr<T> u2 = gcast<T>(g.uw2);
         const long long q0 = (long long)item.tile * kChunk;
         for (int i = threadIdx.x; i < kChunk; i += kThreads) {
             const long long qq = q0 + i;
@@ -100,9 +100,9 @@ k_resid(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
         const GridDev &g = grids[item.grid];
-        if (g.state->done) continue;
-        T *phi = static_cast<T *>(g.phi);
-        const T *ps = static_cast<const T *>(g.ps);
+        if (gmem(g.state)->done) continue;
+        gptr<T> phi = gcast<T>(g.phi);
+        gptr<const T> ps = gcast<const T>(g.ps);
         const long long q0 = (long long)item.tile * kChunk;
         double mx = 0.0, sm = 0.0;
         for (int i = threadIdx.x; i < kChunk; i += kThreads) {
@@ -116,8 +116,8 @@ k_resid(const GridDev *__restrict__ grids, const Item *__restrict__ items,
         }
         block_reduce(mx, sm, sh);
         if (threadIdx.x == 0) {
-            g.rpart[2 * item.tile] = mx;
-            g.rpart[2 * item.tile + 1] = sm;
+            gmem(g.rpart)[2 * item.tile] = mx;
+            gmem(g.rpart)[2 * item.tile + 1] = sm;
         }
         __syncthreads();
     }
@@ -135,10 +135,10 @@ k_face(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
         const GridDev &g = grids[item.grid];
-        if (g.state->done && target == 1) continue;
+        if (gmem(g.state)->done && target == 1) continue;
         const int code = g.xbc[face];
         if (code == XBC_NONE) continue;
-        T *f = static_cast<T *>(target ? g.ps : g.phi);
+        gptr<T> f = gcast<T>(target ? g.ps : g.phi);
         const long long nface = g.N / g.n[l];
         const long long k0 = (long long)item.tile * kChunk;
         const int ib = side ? g.n[l] - 1 : 0;
@@ -162,7 +162,7 @@ k_face(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                 idx[2] = ib;
             }
             const long long q = idx[0] + (long long)n0 * (idx[1] + (long long)g.n[1] * idx[2]);
-            if (wall_point(g, idx) || (g.mask && g.mask[q])) continue;
+            if (wall_point(g, idx) || (g.mask && gmem(g.mask)[q])) continue;
             const T a = f[q + in], b = f[q + 2 * in];
             f[q] = code == XBC_NEUMANN ? ((T)4 * a - b) / (T)3 : (T)2 * a - b;
         }
@@ -180,7 +180,7 @@ k_init(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
         const GridDev &g = grids[item.grid];
-        T *phi = static_cast<T *>(g.phi);
+        gptr<T> phi = gcast<T>(g.phi);
         if (item.tile == 0 && threadIdx.x == 0) {
             GridState st;
             st.done = 0;
@@ -198,7 +198,7 @@ k_init(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             if (q >= g.N) break;
             int idx[3];
             index_of(g, q, idx);
-            const bool zero = !g.warm || wall_point(g, idx) || (g.mask && g.mask[q]);
+            const bool zero = !g.warm || wall_point(g, idx) || (g.mask && gmem(g.mask)[q]);
             if (zero) phi[q] = (T)0;
         }
     }
@@ -210,11 +210,11 @@ k_finalize(const GridDev *__restrict__ grids, int ngrids)
 {
     __shared__ double sh[2 * kThreads / 64];
     const GridDev &g = grids[blockIdx.x];
-    if (g.state->done) return;
+    if (gmem(g.state)->done) return;
     double mx = 0.0, sm = 0.0;
     for (int i = threadIdx.x; i < g.nparts; i += kThreads) {
-        mx = nanmax(mx, g.rpart[2 * i]);
-        sm += g.rpart[2 * i + 1];
+        mx = nanmax(mx, gmem(g.rpart)[2 * i]);
+        sm += gmem(g.rpart)[2 * i + 1];
     }
     block_reduce(mx, sm, sh);
     if (threadIdx.x != 0) return;
@@ -222,8 +222,8 @@ k_finalize(const GridDev *__restrict__ grids, int ngrids)
     const int it = st.iter;
     const double l2 = sqrt(sm / (double)g.N);
     if (it < g.hist_cap) {
-        g.hist[2 * it] = mx;
-        g.hist[2 * it + 1] = l2;
+        gmem(g.hist)[2 * it] = mx;
+        gmem(g.hist)[2 * it + 1] = l2;
     }
     const int nit = it + 1;
     st.iter = nit;
@@ -324,7 +324,7 @@ __global__ void k_poisson_dist(const GridDev *__restrict__ gp, const double *__r
         for (int m = 0; m < g.ndim; ++m) {
             double u = 0.0;
             for (int l = 0; l < g.ndim; ++l)
-                u += (double)metric<T>(g, l, m, q) * static_cast<const double *>(g.F[l])[q];
+                u += (double)metric<T>(g, l, m, q) * gcast<const double>(g.F[l])[q];
             s += u * u;
         }
         const double gm = sqrt(s);

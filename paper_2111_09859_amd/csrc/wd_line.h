@@ -32,9 +32,49 @@
 
 namespace wd {
 
+// The buffers a GridDev points at are device global memory, but the
+// pointers reach the kernels as plain (generic) values read from a table,
+// for which the compiler emits FLAT memory instructions.  On this GPU those
+// also count against the LDS wait counter, so every wait for an LDS result
+// (each barrier of a line solve) would wait for all outstanding global loads
+// and stores as well.  Passing the pointers through the global address
+// space makes it emit global loads and stores, which LDS waits ignore.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+#else
+template <typename T>
+using gptr = T *;   // the host pass only parses device code
+#endif
+
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(T *p)
+{
+    return (gptr<T>)p;
+}
+
+// gcast<E>(p): the buffer p as a global pointer to E
+template <typename E, typename V>
+__device__ __forceinline__ gptr<E> gcast(V *p)
+{
+    return (gptr<E>)p;
+}
+
 template <typename T> struct V2;
 template <> struct V2<float> { using t = float2; };
 template <> struct V2<double> { using t = double2; };
+
+// element i of a global array of (left, right) pairs, as one 2-wide load
+template <typename T>
+__device__ __forceinline__ typename V2<T>::t ld2(gptr<const typename V2<T>::t> tab, long long i)
+{
+    typedef T vec2 __attribute__((ext_vector_type(2)));
+    const vec2 v = reinterpret_cast<gptr<const vec2>>(tab)[i];
+    typename V2<T>::t r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
 
 enum { EQ_EIK = 0, EQ_HJ = 1, EQ_POIS = 2 };
 enum { SCH_E2 = 0, SCH_E4 = 1, SCH_E6 = 2, SCH_C4 = 3, SCH_C6 = 4 };
@@ -215,7 +255,7 @@ __device__ inline bool zero_at(const GridDev &g, const Tile &tl, int l, int k, i
 {
     int idx[3];
     tile_index(g, tl, l, k, j, idx);
-    return wall_point(g, idx) || (g.mask && g.mask[q]);
+    return wall_point(g, idx) || (g.mask && gmem(g.mask)[q]);
 }
 
 template <int NP>
@@ -239,7 +279,7 @@ __device__ inline T metric(const GridDev &g, int l, int m, int q)
 {
     if (g.uniform)
         return l == m ? (T)g.invh[l] : (T)0;
-    return static_cast<const T *>(g.met)[(long long)(l * g.ndim + m) * g.N + q];
+    return gcast<const T>(g.met)[(long long)(l * g.ndim + m) * g.N + q];
 }
 
 // ---------------------------------------------------------------------
@@ -407,8 +447,8 @@ __device__ inline void pcr_load(Pcr<T, NP> &pc, const Pts<NP> &pt, const Tile &t
     using T2 = typename V2<T>::t;
     if constexpr (Pcr<T, NP>::kAll) {
         if (op.nlev == 0 || op.uniform) return;
-        const T2 *tab = static_cast<const T2 *>(op.tab);
-        const T *sc = static_cast<const T *>(op.scale);
+        gptr<const T2> tab = gcast<const T2>(op.tab);
+        gptr<const T> sc = gcast<const T>(op.scale);
         const int n = tl.n, nlev = op.nlev;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
@@ -417,7 +457,7 @@ __device__ inline void pcr_load(Pcr<T, NP> &pc, const Pts<NP> &pt, const Tile &t
             pc.sc[k] = sc[j];
 #pragma unroll
             for (int lev = 0; lev < kMaxLev; ++lev)
-                if (lev < nlev) pc.c[k][lev] = tab[(long long)lev * n + j];
+                if (lev < nlev) pc.c[k][lev] = ld2<T>(tab, (long long)lev * n + j);
         }
     }
 }
@@ -461,13 +501,13 @@ __device__ void pcr_multi(T (&v)[G][NP], int g, const Pts<NP> &pt, const Tile &t
         __syncthreads();
     }
     T *cur = A, *nxt = B;
-    const T2 *tab = static_cast<const T2 *>(op.tab);
+    gptr<const T2> tab = gcast<const T2>(op.tab);
     const bool uni = op.uniform;
     T2 cn[kAll ? 1 : NP];   // level in use (larger tiles)
     if (!kAll && !uni) {
 #pragma unroll
         for (int k = 0; k < NP; ++k)
-            if (pvalid(tl, k)) cn[k] = tab[pt.J[k]];
+            if (pvalid(tl, k)) cn[k] = ld2<T>(tab, pt.J[k]);
     }
     auto level = [&](int lev) {
         const int s = op.smod[lev];
@@ -485,7 +525,7 @@ __device__ void pcr_multi(T (&v)[G][NP], int g, const Pts<NP> &pt, const Tile &t
                     c = pc.c[k][lev];
                 } else {
                     c = cn[k];
-                    if (more) cn[k] = tab[(long long)(lev + 1) * n + j];
+                    if (more) cn[k] = ld2<T>(tab, (long long)(lev + 1) * n + j);
                 }
             }
             const int p = tid + k * kThreads;
@@ -523,7 +563,7 @@ __device__ void pcr_multi(T (&v)[G][NP], int g, const Pts<NP> &pt, const Tile &t
         T m;
         if (uni) m = (T)op.usc;
         else if constexpr (kAll) m = pc.sc[k];
-        else m = static_cast<const T *>(op.scale)[pt.J[k]];
+        else m = gcast<const T>(op.scale)[pt.J[k]];
 #pragma unroll
         for (int f = 0; f < G; ++f)
             if (f < g) v[f][k] *= m;
@@ -574,9 +614,9 @@ template <typename T>
 __device__ inline FinIn<T> fin_load(const GridDev &g, int stage, int q, T phis)
 {
     FinIn<T> r;
-    r.pn = stage == 0 ? phis : static_cast<const T *>(g.phi)[q];
-    r.dt = stage == 0 ? (T)0 : static_cast<const T *>(g.dt)[q];
-    r.acc = (g.rk == 1 && stage > 0) ? static_cast<const T *>(g.acc)[q] : (T)0;
+    r.pn = stage == 0 ? phis : gcast<const T>(g.phi)[q];
+    r.dt = stage == 0 ? (T)0 : gcast<const T>(g.dt)[q];
+    r.acc = (g.rk == 1 && stage > 0) ? gcast<const T>(g.acc)[q] : (T)0;
     return r;
 }
 
@@ -618,14 +658,14 @@ __device__ T finish_point(const GridDev &g, int stage, int q, bool zero, T phis,
         else
             den = (T)2 * kp * S1 * gmx + kp2 * kp2 * (gam + nu) * S2;
         dt = (T)g.sigma / den;
-        static_cast<T *>(g.dt)[q] = dt;
+        gcast<T>(g.dt)[q] = dt;
     } else {
         dt = in.dt;
     }
     const T pn = in.pn;
     T out;
     if (g.rk == 1) {
-        T *acc = static_cast<T *>(g.acc);
+        gptr<T> acc = gcast<T>(g.acc);
         if (stage == 0) {
             acc[q] = pn + dt / (T)6 * R;
             out = pn + dt / (T)2 * R;
@@ -805,16 +845,16 @@ k_cart(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
         const GridDev &g = grids[item.grid];
-        if (g.state->done) continue;
+        if (gmem(g.state)->done) continue;
         const Tile tl = decode_tile(g, l, item.tile);
         Pts<NP> pt;
         tile_points<NP>(tl, l, pt);
-        const T *src = static_cast<const T *>(stage == 0 ? g.phi : g.ps);
+        gptr<const T> src = gcast<const T>(stage == 0 ? g.phi : g.ps);
         const int per = g.periodic[l];
         const bool last = l == g.ndim - 1;
-        T *P0 = static_cast<T *>(g.P[0]);
-        T *P1 = static_cast<T *>(g.P[1]);
-        const T *P2 = static_cast<const T *>(g.P[2]);
+        gptr<T> P0 = gcast<T>(g.P[0]);
+        gptr<T> P1 = gcast<T>(g.P[1]);
+        gptr<const T> P2 = gcast<const T>(g.P[2]);
         Pcr<T, NP> pc;
         pcr_load(pc, pt, tl, g.dop[l]);
         T v0[NP], r[NP];
@@ -888,7 +928,7 @@ k_cart(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             S1 += (T)g.invh[d];
             S2 += (T)g.invh[d] * (T)g.invh[d];
         }
-        T *ps = static_cast<T *>(g.ps);
+        gptr<T> ps = gcast<T>(g.ps);
         bool zero[NP];
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
@@ -939,13 +979,13 @@ k_d1(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
         const GridDev &g = grids[item.grid];
-        if (g.state->done) continue;
+        if (gmem(g.state)->done) continue;
         const Tile tl = decode_tile(g, l, item.tile);
         Pts<NP> pt;
         tile_points<NP>(tl, l, pt);
         Pcr<T, NP> pc;
         pcr_load(pc, pt, tl, g.dop[l]);
-        const T *src = static_cast<const T *>(stage == 0 ? g.phi : g.ps);
+        gptr<const T> src = gcast<const T>(stage == 0 ? g.phi : g.ps);
         const int per = g.periodic[l];
         T r[NP];
 #pragma unroll
@@ -958,7 +998,7 @@ k_d1(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             if (pvalid(tl, k))
                 r[k] = deriv_rhs(g, A, threadIdx.x + k * kThreads, pt.J[k], tl.n, tl.lj, per, jump);
         if (stage == 0 && g.lad) {
-            T *S = static_cast<T *>(g.P[2]);
+            gptr<T> S = gcast<T>(g.P[2]);
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
                 if (!pvalid(tl, k)) continue;
@@ -970,7 +1010,7 @@ k_d1(const GridDev *__restrict__ grids, const Item *__restrict__ items,
         }
         __syncthreads();
         pcr_solve<T, NP>(r, pt, tl, g.dop[l], pc, A, B);
-        T *F = static_cast<T *>(g.F[l]);
+        gptr<T> F = gcast<T>(g.F[l]);
 #pragma unroll
         for (int k = 0; k < NP; ++k)
             if (pvalid(tl, k)) F[pt.Q[k]] = r[k];
@@ -1004,7 +1044,7 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
         const GridDev &g = grids[item.grid];
-        if (g.state->done) continue;
+        if (gmem(g.state)->done) continue;
         const Tile tl = decode_tile(g, l, item.tile);
         Pts<NP> pt;
         tile_points<NP>(tl, l, pt);
@@ -1012,10 +1052,10 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
         const int d = g.ndim;
         const int P = tl.P;
         const bool last = l == d - 1;
-        const T *src = static_cast<const T *>(stage == 0 ? g.phi : g.ps);
-        T *P0 = static_cast<T *>(g.P[0]);
-        T *P1 = static_cast<T *>(g.P[1]);
-        const T *P2 = static_cast<const T *>(g.P[2]);
+        gptr<const T> src = gcast<const T>(stage == 0 ? g.phi : g.ps);
+        gptr<T> P0 = gcast<T>(g.P[0]);
+        gptr<T> P1 = gcast<T>(g.P[1]);
+        gptr<const T> P2 = gcast<const T>(g.P[2]);
         Pcr<T, NP> pc;
         pcr_load(pc, pt, tl, g.dop[l]);
         // j, q of point k: from the unrolled table, or recomputed in loops
@@ -1036,7 +1076,7 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
         bool zr[NP];
         FinIn<T> fin[kPre ? NP : 1];
         const bool ladst = stage == 0 && g.lad;   // this pass updates the LAD field
-        T *Sl = static_cast<T *>(g.P[2]);
+        gptr<T> Sl = gcast<T>(g.P[2]);
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             zr[k] = true;
@@ -1046,7 +1086,7 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             if constexpr (kPre) {
 #pragma unroll
                 for (int m = 0; m < 3; ++m)
-                    if (m < d && !(FUSED && m == l)) Fv[k][m] = static_cast<const T *>(g.F[m])[q];
+                    if (m < d && !(FUSED && m == l)) Fv[k][m] = gcast<const T>(g.F[m])[q];
                 metric_load<T>(g, q, Mv[k]);
                 pl[k] = l > 0 ? P0[q] : (T)0;
                 pk[k] = (l > 0 && g.curv) ? P1[q] : (T)0;
@@ -1061,8 +1101,8 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             // upwind advective term of the stage value (Eqs. UW1-UW5): its
             // stencil reaches across tiles, so it is formed here, in a pass
             // that does not write the stage value, for the last pass's finish
-            T *adv = static_cast<T *>(g.P[1]);
-            T *u2 = static_cast<T *>(g.uw2);
+            gptr<T> adv = gcast<T>(g.P[1]);
+            gptr<T> u2 = gcast<T>(g.uw2);
 #pragma unroll UR
             for (int k = 0; k < NP; ++k) {
                 if (!pvalid(tl, k)) continue;
@@ -1144,7 +1184,7 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                         Sl[pt.Q[k]] = gauss9(A, threadIdx.x + k * kThreads, pt.J[k], tl.n, tl.lj, per);
                 // A is next written after the barrier that follows the field phase
             }
-            T *Fl = static_cast<T *>(g.F[l]);
+            gptr<T> Fl = gcast<T>(g.F[l]);
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
                 if (!pvalid(tl, k)) continue;
@@ -1192,7 +1232,7 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
 #pragma unroll
                     for (int m = 0; m < 3; ++m)
                         if (m < d) F3[m] = (FUSED && m == l) ? Cf[p]
-                                                             : static_cast<const T *>(g.F[m])[q];
+                                                             : gcast<const T>(g.F[m])[q];
                     grad_from<T>(d, m9, F3, U, g2);
                 }
                 if constexpr (kPre) g2s[k] = g2;
@@ -1256,7 +1296,7 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             }
             continue;
         }
-        T *ps = static_cast<T *>(g.ps);
+        gptr<T> ps = gcast<T>(g.ps);
         if constexpr (kPre) {
             T nv[NP];
 #pragma unroll
@@ -1268,8 +1308,8 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                 metric_sums<T>(d, Mv[k], S1, S2);
                 T g2 = g2s[k], adv = g2s[k];
                 if (g.uw) {   // formed by the fused pass along 0
-                    adv = static_cast<const T *>(g.P[1])[pt.Q[k]];
-                    g2 = static_cast<const T *>(g.uw2)[pt.Q[k]];
+                    adv = gcast<const T>(g.P[1])[pt.Q[k]];
+                    g2 = gcast<const T>(g.uw2)[pt.Q[k]];
                 }
                 nv[k] = finish_point<T>(g, stage, pt.Q[k], zr[k], sv[k], g2, adv, lap, kap,
                                         plad[k], S1, S2, fin[k]);
@@ -1311,12 +1351,12 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                 metric_load<T>(g, q, m9);
 #pragma unroll
                 for (int m = 0; m < 3; ++m)
-                    if (m < d) F3[m] = static_cast<const T *>(g.F[m])[q];
+                    if (m < d) F3[m] = gcast<const T>(g.F[m])[q];
                 grad_from<T>(d, m9, F3, U, g2);
                 T adv = g2;
                 if (g.uw) {   // formed by the fused pass along 0
-                    adv = static_cast<const T *>(g.P[1])[q];
-                    g2 = static_cast<const T *>(g.uw2)[q];
+                    adv = gcast<const T>(g.P[1])[q];
+                    g2 = gcast<const T>(g.uw2)[q];
                 }
                 T S1, S2;
                 metric_sums<T>(d, m9, S1, S2);
@@ -1360,13 +1400,13 @@ k_lad(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
         const GridDev &g = grids[item.grid];
-        if (g.state->done) continue;
+        if (gmem(g.state)->done) continue;
         const Tile tl = decode_tile(g, l, item.tile);
         Pts<NP> pt;
         tile_points<NP>(tl, l, pt);
         const int per = g.periodic[l];
-        T *S = static_cast<T *>(g.P[2]);
-        const T *src = phase == 0 ? static_cast<const T *>(g.phi) : S;
+        gptr<T> S = gcast<T>(g.P[2]);
+        gptr<const T> src = phase == 0 ? gcast<const T>(g.phi) : S;
         const bool last = l == g.ndim - 1;
         T sp[NP], w[NP];
 #pragma unroll
@@ -1461,14 +1501,14 @@ k_filter(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
         const GridDev &g = grids[item.grid];
-        if (g.state->done) continue;
+        if (gmem(g.state)->done) continue;
         const Tile tl = decode_tile(g, l, item.tile);
         Pts<NP> pt;
         tile_points<NP>(tl, l, pt);
         Pcr<T, NP> pc;
         pcr_load(pc, pt, tl, g.fop[l]);
-        T *ps = static_cast<T *>(g.ps);
-        T *phi = static_cast<T *>(g.phi);
+        gptr<T> ps = gcast<T>(g.ps);
+        gptr<T> phi = gcast<T>(g.phi);
         const int per = g.periodic[l];
         const bool last = l == g.ndim - 1;
         const bool resid = last && g.fused_resid;
@@ -1535,8 +1575,8 @@ k_filter(const GridDev *__restrict__ grids, const Item *__restrict__ items,
         if (resid) {
             block_reduce(mx, sm, reinterpret_cast<double *>(B));
             if (threadIdx.x == 0) {
-                g.rpart[2 * item.tile] = mx;
-                g.rpart[2 * item.tile + 1] = sm;
+                gmem(g.rpart)[2 * item.tile] = mx;
+                gmem(g.rpart)[2 * item.tile + 1] = sm;
             }
             __syncthreads();
         }

@@ -4,8 +4,9 @@
 // caller's budget and the batch tables.  Each request's footprint is its
 // grid region (fields, partial sums, history, stopping state).  Between
 // rounds of K pseudo iterations the thread retires grids that stopped,
-// admits queued requests in arrival order while a slot is free and their
-// region fits in the arena, and re-plans the batch; a grid joining a
+// admits queued requests (smallest first, long waiters first) while a slot
+// is free, their region fits in the arena and the points iterated together
+// stay within a budget, and re-plans the batch; a grid joining a
 // running batch starts at its own iteration 0 and every grid keeps its own
 // state, so results do not depend on what else is running.
 #include "wd_host.h"
@@ -26,6 +27,13 @@ static double now_s()
 }
 
 static size_t al256s(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static long long grid_points(const wd_grid_desc &d)
+{
+    long long N = 1;
+    for (int l = 0; l < d.ndim; ++l) N *= d.n[l];
+    return N;
+}
 
 // first-fit allocator over one device allocation, coalescing on release
 struct Arena {
@@ -113,6 +121,8 @@ struct wd_server {
     long long n_done = 0, n_iters = 0;
     int peak_active = 0;
     int round_iters = 16;
+    long long point_budget = 8LL << 20;   // grid points iterated together
+    double age_s = 30.0;                  // waiting longer than this: first
     std::vector<long long> last_set;
 };
 
@@ -145,6 +155,12 @@ static bool session_head(wd_server *srv, const Req &r)
 }
 
 // admission under the lock: arrival order, a free slot, room in the arena
+// Admission: cancelled requests leave the queue; then, while a slot is
+// free, requests join the running set -- first any that has waited longer
+// than age_s (in arrival order), otherwise the smallest waiting one -- as
+// long as the arena has room and the points iterated together stay within
+// point_budget (a lone request always runs).  A session's requests run in
+// submission order.
 static void admit_locked(wd_server *srv)
 {
     for (auto it = srv->queue.begin(); it != srv->queue.end();) {
@@ -154,33 +170,54 @@ static void admit_locked(wd_server *srv)
             it = srv->queue.erase(it);
             continue;
         }
-        if ((int)srv->active.size() >= srv->max_slots) break;
-        if (!session_head(srv, r)) {
-            ++it;
-            continue;
-        }
         if (r.bytes > srv->arena.size) {
             finish_locked(srv, r, WD_ERR_NO_MEMORY);
             it = srv->queue.erase(it);
             continue;
         }
+        ++it;
+    }
+    long long active_pts = 0;
+    for (long long id : srv->active) active_pts += grid_points(srv->reqs[id].desc);
+    const double t = now_s();
+    while ((int)srv->active.size() < srv->max_slots && !srv->queue.empty()) {
+        auto pick = srv->queue.end();
+        long long best = -1;
+        for (auto it = srv->queue.begin(); it != srv->queue.end(); ++it) {
+            Req &r = srv->reqs[*it];
+            if (!session_head(srv, r)) continue;
+            if (t - r.t_submit > srv->age_s) {   // waited long: first come first
+                pick = it;
+                break;
+            }
+            const long long pts = grid_points(r.desc);
+            if (best < 0 || pts < best) {
+                best = pts;
+                pick = it;
+            }
+        }
+        if (pick == srv->queue.end()) break;
+        Req &r = srv->reqs[*pick];
+        const long long pts = grid_points(r.desc);
+        if (!srv->active.empty() && active_pts + pts > srv->point_budget) break;
         size_t off = 0;
-        if (!srv->arena.alloc(r.bytes, off)) break;   // wait for memory, in order
+        if (!srv->arena.alloc(r.bytes, off)) break;   // wait for memory
         r.off = off;
         int rc = layout_grid(srv->ctx, r.desc, r.meth, r.phi,
                              static_cast<unsigned char *>(srv->arena_mem) + off, r.g, r.h);
         if (rc) {
             srv->arena.release(off, r.bytes);
             finish_locked(srv, r, rc);
-            it = srv->queue.erase(it);
+            srv->queue.erase(pick);
             continue;
         }
         r.running = true;
         r.fresh = true;
         r.t_admit = now_s();
         srv->active.push_back(r.id);
+        active_pts += pts;
         srv->peak_active = std::max(srv->peak_active, (int)srv->active.size());
-        it = srv->queue.erase(it);
+        srv->queue.erase(pick);
     }
 }
 
@@ -353,6 +390,10 @@ int wd_server_create(wd_ctx *ctx, size_t budget_bytes, int max_slots, wd_server 
     srv->arena.reset(budget_bytes);
     const char *k = std::getenv("WD_SERVER_ROUND");
     if (k) srv->round_iters = std::max(1, std::atoi(k));
+    const char *pb = std::getenv("WD_SERVER_POINTS");
+    if (pb) srv->point_budget = std::max(1LL, std::atoll(pb));
+    const char *ag = std::getenv("WD_SERVER_AGE");
+    if (ag) srv->age_s = std::max(0.0, std::atof(ag));
     srv->th = std::thread(server_loop, srv);
     *out = srv;
     return WD_OK;
