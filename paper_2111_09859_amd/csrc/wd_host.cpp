@@ -818,9 +818,21 @@ void prof_collect(wd_ctx *ctx)
 
 // ---------------------------------------------------------------------
 // issuing work
-static int nwg_for(wd_ctx *ctx, int fp64, int count)
+// Workgroups of one launch: a line pass gets as many as the chip holds at
+// once (its kernel's occupancy times the compute units), so a persistent
+// loop over more items never leaves a partial second round of workgroups;
+// pointwise passes get up to 4 (FP32) or 2 (FP64) per compute unit.
+static int nwg_for(wd_ctx *ctx, int fp64, int kind, int np, int count)
 {
-    int cap = ctx->cus * (fp64 ? 2 : 4);
+    int per = fp64 ? 2 : 4;
+    switch (kind) {
+    case PASS_CART: case PASS_D1: case PASS_D2: case PASS_D12: case PASS_FILTER: case PASS_LAD:
+        per = std::min(4, line_blocks_per_cu(kind, fp64, np));
+        break;
+    default:
+        break;
+    }
+    int cap = ctx->cus * per;
     cap = std::max(8, cap & ~7);
     return std::min(count, cap);
 }
@@ -833,7 +845,7 @@ void issue_list(wd_ctx *ctx, const Plan &P, int li, int stage, hipStream_t s)
     PendingLaunch pl;
     if (ctx->profile) prof_begin(ctx, pl, kind_name(L.kind), launch_bytes(P, L, stage), s);
     launch_pass(L.kind, P.fp64, L.np, P.d_grids, P.d_items + L.first, L.count, L.l, arg,
-                nwg_for(ctx, P.fp64, L.count), s);
+                nwg_for(ctx, P.fp64, L.kind, L.np, L.count), s);
     if (ctx->profile) prof_end(ctx, pl, s);
 }
 
@@ -851,7 +863,7 @@ void issue_faces(wd_ctx *ctx, const Plan &P, int target, hipStream_t s)
         PendingLaunch pl;
         if (ctx->profile) prof_begin(ctx, pl, "k_face", 0.0, s);
         launch_pass(PASS_FACE, P.fp64, 1, P.d_grids, P.d_items + L.first, L.count, f, target,
-                    nwg_for(ctx, P.fp64, L.count), s);
+                    nwg_for(ctx, P.fp64, L.kind, L.np, L.count), s);
         if (ctx->profile) prof_end(ctx, pl, s);
     }
 }
@@ -1063,7 +1075,8 @@ int poisson_convert(wd_ctx *ctx, const Plan &P, int i, void *aux, hipStream_t s)
             return fail(WD_ERR_INVALID_ARG, "internal: no item space for the Poisson passes");
         if (hipMemcpyAsync(d_it, it.data(), nt * sizeof(Item), hipMemcpyHostToDevice, s) != hipSuccess)
             return fail(WD_ERR_HIP, "poisson items upload failed");
-        launch_pass(PASS_D1, 1, tile_np(g, l), P.d_aux, d_it, nt, l, 0, nwg_for(ctx, 1, nt), s);
+        launch_pass(PASS_D1, 1, tile_np(g, l), P.d_aux, d_it, nt, l, 0,
+                    nwg_for(ctx, 1, PASS_D1, tile_np(g, l), nt), s);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(WD_ERR_HIP, "poisson pass failed");
     }
     GridDev w = g;  // metrics in the solve precision, F in FP64
@@ -1178,6 +1191,12 @@ int wd_ctx_create(int device, wd_ctx **out)
     }
     c->cus = prop.multiProcessorCount;
     std::snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
+    // occupancy of every line kernel, queried now rather than on a first
+    // launch that may sit inside a graph capture
+    for (int fp64 = 0; fp64 < 2; ++fp64)
+        for (int np = 1; np <= 8; np *= 2)
+            for (int kind : {PASS_CART, PASS_D1, PASS_D2, PASS_D12, PASS_FILTER, PASS_LAD})
+                (void)line_blocks_per_cu(kind, fp64, np);
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
@@ -1339,7 +1358,7 @@ int wd_compute_metrics(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, const 
                 break;
             }
             launch_pass(PASS_D1, 1, tile_np(g, l), dg, ditems, g.ntiles[l], l, 0,
-                        nwg_for(ctx, 1, g.ntiles[l]), s);
+                        nwg_for(ctx, 1, PASS_D1, tile_np(g, l), g.ntiles[l]), s);
             if (hipStreamSynchronize(s) != hipSuccess) rc = fail(WD_ERR_HIP, "metric pass failed");
         }
     }

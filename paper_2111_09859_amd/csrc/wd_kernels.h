@@ -29,7 +29,8 @@ void launch_pass(int kind, int fp64, int np, const GridDev *grids, const Item *i
 // line-pass launchers, one per value type and points per thread
 #define WD_LINE_LAUNCHER(name)                                                    \
     void name(int kind, const GridDev *grids, const Item *items, int nitems, int l, \
-              int stage, int nwg, hipStream_t s);
+              int stage, int nwg, hipStream_t s);                                   \
+    int name##_occ(int kind);
 WD_LINE_LAUNCHER(line_launch_f32_1)
 WD_LINE_LAUNCHER(line_launch_f32_2)
 WD_LINE_LAUNCHER(line_launch_f32_4)
@@ -39,6 +40,8 @@ WD_LINE_LAUNCHER(line_launch_f64_2)
 WD_LINE_LAUNCHER(line_launch_f64_4)
 WD_LINE_LAUNCHER(line_launch_f64_8)
 #undef WD_LINE_LAUNCHER
+// workgroups of a line pass's kernel that one compute unit holds at once
+int line_blocks_per_cu(int kind, int fp64, int np);
 void launch_finalize(const GridDev *grids, int ngrids, hipStream_t s);
 void launch_mirror(const GridDev *grids, int ngrids, hipStream_t s);
 void launch_convert(int src_fp64, int dst_fp64, const void *src, void *dst,

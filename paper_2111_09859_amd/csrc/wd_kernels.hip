@@ -386,6 +386,24 @@ void launch_pass(int kind, int fp64, int np, const GridDev *g, const Item *it, i
     }
 }
 
+int line_blocks_per_cu(int kind, int fp64, int np)
+{
+    if (fp64) {
+        switch (np) {
+        case 1: return line_launch_f64_1_occ(kind);
+        case 2: return line_launch_f64_2_occ(kind);
+        case 4: return line_launch_f64_4_occ(kind);
+        default: return line_launch_f64_8_occ(kind);
+        }
+    }
+    switch (np) {
+    case 1: return line_launch_f32_1_occ(kind);
+    case 2: return line_launch_f32_2_occ(kind);
+    case 4: return line_launch_f32_4_occ(kind);
+    default: return line_launch_f32_8_occ(kind);
+    }
+}
+
 void launch_mirror(const GridDev *g, int ngrids, hipStream_t s)
 {
     if (ngrids <= 0) return;

@@ -309,19 +309,19 @@ __device__ T deriv_rhs(const GridDev &g, const T *X, int p, int j, int n,
         if (r >= 2)
             s += b * (pval(X, p, j, 2, n, lj, jump) - pval(X, p, j, -2, n, lj, jump)) * (T)0.25;
         if (r >= 3)
-            s += c * (pval(X, p, j, 3, n, lj, jump) - pval(X, p, j, -3, n, lj, jump)) / (T)6;
+            s += c * (pval(X, p, j, 3, n, lj, jump) - pval(X, p, j, -3, n, lj, jump)) * (T)(1.0 / 6.0);
         return s;
     }
     const int p0 = p - j * lj;
     if (g.compact) {
         if (j == 0) {
             return (T)(-17.0 / 6.0) * X[p0] + (T)1.5 * X[p0 + lj]
-                   + (T)1.5 * X[p0 + 2 * lj] - X[p0 + 3 * lj] / (T)6;
+                   + (T)1.5 * X[p0 + 2 * lj] - X[p0 + 3 * lj] * (T)(1.0 / 6.0);
         }
         if (j == n - 1) {
             const int e = p0 + (n - 1) * lj;
             return -((T)(-17.0 / 6.0) * X[e] + (T)1.5 * X[e - lj]
-                     + (T)1.5 * X[e - 2 * lj] - X[e - 3 * lj] / (T)6);
+                     + (T)1.5 * X[e - 2 * lj] - X[e - 3 * lj] * (T)(1.0 / 6.0));
         }
         if (g.scheme == SCH_C6 && (j == 1 || j == n - 2))
             return (T)0.75 * (X[p + lj] - X[p - lj]);
@@ -338,16 +338,16 @@ __device__ T deriv_rhs(const GridDev &g, const T *X, int p, int j, int n,
         if (g.scheme == SCH_E2)
             v = ((T)-3 * f[0] + (T)4 * f[1] - f[2]) * (T)0.5;
         else if (k == 0)
-            v = ((T)-25 * f[0] + (T)48 * f[1] - (T)36 * f[2] + (T)16 * f[3] - (T)3 * f[4]) / (T)12;
+            v = ((T)-25 * f[0] + (T)48 * f[1] - (T)36 * f[2] + (T)16 * f[3] - (T)3 * f[4]) * (T)(1.0 / 12.0);
         else if (k == 1)
-            v = ((T)-3 * f[0] - (T)10 * f[1] + (T)18 * f[2] - (T)6 * f[3] + f[4]) / (T)12;
+            v = ((T)-3 * f[0] - (T)10 * f[1] + (T)18 * f[2] - (T)6 * f[3] + f[4]) * (T)(1.0 / 12.0);
         else
-            v = (f[0] - (T)8 * f[1] + (T)8 * f[3] - f[4]) / (T)12;
+            v = (f[0] - (T)8 * f[1] + (T)8 * f[3] - f[4]) * (T)(1.0 / 12.0);
         return hi ? -v : v;
     }
     T s = a * (X[p + lj] - X[p - lj]) * (T)0.5;
     if (r >= 2) s += b * (X[p + 2 * lj] - X[p - 2 * lj]) * (T)0.25;
-    if (r >= 3) s += c * (X[p + 3 * lj] - X[p - 3 * lj]) / (T)6;
+    if (r >= 3) s += c * (X[p + 3 * lj] - X[p - 3 * lj]) * (T)(1.0 / 6.0);
     return s;
 }
 
@@ -596,7 +596,7 @@ __device__ inline T face_value(const GridDev &g, int l, const T *X, int p, int j
     }
     if (code == XBC_NONE || zero) return v;
     const T a = X[p + in], b = X[p + 2 * in];
-    return code == XBC_NEUMANN ? ((T)4 * a - b) / (T)3 : (T)2 * a - b;
+    return code == XBC_NEUMANN ? ((T)4 * a - b) * (T)(1.0 / 3.0) : (T)2 * a - b;
 }
 
 // ---------------------------------------------------------------------
@@ -667,16 +667,16 @@ __device__ T finish_point(const GridDev &g, int stage, int q, bool zero, T phis,
     if (g.rk == 1) {
         gptr<T> acc = gcast<T>(g.acc);
         if (stage == 0) {
-            acc[q] = pn + dt / (T)6 * R;
-            out = pn + dt / (T)2 * R;
+            acc[q] = pn + dt * (T)(1.0 / 6.0) * R;
+            out = pn + dt * (T)0.5 * R;
         } else if (stage == 1) {
-            acc[q] = in.acc + dt / (T)3 * R;
-            out = pn + dt / (T)2 * R;
+            acc[q] = in.acc + dt * (T)(1.0 / 3.0) * R;
+            out = pn + dt * (T)0.5 * R;
         } else if (stage == 2) {
-            acc[q] = in.acc + dt / (T)3 * R;
+            acc[q] = in.acc + dt * (T)(1.0 / 3.0) * R;
             out = pn + dt * R;
         } else {
-            out = in.acc + dt / (T)6 * R;
+            out = in.acc + dt * (T)(1.0 / 6.0) * R;
         }
     } else {
         if (stage == 0)
@@ -684,7 +684,7 @@ __device__ T finish_point(const GridDev &g, int stage, int q, bool zero, T phis,
         else if (stage == 1)
             out = (T)0.75 * pn + (T)0.25 * (phis + dt * R);
         else
-            out = pn / (T)3 + (T)2 / (T)3 * (phis + dt * R);
+            out = pn * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * (phis + dt * R);
     }
     return zero ? (T)0 : out;
 }
