@@ -247,12 +247,13 @@ int wd_line_solve_host(int kind, int n, int periodic, int scheme,
 
 /* ---- serving (continuous batching) ---------------------------------- */
 /* A host thread owns a stream and a device arena of `budget_bytes`.  It
- * admits queued requests while a slot (of max_slots) is free, their
- * workspace fits in the arena and the grid points iterated together stay
- * within a point budget (8M points, environment WD_SERVER_POINTS; a lone
- * request always runs).  Among the waiting requests that are free to run,
- * one that has waited longer than 30 s (environment WD_SERVER_AGE) goes
- * first, in arrival order, otherwise the smallest grid does.  Every admitted grid is advanced
+ * admits queued requests while a slot (of max_slots) is free and their
+ * workspace fits in the arena.  Small grids (at most 1/16 of the point
+ * budget) go first, smallest first.  Larger grids are admitted while the
+ * larger grids iterated together stay within the point budget (8M points,
+ * environment WD_SERVER_POINTS; a lone request always runs): one that has
+ * waited longer than 30 s (environment WD_SERVER_AGE) first, in arrival
+ * order, otherwise the smallest.  Every admitted grid is advanced
  * together and retired as soon as it stops; requests admitted while others
  * run join at the next round boundary (16 iterations, environment
  * WD_SERVER_ROUND).  Results do not depend on what else runs (bitwise

@@ -4,9 +4,9 @@
 // caller's budget and the batch tables.  Each request's footprint is its
 // grid region (fields, partial sums, history, stopping state).  Between
 // rounds of K pseudo iterations the thread retires grids that stopped,
-// admits queued requests (smallest first, long waiters first) while a slot
-// is free, their region fits in the arena and the points iterated together
-// stay within a budget, and re-plans the batch; a grid joining a
+// admits queued requests (small grids first; larger ones smallest first,
+// long waiters first, within a point budget) while a slot is free and their
+// region fits in the arena, and re-plans the batch; a grid joining a
 // running batch starts at its own iteration 0 and every grid keeps its own
 // state, so results do not depend on what else is running.
 #include "wd_host.h"
@@ -156,11 +156,13 @@ static bool session_head(wd_server *srv, const Req &r)
 
 // admission under the lock: arrival order, a free slot, room in the arena
 // Admission: cancelled requests leave the queue; then, while a slot is
-// free, requests join the running set -- first any that has waited longer
-// than age_s (in arrival order), otherwise the smallest waiting one -- as
-// long as the arena has room and the points iterated together stay within
-// point_budget (a lone request always runs).  A session's requests run in
-// submission order.
+// free and the arena has room, requests join the running set.  Small ones
+// (at most 1/16 of the point budget) go first, smallest first, and do not
+// count against the budget: they cost little per iteration and finish
+// quickly.  Among the larger ones, any that has waited longer than age_s
+// goes first (in arrival order), otherwise the smallest, as long as the
+// larger grids iterated together stay within point_budget (a lone request
+// always runs).  A session's requests run in submission order.
 static void admit_locked(wd_server *srv)
 {
     for (auto it = srv->queue.begin(); it != srv->queue.end();) {
@@ -177,29 +179,42 @@ static void admit_locked(wd_server *srv)
         }
         ++it;
     }
-    long long active_pts = 0;
-    for (long long id : srv->active) active_pts += grid_points(srv->reqs[id].desc);
+    const long long small = std::max(1LL, srv->point_budget / 16);
+    long long big_pts = 0;
+    for (long long id : srv->active) {
+        const long long n = grid_points(srv->reqs[id].desc);
+        if (n > small) big_pts += n;
+    }
     const double t = now_s();
     while ((int)srv->active.size() < srv->max_slots && !srv->queue.empty()) {
-        auto pick = srv->queue.end();
-        long long best = -1;
+        auto pick_small = srv->queue.end(), pick_aged = srv->queue.end(),
+             pick_big = srv->queue.end();
+        long long best_small = -1, best_big = -1;
         for (auto it = srv->queue.begin(); it != srv->queue.end(); ++it) {
             Req &r = srv->reqs[*it];
             if (!session_head(srv, r)) continue;
-            if (t - r.t_submit > srv->age_s) {   // waited long: first come first
-                pick = it;
-                break;
-            }
             const long long pts = grid_points(r.desc);
-            if (best < 0 || pts < best) {
-                best = pts;
-                pick = it;
+            if (pts <= small) {
+                if (best_small < 0 || pts < best_small) {
+                    best_small = pts;
+                    pick_small = it;
+                }
+            } else if (t - r.t_submit > srv->age_s) {
+                if (pick_aged == srv->queue.end()) pick_aged = it;   // the earliest
+            } else if (best_big < 0 || pts < best_big) {
+                best_big = pts;
+                pick_big = it;
             }
         }
-        if (pick == srv->queue.end()) break;
+        auto pick = pick_small;
+        if (pick == srv->queue.end()) {
+            pick = pick_aged != srv->queue.end() ? pick_aged : pick_big;
+            if (pick == srv->queue.end()) break;
+            const long long pts = grid_points(srv->reqs[*pick].desc);
+            if (!srv->active.empty() && big_pts + pts > srv->point_budget) break;
+        }
         Req &r = srv->reqs[*pick];
         const long long pts = grid_points(r.desc);
-        if (!srv->active.empty() && active_pts + pts > srv->point_budget) break;
         size_t off = 0;
         if (!srv->arena.alloc(r.bytes, off)) break;   // wait for memory
         r.off = off;
@@ -215,7 +230,7 @@ static void admit_locked(wd_server *srv)
         r.fresh = true;
         r.t_admit = now_s();
         srv->active.push_back(r.id);
-        active_pts += pts;
+        if (pts > small) big_pts += pts;
         srv->peak_active = std::max(srv->peak_active, (int)srv->active.size());
         srv->queue.erase(pick);
     }

@@ -37,6 +37,14 @@ CASES = [
     ("cyl64x40_UW_lad", lambda: G.cylinder(64, 40, rout=6.0, dr1=1e-2, ratio=1.12, far=G.NEUMANN),
      dict(eq="HJ", gamma="LAD", scheme="UW", filt=0), 30,
      [(1, 4), (9, 13), (17, 26), (40, 64)]),
+    # Cartesian grids whose lines do not fill a tile row: ragged tiles of
+    # odd widths, lines shorter than a workgroup, 3D with an explicit scheme
+    ("duct33x33x40_E4_lad", lambda: G.duct(33, nx=40),
+     dict(eq="HJ", gamma="LAD", scheme="E4"), 20,
+     [(8, 8, 8), (3, 5, 7), (1, 2, 2), (43, 33, 33)]),
+    ("box100_C6_hj", lambda: G.box2d(100),
+     dict(eq="HJ", gamma="LINEAR", scheme="C6"), 20,
+     [(8, 8), (6, 3), (1, 1), (40, 40)]),
 ]
 
 
