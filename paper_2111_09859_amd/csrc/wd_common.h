@@ -58,7 +58,10 @@ struct GridDev {
     int uniform;
     double invh[3];
     double jump[3];           // coordinate seam jump (metric helper only)
-    const void *met;          // FIELDS metrics (T), ndim*ndim SoA
+    const void *met;          // FIELDS metrics (T), point-major: the ndim*ndim
+                              // values of a point together, [q][l*ndim + m]
+    const void *met_src;      // the caller's field-major metrics [l*ndim + m][q],
+                              // copied into met by the initial pass
     const unsigned char *mask;
 
     // method

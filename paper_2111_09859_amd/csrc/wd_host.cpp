@@ -302,6 +302,8 @@ size_t grid_region_bytes(const wd_grid_desc &d, const wd_method &m)
     b += f;                                      // ps
     if (m.rk == WD_RK4) b += f;                  // acc
     b += f;                                      // dt
+    if (d.metric_mode == WD_METRIC_FIELDS)
+        b += (size_t)d.ndim * d.ndim * f;        // point-major metrics
     if (grid_mode(d, m) == MODE_GENERAL) b += (size_t)d.ndim * f;  // F_l
     b += 3 * f;                                  // partial sums / LAD field
     if (m.scheme == WD_UW && m.equation != WD_EQ_POISSON) b += f;   // upwind |U|^2
@@ -422,7 +424,7 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     }
     g.uniform = d.metric_mode == WD_METRIC_UNIFORM;
     for (int l = 0; l < 3; ++l) g.invh[l] = (g.uniform && l < d.ndim) ? 1.0 / d.h[l] : 0.0;
-    g.met = d.metrics;
+    g.met_src = d.metrics;
     g.mask = d.mask;
     g.eq = m.equation;
     g.lad = m.equation == WD_EQ_HJ && m.gamma == WD_GAMMA_LAD;
@@ -472,6 +474,7 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     g.ps = take(f);
     g.acc = m.rk == WD_RK4 ? take(f) : nullptr;
     g.dt = take(f);
+    if (!g.uniform) g.met = take((size_t)d.ndim * d.ndim * f);
     if (g.mode == MODE_GENERAL)
         for (int l = 0; l < d.ndim; ++l) g.F[l] = take(f);
     for (int k = 0; k < 3; ++k) g.P[k] = take(f);
@@ -1563,6 +1566,9 @@ int wd_poisson_distance(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, int p
     if (dist != phip &&
         hipMemcpyAsync(dist, phip, (size_t)P.grids[0].N * S, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return fail(WD_ERR_HIP, "copy failed");
+    const GridDev &g = P.grids[0];
+    if (!g.uniform)   // no initial pass here: the point-major metrics directly
+        launch_met_points(P.fp64, g.met_src, const_cast<void *>(g.met), g.N, g.ndim * g.ndim, s);
     return poisson_convert(ctx, P, 0, nullptr, s);
 }
 

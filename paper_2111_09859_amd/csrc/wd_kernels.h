@@ -44,6 +44,8 @@ WD_LINE_LAUNCHER(line_launch_f64_8)
 int line_blocks_per_cu(int kind, int fp64, int np);
 void launch_finalize(const GridDev *grids, int ngrids, hipStream_t s);
 void launch_mirror(const GridDev *grids, int ngrids, hipStream_t s);
+// field-major metrics [c][q] into the point-major array [q][c] (dd = ndim^2)
+void launch_met_points(int fp64, const void *src, void *dst, long long N, int dd, hipStream_t s);
 void launch_convert(int src_fp64, int dst_fp64, const void *src, void *dst,
                     long long n, hipStream_t s);
 void launch_invert(const double *J, void *out, int out_fp64, int d,

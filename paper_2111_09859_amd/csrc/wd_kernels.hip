@@ -8,6 +8,8 @@
 #include "wd_line.h"
 #include "wd_kernels.h"
 
+#include <algorithm>
+
 namespace wd {
 
 // Pointwise stage finish for general grids without a second derivative
@@ -170,7 +172,9 @@ k_face(const GridDev *__restrict__ grids, const Item *__restrict__ items,
 }
 
 // Initial field (Sec. 3.5): zero (cold) or the given guess, walls/solids
-// set to zero; resets the grid's stopping state.
+// set to zero; resets the grid's stopping state; copies the caller's
+// field-major metrics into the grid's point-major array (the passes read a
+// point's metrics with one or two wide loads).
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_init(const GridDev *__restrict__ grids, const Item *__restrict__ items,
@@ -200,6 +204,20 @@ k_init(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             index_of(g, q, idx);
             const bool zero = !g.warm || wall_point(g, idx) || (g.mask && gmem(g.mask)[q]);
             if (zero) phi[q] = (T)0;
+        }
+        if (!g.uniform) {
+            // element e of this chunk's point-major block: point e / dd,
+            // component e % dd (coalesced writes)
+            const int dd = g.ndim * g.ndim;
+            gptr<const T> src = gcast<const T>(g.met_src);
+            gptr<T> dst = gcast<T>(const_cast<void *>(g.met));
+            const long long e0 = q0 * dd;
+            const long long e1 = min(g.N, q0 + kChunk) * dd;
+            for (long long e = e0 + threadIdx.x; e < e1; e += kThreads) {
+                const long long q = e / dd;
+                const int c = (int)(e - q * dd);
+                dst[e] = src[(long long)c * g.N + q];
+            }
         }
     }
 }
@@ -252,6 +270,18 @@ k_finalize(const GridDev *__restrict__ grids, int ngrids)
     }
     *g.state = st;
     *g.mirror = st;   // the host reads the contiguous mirrors after each round
+}
+
+// field-major metrics [c][q] -> point-major [q][c] (dd components)
+template <typename T>
+__global__ void k_met_points(const T *__restrict__ src, T *__restrict__ dst, long long N, int dd)
+{
+    const long long n = N * dd;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long q = e / dd;
+        dst[e] = src[(e - q * dd) * N + q];
+    }
 }
 
 // copy every grid's state into the batch mirrors (after a re-plan)
@@ -402,6 +432,19 @@ int line_blocks_per_cu(int kind, int fp64, int np)
     case 4: return line_launch_f32_4_occ(kind);
     default: return line_launch_f32_8_occ(kind);
     }
+}
+
+void launch_met_points(int fp64, const void *src, void *dst, long long N, int dd, hipStream_t s)
+{
+    if (N <= 0 || !src || !dst) return;
+    const long long n = N * dd;
+    const int nb = (int)std::min<long long>((n + kThreads - 1) / kThreads, 4096);
+    if (fp64)
+        hipLaunchKernelGGL(k_met_points<double>, dim3(nb), dim3(kThreads), 0, s,
+                           static_cast<const double *>(src), static_cast<double *>(dst), N, dd);
+    else
+        hipLaunchKernelGGL(k_met_points<float>, dim3(nb), dim3(kThreads), 0, s,
+                           static_cast<const float *>(src), static_cast<float *>(dst), N, dd);
 }
 
 void launch_mirror(const GridDev *g, int ngrids, hipStream_t s)

@@ -279,7 +279,8 @@ __device__ inline T metric(const GridDev &g, int l, int m, int q)
 {
     if (g.uniform)
         return l == m ? (T)g.invh[l] : (T)0;
-    return gcast<const T>(g.met)[(long long)(l * g.ndim + m) * g.N + q];
+    const int d = g.ndim;
+    return gcast<const T>(g.met)[(long long)q * (d * d) + l * d + m];
 }
 
 // ---------------------------------------------------------------------
@@ -719,12 +720,29 @@ __device__ inline void metric_sums(int d, const T *m, T &S1, T &S2)
 template <typename T>
 __device__ inline void metric_load(const GridDev &g, int q, T *m)
 {
-    const int d = g.ndim;
+    if (g.uniform) {
 #pragma unroll
-    for (int l = 0; l < 3; ++l)
+        for (int l = 0; l < 3; ++l)
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            if (l < d && c < d) m[3 * l + c] = metric<T>(g, l, c, q);
+            for (int c = 0; c < 3; ++c)
+                m[3 * l + c] = (l == c && l < g.ndim) ? (T)g.invh[l] : (T)0;
+        return;
+    }
+    // a point's metrics are contiguous: constant offsets, so the loads merge
+    gptr<const T> a = gcast<const T>(g.met);
+    if (g.ndim == 2) {
+        a += (long long)q * 4;
+        m[0] = a[0];
+        m[1] = a[1];
+        m[3] = a[2];
+        m[4] = a[3];
+    } else {
+        a += (long long)q * 9;
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) m[3 * l + c] = a[3 * l + c];
+    }
 }
 
 // contravariant pieces U_m = sum_l xi_{l,m} F_l and g2 = |U|^2
