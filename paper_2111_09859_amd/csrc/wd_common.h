@@ -68,6 +68,8 @@ struct GridDev {
     int eq, lad, curv, scheme, rk, need_lap, filter, fused_resid;
     int fuse_faces;           // extrapolated faces all normal to the last
                               // direction: applied inside its passes
+    int fnext;                // the finishing pass also forms the next
+                              // stage's F of the last direction
     int stages;
     int uw;                   // first-order upwind advective term (Eqs. UW1-UW5)
     double eps, C, nu0, eps0, sigma, tol;

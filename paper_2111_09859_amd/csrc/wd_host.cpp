@@ -448,6 +448,9 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     // (that direction's tiles hold whole lines); otherwise face kernels
     g.fuse_faces = has_x && only_last && !(g.mode == MODE_GENERAL && !g.need_lap);
     g.fused_resid = m.filter && (!has_x || g.fuse_faces);
+    // a general grid's finishing pass holds whole lines of the new stage
+    // value (no face pass after it) and forms the next stage's F there
+    g.fnext = g.mode == MODE_GENERAL && g.need_lap && (!has_x || g.fuse_faces);
     g.eps = m.eps;
     g.C = m.c_lad;
     g.nu0 = m.nu0;
@@ -631,6 +634,12 @@ void build_items(Plan &P)
     // fused pass along 0, then pass 2 along l >= 1 (the last one finishes)
     line_slot(P.d1[0], PASS_D1, 0, 0, gen_eik_f);
     for (int l = 1; l < 3; ++l) line_slot(P.d1[l], PASS_D1, l, 0, gen_f);
+    // stages > 0: the finishing pass of the previous stage formed F_{d-1}
+    line_slot(P.d1n[0], PASS_D1, 0, 0, gen_eik_f);
+    for (int l = 1; l < 3; ++l)
+        line_slot(P.d1n[l], PASS_D1, l, 0, [&gen_f, l](const GridDev &g) {
+            return gen_f(g) && !(g.fnext && l == g.ndim - 1);
+        });
     line_slot(P.d12, PASS_D12, 0, 0, gen_lap);
     P.d2[0] = Slot();
     for (int l = 1; l < 3; ++l) line_slot(P.d2[l], PASS_D2, l, 0, gen_lap);
@@ -734,6 +743,7 @@ static double point_accesses(const GridDev &g, int kind, int l, int stage)
         if (!last) a += np;
         else a += finish(0);
         if (stage == 0 && g.lad) a += last ? 1 : 2;   // LAD field smoothed in place
+        if (last && g.fnext && stage < g.stages - 1) a += 1;   // next stage's F_l out
         return a;
     }
     case PASS_D12:
@@ -879,7 +889,7 @@ void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s)
     for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.lad1[l], 1, s);
     for (int st = 0; st < P.stages; ++st) {
         for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.cart[l], st, s);
-        for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.d1[l], st, s);
+        for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, st == 0 ? P.d1[l] : P.d1n[l], st, s);
         issue_slot(ctx, P, P.d12, st, s);
         for (int l = 1; l < P.maxdim; ++l) issue_slot(ctx, P, P.d2[l], st, s);
         issue_list(ctx, P, P.uwadv, st, s);

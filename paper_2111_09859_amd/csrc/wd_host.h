@@ -88,7 +88,7 @@ struct Plan {
     long long items_cap = 0;
     std::vector<Item> items;
     std::vector<ItemList> lists;
-    Slot cart[3], d1[3], d12, d2[3], filt[3], lad0[3], lad1[3];
+    Slot cart[3], d1[3], d1n[3], d12, d2[3], filt[3], lad0[3], lad1[3];   // d1n: stages > 0
     int face[6], face_init[6];
     int fin = 0, resid = 0, init = 0, uwadv = 0;
     GridDev *d_grids = nullptr;

@@ -1315,6 +1315,10 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             continue;
         }
         gptr<T> ps = gcast<T>(g.ps);
+        // the next stage's F_l = D_l of the new stage value, from the
+        // tile's whole lines (the next stage's pass along l skips the grid)
+        const bool fnext = g.fnext && stage < g.stages - 1;
+        const T jump = (T)g.jump[l];
         if constexpr (kPre) {
             T nv[NP];
 #pragma unroll
@@ -1346,6 +1350,25 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
 #pragma unroll
             for (int k = 0; k < NP; ++k)
                 if (pvalid(tl, k)) ps[pt.Q[k]] = nv[k];
+            if (fnext) {
+                __syncthreads();   // the face step's reads of A are done
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    if (pvalid(tl, k)) A[threadIdx.x + k * kThreads] = nv[k];
+                __syncthreads();
+                T fl[NP];
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    if (pvalid(tl, k))
+                        fl[k] = deriv_rhs(g, A, threadIdx.x + k * kThreads, pt.J[k], tl.n, tl.lj,
+                                          per, jump);
+                __syncthreads();
+                pcr_solve<T, NP>(fl, pt, tl, g.dop[l], pc, A, B);
+                gptr<T> Fl = gcast<T>(g.F[l]);
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    if (pvalid(tl, k)) Fl[pt.Q[k]] = fl[k];
+            }
         } else {
             // park the partial sums in LDS (own points only) and finish the
             // stage point by point, keeping the unrolled state small
@@ -1394,8 +1417,27 @@ k_d2(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                     const int p = threadIdx.x + k * kThreads;
                     int j, q;
                     JQ(k, j, q);
-                    ps[q] = face_value(g, l, A, p, j, tl.n, tl.lj, A[p], B[p] != (T)0);
+                    const T fv = face_value(g, l, A, p, j, tl.n, tl.lj, A[p], B[p] != (T)0);
+                    ps[q] = fv;
+                    B[p] = fv;   // own slot: read just above by this thread only
                 }
+            }
+            if (fnext) {
+                // the new stage values sit in A (or, after the face step, in B)
+                const T *X = g.fuse_faces ? B : A;
+                __syncthreads();
+                T fl[NP];
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    if (pvalid(tl, k))
+                        fl[k] = deriv_rhs(g, X, threadIdx.x + k * kThreads, pt.J[k], tl.n, tl.lj,
+                                          per, jump);
+                __syncthreads();
+                pcr_solve<T, NP>(fl, pt, tl, g.dop[l], pc, A, B);
+                gptr<T> Fl = gcast<T>(g.F[l]);
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    if (pvalid(tl, k)) Fl[pt.Q[k]] = fl[k];
             }
         }
         __syncthreads();
