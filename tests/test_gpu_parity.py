@@ -83,6 +83,11 @@ CASES = [
     ("cyl48x40_E4_lin_curv_neumann", lambda: G.cylinder(48, 40, rout=6.0, dr1=1e-2, ratio=1.12,
                                                          far=G.NEUMANN),
      dict(eq="HJ", curv=1, scheme="E4"), 40),
+    # annulus between two walls: no extrapolated face, so the finishing pass
+    # forms the next stage's F from values it holds in LDS before any face step
+    ("cyl48x40_E6_lad_walls", lambda: G.cylinder(48, 40, rout=6.0, dr1=1e-2, ratio=1.12,
+                                                  far=G.WALL),
+     dict(eq="HJ", gamma="LAD", scheme="E6"), 40),
     ("ell40x33_E6_eik", lambda: G.ellipse(40, 33, axis_ratio=2.0, ratio=1.15, rout=5.0, dr1=1e-2),
      dict(eq="EIKONAL", scheme="E6"), 40),
     ("ell40x33_C6_poisson", lambda: G.ellipse(40, 33, axis_ratio=2.0, ratio=1.15, rout=5.0, dr1=1e-2),

@@ -24,6 +24,10 @@ CASES = [
     ("cyl64x40_C6_lad_curv", lambda: G.cylinder(64, 40, rout=6.0, dr1=1e-2, ratio=1.12),
      dict(eq="HJ", gamma="LAD", curv=1, scheme="C6"), 30,
      [(1, 4), (9, 13), (17, 26), (40, 64)]),
+    ("cyl64x40_C6_hj_walls", lambda: G.cylinder(64, 40, rout=6.0, dr1=1e-2, ratio=1.12,
+                                                 far=G.WALL),
+     dict(eq="HJ", scheme="C6", eps=0.2), 30,
+     [(1, 4), (9, 13), (17, 26), (40, 64)]),
     ("cyl64x40_E6_poisson_neumann", lambda: G.cylinder(64, 40, rout=6.0, dr1=1e-2, ratio=1.12,
                                                        far=G.NEUMANN),
      dict(eq="POISSON", scheme="E6"), 20,
