@@ -80,6 +80,11 @@ def lib():
         L.wdo_poisson_distance.argtypes = [C.POINTER(_Grid), C.c_int, dp, dp, dp]
         L.wdo_brute_force.argtypes = [C.c_int, C.c_int, dp, C.c_int, dp, dp]
         L.wdo_brute_force.restype = None
+        L.wdo_signed_distance.argtypes = [C.c_long, C.POINTER(C.c_ubyte), dp, dp, dp]
+        L.wdo_signed_distance.restype = None
+        L.wdo_levelset_advance.argtypes = [C.POINTER(_Grid), C.c_double, C.c_double, C.c_int, dp]
+        L.wdo_level_length.argtypes = [C.POINTER(_Grid), dp, C.c_double]
+        L.wdo_level_length.restype = C.c_double
         _lib = L
     return _lib
 
@@ -235,3 +240,34 @@ def brute_force(points, wall):
     lib().wdo_brute_force(ndim, points.shape[0], _ptr(points), wall.shape[0],
                           _ptr(wall), _ptr(out))
     return out
+
+
+def signed_distance(solid, d_solid, d_gas):
+    """Sec. 5.5: phi_s = d_solid on solid points, -d_gas elsewhere."""
+    solid = np.ascontiguousarray(solid, dtype=np.uint8)
+    d_solid = np.ascontiguousarray(d_solid, dtype=np.float64)
+    d_gas = np.ascontiguousarray(d_gas, dtype=np.float64)
+    out = np.empty_like(d_solid)
+    lib().wdo_signed_distance(out.size, solid.ctypes.data_as(C.POINTER(C.c_ubyte)),
+                              _ptr(d_solid), _ptr(d_gas), _ptr(out))
+    return out
+
+
+def levelset_advance(spec, phi, speed, dt, nsteps):
+    """Eq. levelset (right-hand side read as 0), RK4, zero-gradient faces."""
+    og = OracleGrid(spec)
+    phi = np.array(phi, dtype=np.float64, copy=True)
+    rc = lib().wdo_levelset_advance(C.byref(og.g), speed, dt, nsteps, _ptr(phi))
+    if rc:
+        raise ValueError("wdo_levelset_advance failed")
+    return phi
+
+
+def level_length(spec, phi, level):
+    """Length of the 2D iso-line phi = level (marching squares)."""
+    og = OracleGrid(spec)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    v = lib().wdo_level_length(C.byref(og.g), _ptr(phi), level)
+    if v < 0:
+        raise ValueError("wdo_level_length needs a uniform 2D grid")
+    return v

@@ -106,6 +106,21 @@ int wdo_poisson_distance(const wdo_grid *g, int scheme, const double *met,
                          const double *phip, double *d);
 
 /* Brute-force nearest distance from npts points to nwall wall samples. */
+/* Level-set burnback (Sec. 5.5, Eq. levelset with its right-hand side
+ * read as 0): phi_s is the signed distance, positive on the solid
+ * (propellant) side, negative in the gas; uniform grids only.
+ *   wdo_signed_distance: phi_s = d_solid where solid[q], else -d_gas.
+ *   wdo_levelset_advance: nsteps classical RK4 steps of
+ *     d phi_s / dt = -F |grad phi_s| (upwind switch of Eqs. UW3-UW5),
+ *     zero-gradient faces after every stage.
+ *   wdo_level_length: 2D length of the iso-line phi_s = level (linear
+ *     interpolation on cell edges, saddles split by the cell mean).    */
+void wdo_signed_distance(long n, const unsigned char *solid, const double *d_solid,
+                         const double *d_gas, double *phi_s);
+int wdo_levelset_advance(const wdo_grid *g, double speed, double dt, int nsteps,
+                         double *phi);
+double wdo_level_length(const wdo_grid *g, const double *phi, double level);
+
 void wdo_brute_force(int ndim, int npts, const double *pts, int nwall,
                      const double *wall, double *d);
 

@@ -184,6 +184,34 @@ def star_port_radius(theta, step: int = 0, r0: float = 0.2, amp: float = 0.3,
     return r0 * (1.0 + amp * np.cos(lobes * theta)) + step * recession
 
 
+def square(n: int = 65, half: float = 1.0, bc: int = NEUMANN) -> GridSpec:
+    """Cartesian n x n grid on [-half, half]^2 with the same kind on every
+    face (a field's domain for the level-set march and the iso-lines)."""
+    h = 2.0 * half / (n - 1)
+    return GridSpec("square", 2, (n, n, 1), ((bc, bc), (bc, bc), (WALL, WALL)),
+                    h=(h, h, 1.0), meta={"half": half})
+
+
+def square_xy(spec: GridSpec):
+    """Node coordinates (X, Y) of a `square` grid, arrays of spec.shape."""
+    half = spec.meta["half"]
+    x = -half + np.arange(spec.n[0]) * spec.h[0]
+    y = -half + np.arange(spec.n[1]) * spec.h[1]
+    return np.meshgrid(x, y)
+
+
+def star_grain_solid(n: int = 512, step: int = 0, **kw) -> GridSpec:
+    """The star grain's propellant side: the port (r < r_k(theta)) is masked,
+    so its boundary is the wall, and the outer faces have zero normal
+    gradient; the distance solved here is the solid-side half of the signed
+    distance of the burnback (Sec. 5.5)."""
+    g = star_grain(n, step, **kw)
+    port = (1 - g.mask).astype(np.uint8)
+    return GridSpec("star_grain_solid", 2, g.n,
+                    ((NEUMANN, NEUMANN), (NEUMANN, NEUMANN), (WALL, WALL)),
+                    h=g.h, mask=port, meta=dict(g.meta))
+
+
 def star_grain(n: int = 512, step: int = 0, **kw) -> GridSpec:
     """Cartesian n x n grid on [-0.5, 0.5]^2; the star-shaped port
     r < r_k(theta) is fluid, everything else is solid propellant (mask 1).

@@ -406,3 +406,73 @@ def test_uw_eikonal_box_first_order(oracle):
         errs.append(np.abs(phi - spec.exact).max())
         assert np.abs(phi - phi.T).max() == 0.0
     assert 1.7 < errs[0] / errs[1] < 2.3
+
+
+# ---- level-set burnback (Sec. 5.5) ------------------------------------
+
+def test_level_length_line_and_circle(oracle):
+    """Iso-line lengths: a straight level of a linear field is the domain
+    width exactly; the level 0 of r - R is 2 pi R up to the O(h^2) chords."""
+    spec = G.square(101, 1.0)
+    X, Y = G.square_xy(spec)
+    width = 2.0
+    for c in (0.013, -0.4):
+        assert abs(oracle.level_length(spec, Y - c, 0.0) - width) < 1e-12
+    spec = G.square(401, 1.0)
+    X, Y = G.square_xy(spec)
+    r = np.hypot(X, Y)
+    for R in (0.3, 0.71):
+        L = oracle.level_length(spec, r - R, 0.0)
+        assert abs(L / (2 * np.pi * R) - 1) < 2e-4
+    # a saddle cell (corners +, -, +, - counter-clockwise): the sign of the
+    # cell mean decides which corners the two segments cut off
+    one = G.square(2, 0.5)
+    v = np.array([[0.9, -1.1], [-1.1, 0.9]])        # rows y, columns x
+    assert abs(oracle.level_length(one, v, 0.0) - 0.9 * np.sqrt(2)) < 1e-14
+    assert abs(oracle.level_length(one, v + 0.2, 0.0) - np.sqrt(2) * 2 * 0.45) < 1e-14
+
+
+def test_levelset_planar_front_moves_at_speed(oracle):
+    """phi = x - c with speed F: the upwind differences of a linear field
+    are exact, RK4 integrates the constant rate exactly, so away from the
+    two faces' zero-gradient rows (whose influence spreads from the upwind
+    face) phi = x - c - F t to rounding."""
+    spec = G.square(81, 1.0)
+    X, Y = G.square_xy(spec)
+    F, h = 0.3, spec.h[0]
+    dt = 0.5 * h / F
+    n = 40
+    phi = oracle.levelset_advance(spec, X - 0.1, F, dt, n)
+    t = n * dt
+    far = (X > -1.0 + F * t + 1.0) & (X < 0.9)
+    assert np.abs(phi - (X - 0.1 - F * t))[far].max() < 1e-12
+
+
+def test_levelset_expanding_circle(oracle):
+    """A port of radius R0 (phi = r - R0, positive in the solid) burns
+    outward: after time t its boundary is the circle R0 + F t; the level-0
+    length follows 2 pi (R0 + F t) and phi near the front is r - R0 - F t
+    to first order in h."""
+    errs = []
+    for n in (81, 161):
+        spec = G.square(n, 1.0)
+        X, Y = G.square_xy(spec)
+        r = np.hypot(X, Y)
+        F, h, R0 = 0.3, spec.h[0], 0.25
+        dt = 0.5 * h / F
+        nsteps = int(round(0.5 / dt))
+        t = nsteps * dt
+        phi = oracle.levelset_advance(spec, r - R0, F, dt, nsteps)
+        Rt = R0 + F * t
+        L = oracle.level_length(spec, phi, 0.0)
+        assert abs(L / (2 * np.pi * Rt) - 1) < 0.02
+        band = np.abs(r - Rt) < 0.15
+        errs.append(np.abs(phi - (r - Rt))[band].max())
+    assert errs[1] < 0.7 * errs[0]
+
+
+def test_signed_distance_combination(oracle):
+    solid = np.array([[0, 1], [1, 0]], dtype=np.uint8)
+    ds = np.array([[9.0, 2.0], [3.0, 9.0]])
+    dg = np.array([[4.0, 9.0], [9.0, 5.0]])
+    assert np.array_equal(oracle.signed_distance(solid, ds, dg), np.array([[-4.0, 2.0], [3.0, -5.0]]))
