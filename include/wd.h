@@ -214,6 +214,42 @@ int wd_poisson_distance(wd_ctx *ctx, const wd_grid_desc *desc, int scheme,
                         int precision, const void *phip, void *dist, void *ws,
                         size_t ws_bytes, void *stream);
 
+/* ---- level-set burnback (Sec. 5.5, Eq. levelset) ---------------------
+ * A front (the burning surface of a propellant grain) moves along its
+ * normal at speed F: d phi_s / dt + F |grad phi_s| = 0 (the printed right-
+ * hand side "1" read as 0), phi_s the signed distance to the front,
+ * positive on the solid side, so the front moves into the solid.  Uniform
+ * grids (metric_mode WD_METRIC_UNIFORM; desc->mask and the face kinds are
+ * not used: every non-periodic face gets a zero normal gradient). */
+
+/* Device workspace for wd_levelset_advance and wd_level_lengths. */
+int wd_levelset_workspace_bytes(wd_ctx *ctx, const wd_grid_desc *desc, int precision,
+                                size_t *bytes);
+
+/* phi_s = d_solid where solid[q] != 0, -d_gas elsewhere (n points; device
+ * arrays in `precision`, solid as bytes; phi_s may alias either input). */
+int wd_signed_distance(wd_ctx *ctx, long long n, int precision, const unsigned char *solid,
+                       const void *d_solid, const void *d_gas, void *phi_s, void *stream);
+
+/* nsteps classical RK4 steps of size dt of the equation above, in place on
+ * phi_s (device, grid layout, `precision`): each one-sided difference by the
+ * upwind switch of Eqs. UW3-UW5, divided by the grid spacing; after every
+ * stage each non-periodic face takes f_b = (4 f_1 - f_2) / 3 along its grid
+ * line, faces normal to direction 0 first.  Asynchronous on `stream`. */
+int wd_levelset_advance(wd_ctx *ctx, const wd_grid_desc *desc, int precision, double speed,
+                        double dt, int nsteps, void *phi_s, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* Lengths of the iso-lines phi_s = levels[k] (k < nlevels <= 8) of a 2D
+ * uniform grid, in grid units of desc->h: in each cell the crossings of
+ * the four edges by linear interpolation joined in pairs (a cell with four
+ * crossings split by the sign of its mean value), summed in FP64.  The
+ * grain's burning perimeter per unit depth (the surface S_b, Sec. 5.5) is
+ * the length of the level 0.  lengths: host.  Waits for the stream. */
+int wd_level_lengths(wd_ctx *ctx, const wd_grid_desc *desc, int precision, const void *phi_s,
+                     const double *levels, int nlevels, double *lengths, void *ws,
+                     size_t ws_bytes, void *stream);
+
 /* ---- live kernel timing --------------------------------------------- */
 typedef struct wd_kernel_stat {
     char name[32];        /* kernel family, e.g. "k_d2", "k_filter"        */

@@ -83,6 +83,12 @@ def lib():
                               C.POINTER(dp), C.c_int, ip, ip, vp, C.c_size_t, vp], C.c_int),
         "wd_poisson_distance": ([vp, gd, C.c_int, C.c_int, vp, vp, vp, C.c_size_t, vp], C.c_int),
         "wd_autotune": ([vp, gd, me, vp, vp, C.c_size_t, C.c_int, ip, vp], C.c_int),
+        "wd_levelset_workspace_bytes": ([vp, gd, C.c_int, szp], C.c_int),
+        "wd_signed_distance": ([vp, C.c_longlong, C.c_int, vp, vp, vp, vp, vp], C.c_int),
+        "wd_levelset_advance": ([vp, gd, C.c_int, C.c_double, C.c_double, C.c_int, vp, vp,
+                                 C.c_size_t, vp], C.c_int),
+        "wd_level_lengths": ([vp, gd, C.c_int, vp, dp, C.c_int, dp, vp, C.c_size_t, vp],
+                             C.c_int),
         "wd_tune_get": ([vp, gd, C.c_int, ip], C.c_int),
         "wd_tune_set": ([vp, gd, C.c_int, ip], C.c_int),
         "wd_ctx_profile": ([vp, C.c_int], C.c_int),
@@ -197,6 +203,35 @@ def wd_poisson_distance(ctx, desc, scheme, precision, phip_ptr, dist_ptr, ws_ptr
     return _check(lib().wd_poisson_distance(ctx, C.byref(desc), scheme, precision, phip_ptr,
                                             dist_ptr, ws_ptr, ws_bytes, stream),
                   "wd_poisson_distance")
+
+
+def wd_levelset_workspace_bytes(ctx, desc, precision):
+    b = C.c_size_t(0)
+    _check(lib().wd_levelset_workspace_bytes(ctx, C.byref(desc), precision, C.byref(b)),
+           "wd_levelset_workspace_bytes")
+    return b.value
+
+
+def wd_signed_distance(ctx, n, precision, solid_ptr, d_solid_ptr, d_gas_ptr, out_ptr,
+                       stream=None):
+    return _check(lib().wd_signed_distance(ctx, n, precision, solid_ptr, d_solid_ptr,
+                                           d_gas_ptr, out_ptr, stream), "wd_signed_distance")
+
+
+def wd_levelset_advance(ctx, desc, precision, speed, dt, nsteps, phi_ptr, ws_ptr, ws_bytes,
+                        stream=None):
+    return _check(lib().wd_levelset_advance(ctx, C.byref(desc), precision, speed, dt, nsteps,
+                                            phi_ptr, ws_ptr, ws_bytes, stream),
+                  "wd_levelset_advance")
+
+
+def wd_level_lengths(ctx, desc, precision, phi_ptr, levels, ws_ptr, ws_bytes, stream=None):
+    n = len(levels)
+    lv = (C.c_double * max(n, 1))(*[float(v) for v in levels])
+    out = (C.c_double * max(n, 1))()
+    _check(lib().wd_level_lengths(ctx, C.byref(desc), precision, phi_ptr, lv, n, out, ws_ptr,
+                                  ws_bytes, stream), "wd_level_lengths")
+    return [out[k] for k in range(n)]
 
 
 def wd_autotune(ctx, desc, method, phi_ptr, ws_ptr, ws_bytes, iters=20, stream=None):

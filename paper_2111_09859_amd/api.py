@@ -154,6 +154,37 @@ class Solver:
         return L.wd_tune_get(self.ctx, prep.desc, PRECISIONS["fp64" if prep.dtype == self.torch.float64
                                                              else "fp32"])
 
+    # -- level-set burnback (Sec. 5.5) ---------------------------------
+    def _prec(self, prep: Prepared):
+        return L.WD_FP64 if prep.dtype == self.torch.float64 else L.WD_FP32
+
+    def signed_distance(self, solid, d_solid, d_gas):
+        """phi_s = d_solid on solid points (uint8 device mask), -d_gas elsewhere."""
+        torch = self.torch
+        out = torch.empty_like(d_solid)
+        prec = L.WD_FP64 if d_solid.dtype == torch.float64 else L.WD_FP32
+        L.wd_signed_distance(self.ctx, d_solid.numel(), prec, C.c_void_p(solid.data_ptr()),
+                             C.c_void_p(d_solid.data_ptr()), C.c_void_p(d_gas.data_ptr()),
+                             C.c_void_p(out.data_ptr()), self.stream())
+        return out
+
+    def levelset_advance(self, prep: Prepared, phi_s, speed: float, dt: float, nsteps: int):
+        """nsteps RK4 steps of d phi_s/dt + speed |grad phi_s| = 0, in place."""
+        prec = self._prec(prep)
+        ws = self.workspace(L.wd_levelset_workspace_bytes(self.ctx, prep.desc, prec))
+        L.wd_levelset_advance(self.ctx, prep.desc, prec, speed, dt, nsteps,
+                              C.c_void_p(phi_s.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
+                              self.stream())
+        return phi_s
+
+    def level_lengths(self, prep: Prepared, phi_s, levels):
+        """Lengths of the 2D iso-lines phi_s = level for each level."""
+        prec = self._prec(prep)
+        ws = self.workspace(L.wd_levelset_workspace_bytes(self.ctx, prep.desc, prec))
+        return L.wd_level_lengths(self.ctx, prep.desc, prec, C.c_void_p(phi_s.data_ptr()),
+                                  list(levels), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                  self.stream())
+
     def set_tiles(self, prep: Prepared, widths):
         """Use these tile widths for this grid's shape and precision."""
         L.wd_tune_set(self.ctx, prep.desc, PRECISIONS["fp64" if prep.dtype == self.torch.float64

@@ -1582,4 +1582,142 @@ int wd_poisson_distance(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, int p
     return poisson_convert(ctx, P, 0, nullptr, s);
 }
 
+// ---------------------------------------------------------------------
+// Level-set burnback (Sec. 5.5).  The march borrows a solve plan of the
+// grid for its buffers (stage values in ps and P[0], the RK4 accumulator)
+// and its pointwise work items; the length partials sit after the plan.
+
+static wd_method levelset_method(int precision)
+{
+    wd_method m;
+    wd_method_default(&m);
+    m.equation = WD_EQ_EIKONAL;
+    m.scheme = WD_UW;
+    m.filter = 0;
+    m.rk = WD_RK4;
+    m.precision = precision;
+    return m;
+}
+
+static int levelset_check(const wd_grid_desc *desc, int precision)
+{
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (desc->metric_mode != WD_METRIC_UNIFORM)
+        return fail(WD_ERR_UNSUPPORTED, "the level-set march takes uniform grids");
+    if (precision != WD_FP32 && precision != WD_FP64)
+        return fail(WD_ERR_INVALID_ARG, "precision must be WD_FP32 or WD_FP64");
+    return WD_OK;
+}
+
+static size_t levelset_part_blocks() { return 1024; }
+
+int wd_levelset_workspace_bytes(wd_ctx *ctx, const wd_grid_desc *desc, int precision,
+                                size_t *bytes)
+{
+    if (!ctx || !bytes) return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    int rc = levelset_check(desc, precision);
+    if (rc) return rc;
+    wd_grid_desc d = *desc;
+    d.mask = nullptr;
+    wd_method m = levelset_method(precision);
+    size_t b = 0;
+    rc = wd_workspace_bytes(ctx, 1, &d, &m, &b);
+    if (rc) return rc;
+    *bytes = b + levelset_part_blocks() * kMaxLevels * sizeof(double) + 256;
+    return WD_OK;
+}
+
+int wd_levelset_advance(wd_ctx *ctx, const wd_grid_desc *desc, int precision, double speed,
+                        double dt, int nsteps, void *phi_s, void *ws, size_t ws_bytes,
+                        void *stream)
+{
+    if (!ctx || !phi_s || nsteps < 0) return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    if (!(std::fabs(speed * dt) < 1e300)) return fail(WD_ERR_INVALID_ARG, "speed * dt is not finite");
+    int rc = levelset_check(desc, precision);
+    if (rc) return rc;
+    if (nsteps == 0) return WD_OK;
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    StreamJoin join(ctx, stream);
+    hipStream_t s = ctx->stream;
+    wd_grid_desc d = *desc;
+    d.mask = nullptr;
+    wd_method m = levelset_method(precision);
+    void *phis[1] = {phi_s};
+    Plan P;
+    rc = plan_batch(ctx, 1, &d, &m, phis, ws, ws_bytes, P);
+    if (rc) return rc;
+    rc = upload_plan(ctx, P, s);
+    if (rc) return rc;
+    // the initial pass's list holds tiles 0 .. nchunks-1 of the grid, in
+    // order: the stage launches take all of them, a face launch its first
+    // ceil(face points / chunk) ones
+    const ItemList &L = P.lists[P.init];
+    const GridDev &g = P.grids[0];
+    const Item *items = P.d_items + L.first;
+    const int nwg = std::max(8, ctx->cus * (P.fp64 ? 2 : 4));
+    const double fdt = speed * dt;
+    for (int it = 0; it < nsteps; ++it)
+        for (int st = 0; st < 4; ++st) {
+            launch_ls_stage(P.fp64, P.d_grids, items, L.count, st, fdt, nwg, s);
+            for (int l = 0; l < g.ndim; ++l) {
+                if (g.periodic[l]) continue;
+                const int nf = (int)((g.N / g.n[l] + kChunk - 1) / kChunk);
+                launch_ls_face(P.fp64, P.d_grids, items, nf, l, st, nwg, s);
+            }
+        }
+    if (hipGetLastError() != hipSuccess) return fail(WD_ERR_HIP, "level-set launch failed");
+    return WD_OK;
+}
+
+int wd_level_lengths(wd_ctx *ctx, const wd_grid_desc *desc, int precision, const void *phi_s,
+                     const double *levels, int nlevels, double *lengths, void *ws,
+                     size_t ws_bytes, void *stream)
+{
+    if (!ctx || !phi_s || !levels || !lengths || !ws)
+        return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    int rc = levelset_check(desc, precision);
+    if (rc) return rc;
+    if (desc->ndim != 2) return fail(WD_ERR_UNSUPPORTED, "iso-line lengths are 2D");
+    if (nlevels < 1 || nlevels > kMaxLevels)
+        return fail(WD_ERR_INVALID_ARG, "nlevels must be 1..%d", kMaxLevels);
+    const size_t nb = levelset_part_blocks();
+    const size_t need = nb * kMaxLevels * sizeof(double);
+    if (ws_bytes < need) return fail(WD_ERR_INVALID_ARG, "workspace too small");
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = ctx->stream;
+    std::vector<double> part(nb * kMaxLevels);
+    {
+        StreamJoin join(ctx, stream);
+        launch_ls_length(precision == WD_FP64, phi_s, desc->n[0], desc->n[1], desc->h[0],
+                         desc->h[1], levels, nlevels, static_cast<double *>(ws), (int)nb, s);
+        if (hipMemcpyAsync(part.data(), ws, need, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return fail(WD_ERR_HIP, "length partials copy failed");
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(WD_ERR_HIP, "length pass failed");
+    for (int k = 0; k < nlevels; ++k) {
+        double t = 0.0;
+        for (size_t b = 0; b < nb; ++b) t += part[b * kMaxLevels + k];
+        lengths[k] = t;
+    }
+    return WD_OK;
+}
+
+int wd_signed_distance(wd_ctx *ctx, long long n, int precision, const unsigned char *solid,
+                       const void *d_solid, const void *d_gas, void *phi_s, void *stream)
+{
+    if (!ctx || !solid || !d_solid || !d_gas || !phi_s || n < 0)
+        return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    if (precision != WD_FP32 && precision != WD_FP64)
+        return fail(WD_ERR_INVALID_ARG, "precision must be WD_FP32 or WD_FP64");
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    StreamJoin join(ctx, stream);
+    launch_ls_signed(precision == WD_FP64, n, solid, d_solid, d_gas, phi_s, ctx->stream);
+    if (hipGetLastError() != hipSuccess) return fail(WD_ERR_HIP, "signed-distance launch failed");
+    return WD_OK;
+}
+
 }  // extern "C"

@@ -42,6 +42,17 @@ WD_LINE_LAUNCHER(line_launch_f64_8)
 #undef WD_LINE_LAUNCHER
 // workgroups of a line pass's kernel that one compute unit holds at once
 int line_blocks_per_cu(int kind, int fp64, int np);
+// level-set burnback (uniform grids)
+constexpr int kMaxLevels = 8;   // iso-values per length call
+void launch_ls_stage(int fp64, const GridDev *g, const Item *it, int nitems, int stage,
+                     double fdt, int nwg, hipStream_t s);
+void launch_ls_face(int fp64, const GridDev *g, const Item *it, int nitems, int l, int stage,
+                    int nwg, hipStream_t s);
+void launch_ls_signed(int fp64, long long n, const unsigned char *solid, const void *ds,
+                      const void *dg, void *out, hipStream_t s);
+// partials [nb][kMaxLevels] (FP64, device)
+void launch_ls_length(int fp64, const void *phi, int nx, int ny, double hx, double hy,
+                      const double *levels, int nlev, double *part, int nb, hipStream_t s);
 void launch_finalize(const GridDev *grids, int ngrids, hipStream_t s);
 void launch_mirror(const GridDev *grids, int ngrids, hipStream_t s);
 // field-major metrics [c][q] into the point-major array [q][c] (dd = ndim^2)

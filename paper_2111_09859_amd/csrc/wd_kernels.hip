@@ -272,6 +272,256 @@ k_finalize(const GridDev *__restrict__ grids, int ngrids)
     *g.mirror = st;   // the host reads the contiguous mirrors after each round
 }
 
+// ---------------------------------------------------------------------
+// Level-set burnback (Sec. 5.5, Eq. levelset with its right-hand side read
+// as 0): d phi_s / dt = -F |grad phi_s| on a uniform grid, classical RK4 in
+// physical time, the upwind switch of Eqs. UW3-UW5 for each one-sided
+// difference, zero normal gradient on every non-periodic face.  phi_s is
+// positive on the solid side, so the front moves into the solid.
+
+// |grad f| at point q from the switch-selected index differences
+template <typename T>
+__device__ inline T ls_grad(const GridDev &g, gptr<const T> f, long long q, const int *idx)
+{
+    T s2 = (T)0;
+    const T f0 = f[q];
+    for (int l = 0; l < g.ndim; ++l) {
+        const int n = g.n[l], i = idx[l];
+        const long long s = g.stride[l];
+        const bool per = g.periodic[l] != 0;
+        const bool hm = i > 0 || per, hp = i < n - 1 || per;
+        const long long qm = i > 0 ? q - s : q + (long long)(n - 1) * s;
+        const long long qp = i < n - 1 ? q + s : q - (long long)(n - 1) * s;
+        T b = hm ? f0 - f[qm] : (T)0;
+        T fw = hp ? f[qp] - f0 : (T)0;
+        if (!hm) b = fw;
+        if (!hp) fw = b;
+        T d;
+        if (fw + b >= (T)0) d = b >= (T)0 ? b : (T)0;
+        else d = fw < (T)0 ? fw : (T)0;
+        d *= (T)g.invh[l];
+        s2 += d * d;
+    }
+    return sqrt(s2);
+}
+
+// stage buffers: values in phi (start), ps, P[0], ps, phi (end)
+template <typename T>
+__device__ inline void ls_buffers(const GridDev &g, int stage, gptr<const T> &src, gptr<T> &dst)
+{
+    void *b[5] = {g.phi, g.ps, g.P[0], g.ps, g.phi};
+    src = gcast<const T>(b[stage]);
+    dst = gcast<T>(b[stage + 1]);
+}
+
+// one RK4 stage over a chunk of points (accumulator form, fdt = F dt)
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_ls_stage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int nitems,
+           int stage, double fdt)
+{
+    int step, end;
+    for (int it = item_begin(nitems, step, end); it < end; it += step) {
+        const Item item = items[it];
+        const GridDev &g = grids[item.grid];
+        gptr<const T> src;
+        gptr<T> dst;
+        ls_buffers<T>(g, stage, src, dst);
+        gptr<const T> phi = gcast<const T>(g.phi);
+        gptr<T> acc = gcast<T>(g.acc);
+        const T h = (T)fdt;
+        const long long q0 = (long long)item.tile * kChunk;
+        for (int i = threadIdx.x; i < kChunk; i += kThreads) {
+            const long long q = q0 + i;
+            if (q >= g.N) break;
+            int idx[3];
+            index_of(g, q, idx);
+            const T gm = ls_grad<T>(g, src, q, idx);
+            if (stage == 0) {
+                const T pn = phi[q];
+                acc[q] = pn - h * (T)(1.0 / 6.0) * gm;
+                dst[q] = pn - h * (T)0.5 * gm;
+            } else if (stage == 1) {
+                acc[q] = acc[q] - h * (T)(1.0 / 3.0) * gm;
+                dst[q] = phi[q] - h * (T)0.5 * gm;
+            } else if (stage == 2) {
+                acc[q] = acc[q] - h * (T)(1.0 / 3.0) * gm;
+                dst[q] = phi[q] - h * gm;
+            } else {
+                dst[q] = acc[q] - h * (T)(1.0 / 6.0) * gm;
+            }
+        }
+    }
+}
+
+// zero normal gradient on both faces normal to l of the stage's output:
+// f_b = (4 f_1 - f_2) / 3 along the grid line
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_ls_face(const GridDev *__restrict__ grids, const Item *__restrict__ items, int nitems,
+          int l, int stage)
+{
+    int step, end;
+    for (int it = item_begin(nitems, step, end); it < end; it += step) {
+        const Item item = items[it];
+        const GridDev &g = grids[item.grid];
+        gptr<const T> src;
+        gptr<T> f;
+        ls_buffers<T>(g, stage, src, f);
+        const long long nface = g.N / g.n[l];
+        const long long k0 = (long long)item.tile * kChunk;
+        const long long s = g.stride[l];
+        for (int i = threadIdx.x; i < kChunk; i += kThreads) {
+            const long long k = k0 + i;
+            if (k >= nface) break;
+            // face point k in (dir-0, dir-1, dir-2) order with index l removed
+            long long q;
+            const int n0 = g.n[0];
+            if (l == 0) q = k * n0;
+            else if (l == 1) q = (k % n0) + (k / n0) * (long long)n0 * g.n[1];
+            else q = k;
+            const long long qe = q + (long long)(g.n[l] - 1) * s;
+            f[q] = ((T)4 * f[q + s] - f[q + 2 * s]) * (T)(1.0 / 3.0);
+            f[qe] = ((T)4 * f[qe - s] - f[qe - 2 * s]) * (T)(1.0 / 3.0);
+        }
+    }
+}
+
+// phi_s = d_solid on solid points, -d_gas elsewhere
+template <typename T>
+__global__ void k_ls_signed(long long n, const unsigned char *__restrict__ solid,
+                            const T *__restrict__ ds, const T *__restrict__ dg, T *__restrict__ out)
+{
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x)
+        out[q] = solid[q] ? ds[q] : -dg[q];
+}
+
+// Lengths of the iso-lines phi = levels[k] of a uniform 2D grid (linear
+// interpolation on the cell edges, a saddle split by the cell mean): FP64
+// partial sums per workgroup and level, [block][level].
+struct LsLevels {
+    double v[kMaxLevels];
+    int n;
+};
+
+template <typename T>
+__device__ inline double ls_cell_length(const T *c, double level, double hx, double hy)
+{
+    // corners counter-clockwise from (i, j)
+    const double v[4] = {(double)c[0] - level, (double)c[1] - level, (double)c[2] - level,
+                         (double)c[3] - level};
+    const double cx[4] = {0.0, hx, hx, 0.0}, cy[4] = {0.0, 0.0, hy, hy};
+    double px[4] = {0.0, 0.0, 0.0, 0.0}, py[4] = {0.0, 0.0, 0.0, 0.0};
+    int np = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int a = e, b = (e + 1) & 3;
+        if ((v[a] >= 0.0) != (v[b] >= 0.0)) {
+            const double t = v[a] / (v[a] - v[b]);
+            const double x = cx[a] + t * (cx[b] - cx[a]), y = cy[a] + t * (cy[b] - cy[a]);
+            px[np] = x;   // np < 4 here: at most four edges cross
+            py[np] = y;
+            ++np;
+        }
+    }
+    if (np == 2) return hypot(px[1] - px[0], py[1] - py[0]);
+    if (np != 4) return 0.0;
+    const double mean = 0.25 * (v[0] + v[1] + v[2] + v[3]);
+    if ((mean >= 0.0) == (v[0] >= 0.0))
+        return hypot(px[1] - px[0], py[1] - py[0]) + hypot(px[3] - px[2], py[3] - py[2]);
+    return hypot(px[3] - px[0], py[3] - py[0]) + hypot(px[2] - px[1], py[2] - py[1]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_ls_length(const T *__restrict__ phi, int nx, int ny, double hx, double hy, LsLevels lv,
+            double *__restrict__ part)
+{
+    __shared__ double sh[kMaxLevels][kThreads / 64];
+    double acc[kMaxLevels];
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k) acc[k] = 0.0;
+    const long long cells = (long long)(nx - 1) * (ny - 1);
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < cells;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int j = (int)(c / (nx - 1)), i = (int)(c - (long long)j * (nx - 1));
+        const long long q = (long long)j * nx + i;
+        const T cv[4] = {phi[q], phi[q + 1], phi[q + nx + 1], phi[q + nx]};
+#pragma unroll
+        for (int k = 0; k < kMaxLevels; ++k)
+            if (k < lv.n) acc[k] += ls_cell_length<T>(cv, lv.v[k], hx, hy);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k) {
+        double a = acc[k];
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+        if (lane == 0) sh[k][wv] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxLevels) {
+        double a = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) a += sh[threadIdx.x][w];
+        part[(long long)blockIdx.x * kMaxLevels + threadIdx.x] = a;
+    }
+}
+
+void launch_ls_stage(int fp64, const GridDev *g, const Item *it, int nitems, int stage,
+                     double fdt, int nwg, hipStream_t s)
+{
+    if (nitems <= 0) return;
+    nwg = std::min(nwg, nitems);
+    if (fp64)
+        hipLaunchKernelGGL(k_ls_stage<double>, dim3(nwg), dim3(kThreads), 0, s, g, it, nitems,
+                           stage, fdt);
+    else
+        hipLaunchKernelGGL(k_ls_stage<float>, dim3(nwg), dim3(kThreads), 0, s, g, it, nitems,
+                           stage, fdt);
+}
+
+void launch_ls_face(int fp64, const GridDev *g, const Item *it, int nitems, int l, int stage,
+                    int nwg, hipStream_t s)
+{
+    if (nitems <= 0) return;
+    nwg = std::min(nwg, nitems);
+    if (fp64)
+        hipLaunchKernelGGL(k_ls_face<double>, dim3(nwg), dim3(kThreads), 0, s, g, it, nitems,
+                           l, stage);
+    else
+        hipLaunchKernelGGL(k_ls_face<float>, dim3(nwg), dim3(kThreads), 0, s, g, it, nitems,
+                           l, stage);
+}
+
+void launch_ls_signed(int fp64, long long n, const unsigned char *solid, const void *ds,
+                      const void *dg, void *out, hipStream_t s)
+{
+    if (n <= 0) return;
+    const int nb = (int)std::min<long long>((n + kThreads - 1) / kThreads, 4096);
+    if (fp64)
+        hipLaunchKernelGGL(k_ls_signed<double>, dim3(nb), dim3(kThreads), 0, s, n, solid,
+                           static_cast<const double *>(ds), static_cast<const double *>(dg),
+                           static_cast<double *>(out));
+    else
+        hipLaunchKernelGGL(k_ls_signed<float>, dim3(nb), dim3(kThreads), 0, s, n, solid,
+                           static_cast<const float *>(ds), static_cast<const float *>(dg),
+                           static_cast<float *>(out));
+}
+
+void launch_ls_length(int fp64, const void *phi, int nx, int ny, double hx, double hy,
+                      const double *levels, int nlev, double *part, int nb, hipStream_t s)
+{
+    LsLevels lv;
+    lv.n = nlev;
+    for (int k = 0; k < kMaxLevels; ++k) lv.v[k] = k < nlev ? levels[k] : 0.0;
+    if (fp64)
+        hipLaunchKernelGGL(k_ls_length<double>, dim3(nb), dim3(kThreads), 0, s,
+                           static_cast<const double *>(phi), nx, ny, hx, hy, lv, part);
+    else
+        hipLaunchKernelGGL(k_ls_length<float>, dim3(nb), dim3(kThreads), 0, s,
+                           static_cast<const float *>(phi), nx, ny, hx, hy, lv, part);
+}
+
 // field-major metrics [c][q] -> point-major [q][c] (dd components)
 template <typename T>
 __global__ void k_met_points(const T *__restrict__ src, T *__restrict__ dst, long long N, int dd)
