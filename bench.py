@@ -402,6 +402,83 @@ def run_ratios(args):
                        "results": out}}
 
 
+def run_burnback(args):
+    """Level-set burnback of the star grain (Sec. 5.5): the signed distance
+    from two FP32 E4 LAD pseudo-HJ solves (gas side, propellant side, to the
+    paper's 1e-5), then RK4 steps of d phi_s/dt + F |grad phi_s| = 0 at
+    F = 0.3 with dt = h / (2 F), the lengths of the levels 0, 0.05, 0.1 and
+    -0.02 every 50 steps (the burning perimeter S_b per unit depth is the
+    level 0).  A second, march-only run on a 4096^2 grid from the analytic
+    six-lobed front gives the stage kernels' bandwidth."""
+    import torch
+    from paper_2111_09859_amd import api, grids as G
+    s = api.Solver(0)
+    n = args.burn_n
+    gas, sol = G.star_grain(n), G.star_grain_solid(n)
+    m = method_for(gas, "E4", "fp32", eps=0.2)
+    pg, ps_ = s.prepare(gas, "E4", "fp32"), s.prepare(sol, "E4", "fp32")
+    for p in (pg, ps_):
+        s.autotune(p, m, iters=10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rg = s.solve(pg, m, check=False)
+    rs = s.solve(ps_, m, check=False)
+    mask = torch.as_tensor(gas.mask, device=s.device).contiguous()
+    phi = s.signed_distance(mask, rs["phi"], rg["phi"])
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    print(f"[burnback] init {t_init:.2f} s ({rg['iters']} + {rs['iters']} iterations)",
+          file=sys.stderr, flush=True)
+    F, dt = 0.3, 0.5 * gas.h[0] / 0.3
+    levels = [0.0, 0.05, 0.1, -0.02]
+    series = [(0.0, s.level_lengths(pg, phi, levels))]
+    t_march = 0.0
+    done = 0
+    while done < args.burn_steps:
+        k = min(50, args.burn_steps - done)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.levelset_advance(pg, phi, F, dt, k)
+        torch.cuda.synchronize()
+        t_march += time.perf_counter() - t1
+        done += k
+        series.append((done * dt, s.level_lengths(pg, phi, levels)))
+    print(f"[burnback] {done} steps in {t_march:.3f} s", file=sys.stderr, flush=True)
+    # bandwidth of the march on a large grid (no solves)
+    big = G.square(args.burn_big, 0.5)
+    X, Y = G.square_xy(big)
+    front = np.hypot(X, Y) - 0.2 * (1 + 0.3 * np.cos(6 * np.arctan2(Y, X)))
+    pb = s.prepare(big, "UW", "fp32")
+    pbig = torch.as_tensor(front, dtype=torch.float32, device=s.device).contiguous()
+    bdt = 0.5 * big.h[0] / F
+    s.levelset_advance(pb, pbig, F, bdt, 4)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.levelset_advance(pb, pbig, F, bdt, args.burn_big_steps)
+    torch.cuda.synchronize()
+    t_big = time.perf_counter() - t2
+    # compulsory bytes of one step's stage kernels: stage 0 reads phi and
+    # writes the stage value and the accumulator; stages 1 and 2 read the
+    # stage value, phi and the accumulator and write two; stage 3 reads two
+    # and writes phi: 64 B per point (FP32), faces excluded
+    nb = big.npoints
+    step_bytes = 16.0 * 4 * nb
+    bw = step_bytes * args.burn_big_steps / t_big / 1e9
+    return {
+        "metric": "level-set point-updates/s", "value": gas.npoints * done / t_march,
+        "unit": "point-updates/s", "n_gpus": 1, "steps": done, "warmup": 0,
+        "ms_per_step": 1e3 * t_march / done, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"star-grain burnback {n}x{n}: signed distance from two E4 LAD "
+                               f"pseudo-HJ solves, {done} RK4 level-set steps at F = 0.3",
+                   "init_s": t_init, "init_iters": [rg["iters"], rs["iters"]],
+                   "init_status": [rg["status"], rs["status"]],
+                   "levels": levels, "lengths": [[t, l] for t, l in series],
+                   "march_4096_ms_per_step": 1e3 * t_big / args.burn_big_steps,
+                   "march_4096_point_updates_per_s": nb * args.burn_big_steps / t_big,
+                   "march_4096_stage_GBps": bw, "march_4096_frac_of_8TBps": bw / HBM_PEAK_GBS}}
+
+
 def run_serve(args):
     """Config 5 (bounded sample): open-loop Poisson arrivals (200 req/s) of
     2D grids 129^2..2049^2 and 3D ducts 64^3..192^3 into the continuous-
@@ -519,6 +596,10 @@ def main():
     ap.add_argument("--serve-count", type=int, default=200)
     ap.add_argument("--serve-steps", type=int, default=10)
     ap.add_argument("--serve-budget", type=int, default=4096, help="arena MiB")
+    ap.add_argument("--burn-n", type=int, default=1024)
+    ap.add_argument("--burn-steps", type=int, default=500)
+    ap.add_argument("--burn-big", type=int, default=4096)
+    ap.add_argument("--burn-big-steps", type=int, default=40)
     args = ap.parse_args()
     global ALPHA_F
     if args.alpha_f is not None:
@@ -542,6 +623,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(run_serve(args)), flush=True)
+        return
+    if args.workload == "burnback":
+        print(json.dumps(run_burnback(args)), flush=True)
         return
     spec, kw, desc = workload(args.workload)
     if args.alpha_f is not None:

@@ -235,7 +235,9 @@ int wd_signed_distance(wd_ctx *ctx, long long n, int precision, const unsigned c
  * phi_s (device, grid layout, `precision`): each one-sided difference by the
  * upwind switch of Eqs. UW3-UW5, divided by the grid spacing; after every
  * stage each non-periodic face takes f_b = (4 f_1 - f_2) / 3 along its grid
- * line, faces normal to direction 0 first.  Asynchronous on `stream`. */
+ * line, faces normal to direction 0 first.  With nsteps >= 4 one step is
+ * captured in a HIP graph and replayed, and the call returns once the
+ * steps have run; otherwise it is asynchronous on `stream`. */
 int wd_levelset_advance(wd_ctx *ctx, const wd_grid_desc *desc, int precision, double speed,
                         double dt, int nsteps, void *phi_s, void *ws, size_t ws_bytes,
                         void *stream);

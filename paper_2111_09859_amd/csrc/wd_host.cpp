@@ -1658,7 +1658,7 @@ int wd_levelset_advance(wd_ctx *ctx, const wd_grid_desc *desc, int precision, do
     const Item *items = P.d_items + L.first;
     const int nwg = std::max(8, ctx->cus * (P.fp64 ? 2 : 4));
     const double fdt = speed * dt;
-    for (int it = 0; it < nsteps; ++it)
+    auto one_step = [&]() {
         for (int st = 0; st < 4; ++st) {
             launch_ls_stage(P.fp64, P.d_grids, items, L.count, st, fdt, nwg, s);
             for (int l = 0; l < g.ndim; ++l) {
@@ -1667,6 +1667,37 @@ int wd_levelset_advance(wd_ctx *ctx, const wd_grid_desc *desc, int precision, do
                 launch_ls_face(P.fp64, P.d_grids, items, nf, l, st, nwg, s);
             }
         }
+    };
+    // several steps: one step's launches captured in a graph and replayed
+    hipGraphExec_t exec = nullptr;
+    if (nsteps >= 4 && !ctx->profile) {
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) == hipSuccess) {
+            one_step();
+            if (hipStreamEndCapture(s, &graph) == hipSuccess && graph) {
+                if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                    exec = nullptr;
+                (void)hipGraphDestroy(graph);
+            }
+        }
+        (void)hipGetLastError();
+    }
+    for (int it = 0; it < nsteps; ++it) {
+        if (exec) {
+            if (hipGraphLaunch(exec, s) != hipSuccess) {
+                (void)hipGraphExecDestroy(exec);
+                return fail(WD_ERR_HIP, "hipGraphLaunch failed");
+            }
+        } else {
+            one_step();
+        }
+    }
+    if (exec) {
+        // the executable graph is released once its replays have run
+        const hipError_t e = hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(exec);
+        if (e != hipSuccess) return fail(WD_ERR_HIP, "level-set march failed");
+    }
     if (hipGetLastError() != hipSuccess) return fail(WD_ERR_HIP, "level-set launch failed");
     return WD_OK;
 }

@@ -331,9 +331,11 @@ k_ls_stage(const GridDev *__restrict__ grids, const Item *__restrict__ items, in
         gptr<T> acc = gcast<T>(g.acc);
         const T h = (T)fdt;
         const long long q0 = (long long)item.tile * kChunk;
+        // the chunk's points of this thread together, so their loads overlap
+#pragma unroll
         for (int i = threadIdx.x; i < kChunk; i += kThreads) {
             const long long q = q0 + i;
-            if (q >= g.N) break;
+            if (q >= g.N) continue;
             int idx[3];
             index_of(g, q, idx);
             const T gm = ls_grad<T>(g, src, q, idx);

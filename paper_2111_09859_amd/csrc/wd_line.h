@@ -265,12 +265,16 @@ __device__ inline bool zero_point(const GridDev &g, const Tile &tl, int l,
     return zero_at(g, tl, l, k, pt.J[k], pt.Q[k]);
 }
 
+// grid indices of point q (grids hold fewer than 2^31 points, so 32-bit
+// unsigned division, far shorter than the 64-bit sequence, is exact)
 __device__ inline void index_of(const GridDev &g, long long q, int *idx)
 {
-    idx[0] = (int)(q % g.n[0]);
-    const long long r = q / g.n[0];
-    idx[1] = (int)(r % g.n[1]);
-    idx[2] = (int)(r / g.n[1]);
+    const unsigned u = (unsigned)q, n0 = (unsigned)g.n[0], n1 = (unsigned)g.n[1];
+    const unsigned r = u / n0;
+    idx[0] = (int)(u - r * n0);
+    const unsigned r2 = r / n1;
+    idx[1] = (int)(r - r2 * n1);
+    idx[2] = (int)r2;
 }
 
 // metric d xi_l / d x_m at point q
