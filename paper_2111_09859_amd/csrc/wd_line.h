@@ -724,29 +724,40 @@ __device__ inline void metric_sums(int d, const T *m, T &S1, T &S2)
 template <typename T>
 __device__ inline void metric_load(const GridDev &g, int q, T *m)
 {
-    if (g.uniform) {
-#pragma unroll
-        for (int l = 0; l < 3; ++l)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                m[3 * l + c] = (l == c && l < g.ndim) ? (T)g.invh[l] : (T)0;
-        return;
-    }
-    // a point's metrics are contiguous: constant offsets, so the loads merge
-    gptr<const T> a = gcast<const T>(g.met);
+    // values first, stores after the branches join (every slot is written
+    // at a fixed index, so the array stays in registers)
+    const bool uni = g.uniform != 0;
+    T t[9];
     if (g.ndim == 2) {
-        a += (long long)q * 4;
-        m[0] = a[0];
-        m[1] = a[1];
-        m[3] = a[2];
-        m[4] = a[3];
+        T a0, a1, a2, a3;
+        if (uni) {
+            a0 = (T)g.invh[0];
+            a1 = (T)0;
+            a2 = (T)0;
+            a3 = (T)g.invh[1];
+        } else {
+            // a point's metrics are contiguous: the loads merge
+            gptr<const T> a = gcast<const T>(g.met) + (long long)q * 4;
+            a0 = a[0];
+            a1 = a[1];
+            a2 = a[2];
+            a3 = a[3];
+        }
+        t[0] = a0; t[1] = a1; t[2] = (T)0;
+        t[3] = a2; t[4] = a3; t[5] = (T)0;
+        t[6] = (T)0; t[7] = (T)0; t[8] = (T)0;
     } else {
-        a += (long long)q * 9;
+        if (uni) {
 #pragma unroll
-        for (int l = 0; l < 3; ++l)
+            for (int e = 0; e < 9; ++e) t[e] = (e % 4 == 0) ? (T)g.invh[e / 4] : (T)0;
+        } else {
+            gptr<const T> a = gcast<const T>(g.met) + (long long)q * 9;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) m[3 * l + c] = a[3 * l + c];
+            for (int e = 0; e < 9; ++e) t[e] = a[e];
+        }
     }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m[e] = t[e];
 }
 
 // contravariant pieces U_m = sum_l xi_{l,m} F_l and g2 = |U|^2
