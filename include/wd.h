@@ -81,7 +81,7 @@ typedef struct wd_grid_desc {
                              PERIODIC must be set on both faces             */
     int metric_mode;      /* wd_metric_mode                                 */
     double h[3];          /* UNIFORM: grid spacing per direction            */
-    const void *metrics;  /* FIELDS (2D only): device array of ndim*ndim SoA
+    const void *metrics;  /* FIELDS (2D or 3D): device array of ndim*ndim SoA
                              components in the solve precision; component
                              (l*ndim + m) holds d xi_l / d x_m               */
     const unsigned char *mask; /* optional device array, 1 = solid point

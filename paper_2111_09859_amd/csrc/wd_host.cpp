@@ -244,7 +244,6 @@ int check_desc(const wd_grid_desc *d)
         for (int l = 0; l < d->ndim; ++l)
             if (!(d->h[l] > 0.0)) return fail(WD_ERR_INVALID_ARG, "h[%d] must be > 0", l);
     } else if (d->metric_mode == WD_METRIC_FIELDS) {
-        if (d->ndim != 2) return fail(WD_ERR_UNSUPPORTED, "metric fields are supported on 2D grids");
         if (!d->metrics) return fail(WD_ERR_INVALID_ARG, "metric fields pointer is null");
     } else {
         return fail(WD_ERR_INVALID_ARG, "bad metric mode");

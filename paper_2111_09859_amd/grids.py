@@ -136,6 +136,23 @@ def o_grid(ntheta: int, nr: int, a: float = 0.5, b: float = 0.5,
                           "rho": rho, "theta": t})
 
 
+def cylinder3d(ntheta: int, nr: int, nz: int, R: float = 0.5, rout: float = 6.0,
+               dr1: float = 1e-2, ratio: float = 1.12, far: int = OUTFLOW,
+               length: float = 1.0) -> GridSpec:
+    """The cylinder O-grid extruded along z (nz points on [0, length], faces
+    with zero normal gradient): a 3D curvilinear grid whose metrics mix the
+    two in-plane directions.  Exact d = r - R."""
+    g = cylinder(ntheta, nr, R, rout, dr1, ratio, far)
+    z = np.linspace(0.0, length, nz)
+    X = np.broadcast_to(g.coords[0][None], (nz, nr, ntheta)).copy()
+    Y = np.broadcast_to(g.coords[1][None], (nz, nr, ntheta)).copy()
+    Z = np.broadcast_to(z[:, None, None], (nz, nr, ntheta)).copy()
+    exact = np.broadcast_to(g.exact[None], (nz, nr, ntheta)).copy()
+    return GridSpec("cylinder3d", 3, (ntheta, nr, nz),
+                    ((PERIODIC, PERIODIC), (WALL, far), (NEUMANN, NEUMANN)),
+                    coords=np.stack([X, Y, Z]), exact=exact, meta=dict(g.meta))
+
+
 def cylinder(ntheta: int = 512, nr: int = 256, R: float = 0.5,
              rout: float = 20.0, dr1: float = 1e-3, ratio: float = 1.03,
              far: int = OUTFLOW) -> GridSpec:
