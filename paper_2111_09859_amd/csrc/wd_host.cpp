@@ -251,6 +251,17 @@ int check_desc(const wd_grid_desc *d)
     return WD_OK;
 }
 
+// A solve needs something to measure the distance from: a wall face or a
+// solid mask (the caller's mask may still hold no solid point).
+int check_walls(const wd_grid_desc *d)
+{
+    if (d->mask) return WD_OK;
+    for (int l = 0; l < d->ndim; ++l)
+        for (int s = 0; s < 2; ++s)
+            if (d->bc[l][s] == WD_BC_WALL) return WD_OK;
+    return fail(WD_ERR_INVALID_ARG, "no wall face and no solid mask: the distance is undefined");
+}
+
 int check_method(const wd_method *m)
 {
     if (!m) return fail(WD_ERR_INVALID_ARG, "null method");
@@ -1248,6 +1259,7 @@ int wd_workspace_bytes(wd_ctx *ctx, int n, const wd_grid_desc *descs,
     if (!bytes || n < 1 || !descs || !methods) return fail(WD_ERR_INVALID_ARG, "bad arguments");
     for (int i = 0; i < n; ++i) {
         int rc = check_desc(&descs[i]);
+        if (!rc) rc = check_walls(&descs[i]);
         if (!rc) rc = check_method(&methods[i]);
         if (rc) return rc;
     }
@@ -1263,6 +1275,7 @@ int wd_solve_batched(wd_ctx *ctx, int n, const wd_grid_desc *descs, const wd_met
     std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     for (int i = 0; i < n; ++i) {
         int rc = check_desc(&descs[i]);
+        if (!rc) rc = check_walls(&descs[i]);
         if (!rc) rc = check_method(&methods[i]);
         if (rc) return rc;
         if (!phis[i]) return fail(WD_ERR_INVALID_ARG, "phi[%d] is null", i);
@@ -1387,6 +1400,7 @@ int wd_autotune(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method, 
 {
     if (!ctx || !desc || !method || !phi || iters < 1) return fail(WD_ERR_INVALID_ARG, "bad arguments");
     int rc = check_desc(desc);
+    if (!rc) rc = check_walls(desc);
     if (!rc) rc = check_method(method);
     if (rc) return rc;
     std::lock_guard<std::recursive_mutex> lock(ctx->mu);
@@ -1598,6 +1612,17 @@ static wd_method levelset_method(int precision)
     return m;
 }
 
+// the solve plan that lends the march its buffers: no mask, wall faces
+// (the march's own kernels give every non-periodic face a zero gradient)
+static wd_grid_desc levelset_desc(const wd_grid_desc *desc)
+{
+    wd_grid_desc d = *desc;
+    d.mask = nullptr;
+    for (int l = 0; l < d.ndim; ++l)
+        if (d.bc[l][0] != WD_BC_PERIODIC) d.bc[l][0] = d.bc[l][1] = WD_BC_WALL;
+    return d;
+}
+
 static int levelset_check(const wd_grid_desc *desc, int precision)
 {
     int rc = check_desc(desc);
@@ -1617,8 +1642,7 @@ int wd_levelset_workspace_bytes(wd_ctx *ctx, const wd_grid_desc *desc, int preci
     if (!ctx || !bytes) return fail(WD_ERR_INVALID_ARG, "bad arguments");
     int rc = levelset_check(desc, precision);
     if (rc) return rc;
-    wd_grid_desc d = *desc;
-    d.mask = nullptr;
+    wd_grid_desc d = levelset_desc(desc);
     wd_method m = levelset_method(precision);
     size_t b = 0;
     rc = wd_workspace_bytes(ctx, 1, &d, &m, &b);
@@ -1640,8 +1664,7 @@ int wd_levelset_advance(wd_ctx *ctx, const wd_grid_desc *desc, int precision, do
     (void)hipSetDevice(ctx->device);
     StreamJoin join(ctx, stream);
     hipStream_t s = ctx->stream;
-    wd_grid_desc d = *desc;
-    d.mask = nullptr;
+    wd_grid_desc d = levelset_desc(desc);
     wd_method m = levelset_method(precision);
     void *phis[1] = {phi_s};
     Plan P;

@@ -101,6 +101,7 @@ int fail(int code, const char *fmt, ...);
 extern thread_local std::string g_last_error;
 
 int check_desc(const wd_grid_desc *d);
+int check_walls(const wd_grid_desc *d);
 int check_method(const wd_method *m);
 int grid_mode(const wd_grid_desc &d, const wd_method &m);
 size_t batch_bytes(int n, const wd_grid_desc *d, const wd_method *m);

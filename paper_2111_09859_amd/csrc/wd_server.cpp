@@ -420,6 +420,7 @@ int wd_server_submit(wd_server *srv, const wd_grid_desc *desc, const wd_method *
     if (!srv || !desc || !method || !phi || !req_id || hist_cap < 0)
         return fail(WD_ERR_INVALID_ARG, "bad arguments");
     int rc = check_desc(desc);
+    if (!rc) rc = check_walls(desc);
     if (!rc) rc = check_method(method);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(srv->mu);
