@@ -1673,16 +1673,20 @@ int wd_levelset_advance(wd_ctx *ctx, const wd_grid_desc *desc, int precision, do
     rc = upload_plan(ctx, P, s);
     if (rc) return rc;
     // the initial pass's list holds tiles 0 .. nchunks-1 of the grid, in
-    // order: the stage launches take all of them, a face launch its first
-    // ceil(face points / chunk) ones
+    // order: a stage launch takes the first ceil(N / chunk) of them, a face
+    // launch the first ceil(face points / kChunk)
     const ItemList &L = P.lists[P.init];
     const GridDev &g = P.grids[0];
     const Item *items = P.d_items + L.first;
     const int nwg = std::max(8, ctx->cus * (P.fp64 ? 2 : 4));
     const double fdt = speed * dt;
+    // large grids: 4096-point work items (more loads in flight per thread)
+    // while there are still 8 per compute unit; else 1024-point ones
+    const int chunk = g.N >= 8LL * ctx->cus * kLsChunk ? kLsChunk : kChunk;
     auto one_step = [&]() {
         for (int st = 0; st < 4; ++st) {
-            launch_ls_stage(P.fp64, P.d_grids, items, L.count, st, fdt, nwg, s);
+            launch_ls_stage(P.fp64, P.d_grids, items, (int)((g.N + chunk - 1) / chunk), st, fdt,
+                            chunk, nwg, s);
             for (int l = 0; l < g.ndim; ++l) {
                 if (g.periodic[l]) continue;
                 const int nf = (int)((g.N / g.n[l] + kChunk - 1) / kChunk);

@@ -44,8 +44,10 @@ WD_LINE_LAUNCHER(line_launch_f64_8)
 int line_blocks_per_cu(int kind, int fp64, int np);
 // level-set burnback (uniform grids)
 constexpr int kMaxLevels = 8;   // iso-values per length call
+constexpr int kLsChunk = 4096;  // most points per work item of a level-set stage
+// chunk: points per work item, kThreads .. kLsChunk
 void launch_ls_stage(int fp64, const GridDev *g, const Item *it, int nitems, int stage,
-                     double fdt, int nwg, hipStream_t s);
+                     double fdt, int chunk, int nwg, hipStream_t s);
 void launch_ls_face(int fp64, const GridDev *g, const Item *it, int nitems, int l, int stage,
                     int nwg, hipStream_t s);
 void launch_ls_signed(int fp64, long long n, const unsigned char *solid, const void *ds,

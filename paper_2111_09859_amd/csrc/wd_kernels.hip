@@ -318,7 +318,7 @@ __device__ inline void ls_buffers(const GridDev &g, int stage, gptr<const T> &sr
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_ls_stage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int nitems,
-           int stage, double fdt)
+           int stage, double fdt, int chunk)
 {
     int step, end;
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
@@ -330,12 +330,12 @@ k_ls_stage(const GridDev *__restrict__ grids, const Item *__restrict__ items, in
         gptr<const T> phi = gcast<const T>(g.phi);
         gptr<T> acc = gcast<T>(g.acc);
         const T h = (T)fdt;
-        const long long q0 = (long long)item.tile * kChunk;
+        const long long q0 = (long long)item.tile * chunk;
         // the chunk's points of this thread together, so their loads overlap
 #pragma unroll
-        for (int i = threadIdx.x; i < kChunk; i += kThreads) {
+        for (int i = threadIdx.x; i < kLsChunk; i += kThreads) {
             const long long q = q0 + i;
-            if (q >= g.N) continue;
+            if (i >= chunk || q >= g.N) continue;
             int idx[3];
             index_of(g, q, idx);
             const T gm = ls_grad<T>(g, src, q, idx);
@@ -470,16 +470,16 @@ k_ls_length(const T *__restrict__ phi, int nx, int ny, double hx, double hy, LsL
 }
 
 void launch_ls_stage(int fp64, const GridDev *g, const Item *it, int nitems, int stage,
-                     double fdt, int nwg, hipStream_t s)
+                     double fdt, int chunk, int nwg, hipStream_t s)
 {
     if (nitems <= 0) return;
     nwg = std::min(nwg, nitems);
     if (fp64)
         hipLaunchKernelGGL(k_ls_stage<double>, dim3(nwg), dim3(kThreads), 0, s, g, it, nitems,
-                           stage, fdt);
+                           stage, fdt, chunk);
     else
         hipLaunchKernelGGL(k_ls_stage<float>, dim3(nwg), dim3(kThreads), 0, s, g, it, nitems,
-                           stage, fdt);
+                           stage, fdt, chunk);
 }
 
 void launch_ls_face(int fp64, const GridDev *g, const Item *it, int nitems, int l, int stage,
