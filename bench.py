@@ -479,6 +479,88 @@ def run_burnback(args):
                    "march_4096_stage_GBps": bw, "march_4096_frac_of_8TBps": bw / HBM_PEAK_GBS}}
 
 
+def run_moving(args):
+    """Moving walls (the unsteady cases of Sec. 6), FP32, E4 LAD pseudo-HJ
+    at eps 0.15 and sigma 0.5, stopped at max change <= 1e-5: a piston in
+    an annular bore (128 x 49 x 97 O-grid, half a stroke, h 1.4 -> 0.6 in
+    24 physical steps) and a cube bouncing between a floor and a ceiling
+    (129^3 Cartesian grid, the cube a moving mask, 24 steps over 6 time
+    units: three bounces).  Each sequence runs cold (every step from zero)
+    and warm (every step from the previous step's field); grids are built
+    before the timed region, placing them (coordinates, metrics, mask) is
+    inside it."""
+    import torch
+    from paper_2111_09859_amd import api, grids as G
+    s = api.Solver(0)
+    steps = args.moving_steps
+    m = api.make_method(equation="HJ", gamma="LAD", eps=0.15, scheme="E4", alpha_f=ALPHA_F,
+                        sigma=0.5, tol=1e-5, max_iter=20000, stall_window=1000,
+                        precision="fp32")
+    hs = G.piston_stroke(2 * steps)[: steps + 1]
+    zs = G.bounce_heights(steps, 6.0)
+    cases = {
+        "piston": [G.piston(128, 49, 97, h) for h in hs],
+        "cube": [G.bouncing_cube(129, z) for z in zs],
+    }
+
+    def probe(name, spec, phi):
+        """Field and exact distance at a fixed point off the ridges: the
+        piston's at r = 0.5 (0.25 from the rod), theta = 0, z = 0.5, linear
+        in z between grid planes; the cube's at the node (0.25, 0.5, 0.5)
+        beside its path."""
+        if name == "piston":
+            hz = spec.meta["h"] / (spec.n[2] - 1)
+            k = min(int(0.5 / hz), spec.n[2] - 2)
+            w = 0.5 / hz - k
+            j = (spec.n[1] - 1) // 3
+            v = (1 - w) * phi[k, j, 0] + w * phi[k + 1, j, 0]
+            return float(v), min(0.25, 0.5, spec.meta["h"] - 0.5)
+        n = spec.n[0] - 1
+        q = (n // 2, n // 2, n // 4)
+        return float(phi[q]), float(spec.exact[q])
+
+    out = {}
+    total_steps, total_warm = 0, 0.0
+    for name, specs in cases.items():
+        s.autotune(s.prepare(specs[0], "E4", "fp32"), m, iters=10)
+        rec = {"points": specs[0].npoints}
+        for mode in ("cold", "warm"):
+            probes = []
+
+            def on_step(k, spec, res, name=name, probes=probes):
+                if k % 4 == 0 or k == len(specs) - 1:
+                    v, e = probe(name, spec, res["phi"].cpu().numpy())
+                    probes.append([k, round(v, 5), round(e, 5)])
+
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, _ = s.solve_sequence(specs, m, "E4", "fp32", warm=mode == "warm",
+                                     on_step=on_step)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            its = [i for _, i in st]
+            rec[mode] = {"s": dt, "iters_total": int(sum(its)), "iters_first": its[0],
+                         "iters_later_mean": float(np.mean(its[1:])),
+                         "status": sorted(set(c for c, _ in st)), "probe": probes}
+            print(f"[moving {name} {mode}] {dt:.2f} s, iterations {its}", file=sys.stderr,
+                  flush=True)
+        rec["warm_speedup_s"] = rec["cold"]["s"] / rec["warm"]["s"]
+        rec["warm_iters_ratio_later"] = (rec["cold"]["iters_later_mean"]
+                                         / rec["warm"]["iters_later_mean"])
+        out[name] = rec
+        total_steps += len(specs)
+        total_warm += rec["warm"]["s"]
+    return {
+        "metric": "moving-wall physical steps/s", "value": total_steps / total_warm,
+        "unit": "steps/s", "n_gpus": 1, "steps": total_steps, "warmup": 0,
+        "ms_per_step": 1e3 * total_warm / total_steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"piston 128x49x97 ({steps + 1} positions, half a stroke) and "
+                               f"bouncing cube 129^3 ({steps + 1} positions over three bounces), "
+                               "E4 LAD pseudo-HJ to 1e-5, warm-started",
+                   "cases": out}}
+
+
 def run_serve(args):
     """Config 5 (bounded sample): open-loop Poisson arrivals (200 req/s) of
     2D grids 129^2..2049^2 and 3D ducts 64^3..192^3 into the continuous-
@@ -600,6 +682,7 @@ def main():
     ap.add_argument("--burn-steps", type=int, default=500)
     ap.add_argument("--burn-big", type=int, default=4096)
     ap.add_argument("--burn-big-steps", type=int, default=40)
+    ap.add_argument("--moving-steps", type=int, default=24)
     args = ap.parse_args()
     global ALPHA_F
     if args.alpha_f is not None:
@@ -626,6 +709,9 @@ def main():
         return
     if args.workload == "burnback":
         print(json.dumps(run_burnback(args)), flush=True)
+        return
+    if args.workload == "moving":
+        print(json.dumps(run_moving(args)), flush=True)
         return
     spec, kw, desc = workload(args.workload)
     if args.alpha_f is not None:

@@ -154,6 +154,34 @@ class Solver:
         return L.wd_tune_get(self.ctx, prep.desc, PRECISIONS["fp64" if prep.dtype == self.torch.float64
                                                              else "fp32"])
 
+    # -- moving walls (the unsteady cases of Sec. 6) --------------------
+    def solve_sequence(self, specs, method: L.wd_method, scheme="E4", precision="fp64",
+                       warm=True, on_step=None):
+        """Wall distance while the walls move: one pseudo-time solve per
+        physical time step, on that step's grid (the same index dimensions
+        at every step; metrics, mask and walls may change).  With warm,
+        each solve after the first starts from the previous step's field at
+        the same grid indices, the previous physical time step's solution
+        being the initial estimate; without, every solve starts from zero.
+        on_step(k, spec, result) is called after each step's solve (the
+        result's field is overwritten by the next step).  Returns the list
+        of (status, iterations) and the last step's result."""
+        torch = self.torch
+        phi, out, steps = None, None, []
+        for k, spec in enumerate(specs):
+            prep = self.prepare(spec, scheme, precision)
+            m = L.wd_method.from_buffer_copy(method)
+            m.warm_start = int(bool(warm) and phi is not None)
+            if phi is None or tuple(phi.shape) != tuple(spec.shape):
+                if m.warm_start:
+                    raise ValueError("solve_sequence: grid dimensions changed between steps")
+                phi = torch.zeros(spec.shape, dtype=prep.dtype, device=self.device)
+            out = self.solve(prep, m, phi=phi, hist_cap=1)
+            steps.append((out["status"], out["iters"]))
+            if on_step is not None:
+                on_step(k, spec, out)
+        return steps, out
+
     # -- level-set burnback (Sec. 5.5) ---------------------------------
     def _prec(self, prep: Prepared):
         return L.WD_FP64 if prep.dtype == self.torch.float64 else L.WD_FP32

@@ -244,6 +244,93 @@ def star_grain(n: int = 512, step: int = 0, **kw) -> GridSpec:
                     h=(h, h, 1.0), mask=mask, meta={"step": step})
 
 
+# ---------------------------------------------------------------------------
+# Moving walls (the unsteady canonical cases of Sec. 6): one grid per
+# physical time step, the same index dimensions at every step.
+def piston(ntheta: int = 64, nr: int = 25, nz: int = 33, h: float = 1.0,
+           R: float = 0.25, Rb: float = 1.0) -> GridSpec:
+    """Piston-cylinder stand-in: the annular bore R <= r <= Rb (a rod on the
+    axis keeps the O-grid free of a singular line), closed by the cylinder
+    head at z = 0 and the piston face at z = h.  Walls on the four r and z
+    faces, theta periodic; uniform spacing in r and z, so moving the piston
+    only rescales z.  Exact d = min(r - R, Rb - r, z, h - z)."""
+    t = 2.0 * np.pi * np.arange(ntheta) / ntheta
+    r = R + (Rb - R) * np.arange(nr) / (nr - 1)
+    z = h * np.arange(nz) / (nz - 1)
+    Z, Rr, T = np.meshgrid(z, r, t, indexing="ij")
+    exact = np.minimum(np.minimum(Rr - R, Rb - Rr), np.minimum(Z, h - Z))
+    return GridSpec("piston", 3, (ntheta, nr, nz),
+                    ((PERIODIC, PERIODIC), (WALL, WALL), (WALL, WALL)),
+                    coords=np.stack([Rr * np.cos(T), Rr * np.sin(T), Z]),
+                    exact=exact, meta={"h": h, "R": R, "Rb": Rb})
+
+
+def piston_stroke(steps: int, h0: float = 1.0, amp: float = 0.4) -> np.ndarray:
+    """Piston positions h_k = h0 + amp cos(2 pi k / steps), k = 0..steps:
+    one full stroke (top dead centre, bottom, back)."""
+    k = np.arange(steps + 1)
+    return h0 + amp * np.cos(2.0 * np.pi * k / steps)
+
+
+def bouncing_cube(n: int = 65, zb: float = 0.5, side: float = 0.25,
+                  cx: float = 0.5, cy: float = 0.5) -> GridSpec:
+    """Cube-between-walls stand-in: Cartesian n^3 grid on [0, 1]^3, walls at
+    the floor z = 0 and the ceiling z = 1, zero normal gradient on the four
+    sides, and a solid cube (mask 1, surface included) whose faces lie on
+    grid planes: its extents are snapped to the nearest nodes, its bottom
+    at zb.  Exact d = min(z, 1 - z, distance to the snapped cube)."""
+    h = 1.0 / (n - 1)
+    w = int(round(side / h))
+    i0 = int(round(cx / h - 0.5 * w))
+    j0 = int(round(cy / h - 0.5 * w))
+    k0 = min(max(int(round(zb / h)), 0), n - 1 - w)
+    x = np.arange(n) * h
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    lo = (i0 * h, j0 * h, k0 * h)
+    hi = ((i0 + w) * h, (j0 + w) * h, (k0 + w) * h)
+
+    def gap(c, a, b):
+        return np.maximum(np.maximum(a - c, c - b), 0.0)
+
+    box = np.sqrt(gap(X, lo[0], hi[0]) ** 2 + gap(Y, lo[1], hi[1]) ** 2
+                  + gap(Z, lo[2], hi[2]) ** 2)
+    exact = np.minimum(np.minimum(Z, 1.0 - Z), box)
+    inside = ((X >= lo[0] - 1e-12) & (X <= hi[0] + 1e-12) & (Y >= lo[1] - 1e-12)
+              & (Y <= hi[1] + 1e-12) & (Z >= lo[2] - 1e-12) & (Z <= hi[2] + 1e-12))
+    return GridSpec("bouncing_cube", 3, (n, n, n),
+                    ((NEUMANN, NEUMANN), (NEUMANN, NEUMANN), (WALL, WALL)),
+                    h=(h, h, h), mask=inside.astype(np.uint8), exact=exact,
+                    meta={"lo": lo, "hi": hi, "zb": k0 * h})
+
+
+def bounce_heights(steps: int, t_end: float, z0: float = 0.6, g: float = 1.0,
+                   kept: float = 0.8) -> np.ndarray:
+    """Bottom height of a cube dropped from rest at z0 under gravity g onto
+    the floor, keeping the fraction `kept` of its energy at every bounce
+    (the rebound speed scales by sqrt(kept)); sampled at t_k = k t_end /
+    steps, k = 0..steps.  Closed form per flight."""
+    out = np.empty(steps + 1)
+    for k in range(steps + 1):
+        t = k * t_end / steps
+        # first flight: the drop
+        t_hit = math.sqrt(2.0 * z0 / g)
+        if t < t_hit:
+            out[k] = z0 - 0.5 * g * t * t
+            continue
+        t -= t_hit
+        v = g * t_hit
+        z = 0.0
+        while True:
+            v *= math.sqrt(kept)
+            flight = 2.0 * v / g
+            if flight < 1e-9 or t < flight:
+                z = max(v * t - 0.5 * g * t * t, 0.0) if flight >= 1e-9 else 0.0
+                break
+            t -= flight
+        out[k] = z
+    return out
+
+
 def cartesian_points(spec: GridSpec) -> np.ndarray:
     """(npoints, ndim) physical coordinates of a grid, x fastest."""
     if spec.coords is not None:
