@@ -538,10 +538,12 @@ def run_moving(args):
                                      on_step=on_step)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            its = [i for _, i in st]
+            its = [i for _, i, _ in st]
             rec[mode] = {"s": dt, "iters_total": int(sum(its)), "iters_first": its[0],
                          "iters_later_mean": float(np.mean(its[1:])),
-                         "status": sorted(set(c for c, _ in st)), "probe": probes}
+                         "status": sorted(set(c for c, _, _ in st)),
+                         "restarted_cold": [k for k, (_, _, r) in enumerate(st) if r],
+                         "probe": probes}
             print(f"[moving {name} {mode}] {dt:.2f} s, iterations {its}", file=sys.stderr,
                   flush=True)
         rec["warm_speedup_s"] = rec["cold"]["s"] / rec["warm"]["s"]

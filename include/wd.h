@@ -112,7 +112,14 @@ typedef struct wd_method {
                              crosses the grid do not count; 0 disables      */
     int precision;        /* wd_precision of fields and arithmetic; the
                              convergence reductions are always FP64         */
-    int warm_start;       /* 1: phi holds the initial guess; 0: phi = 0     */
+    int warm_start;       /* 1: phi holds the initial guess (e.g. the
+                             previous physical time step's field when walls
+                             move, Sec. 6); wall and solid points are set to
+                             zero first.  A guess that jumps by much more
+                             than the spacing beside a wall can undershoot
+                             below zero and run away (Gamma is 0 there):
+                             callers watch for phi < 0 and restart cold.
+                             0: phi = 0                                     */
 } wd_method;
 
 typedef struct wd_ctx wd_ctx;

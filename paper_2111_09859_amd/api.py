@@ -156,7 +156,7 @@ class Solver:
 
     # -- moving walls (the unsteady cases of Sec. 6) --------------------
     def solve_sequence(self, specs, method: L.wd_method, scheme="E4", precision="fp64",
-                       warm=True, on_step=None):
+                       warm=True, on_step=None, probe=300):
         """Wall distance while the walls move: one pseudo-time solve per
         physical time step, on that step's grid (the same index dimensions
         at every step; metrics, mask and walls may change).  With warm,
@@ -164,8 +164,18 @@ class Solver:
         the same grid indices, the previous physical time step's solution
         being the initial estimate; without, every solve starts from zero.
         on_step(k, spec, result) is called after each step's solve (the
-        result's field is overwritten by the next step).  Returns the list
-        of (status, iterations) and the last step's result."""
+        result's field is overwritten by the next step).
+
+        A warm estimate far from the new walls (a wall that moved many
+        cells in one step) can start a runaway: the central scheme
+        undershoots below zero beside a new wall, where Gamma = 0 leaves
+        only 1 - |grad phi|^2, which drives the point further down.  So a
+        warm step first runs `probe` pseudo-steps; a field that has gone
+        below -0.1 of its maximum there (a transient undershoot beside a
+        new wall is a small fraction of that and recovers), or a warm solve
+        that does not end converged or stagnated, is solved again from zero.  Returns the list
+        of (status, iterations, restarted) -- iterations include a failed
+        warm attempt -- and the last step's result."""
         torch = self.torch
         phi, out, steps = None, None, []
         for k, spec in enumerate(specs):
@@ -176,8 +186,27 @@ class Solver:
                 if m.warm_start:
                     raise ValueError("solve_sequence: grid dimensions changed between steps")
                 phi = torch.zeros(spec.shape, dtype=prep.dtype, device=self.device)
-            out = self.solve(prep, m, phi=phi, hist_cap=1)
-            steps.append((out["status"], out["iters"]))
+            restarted, spent = False, 0
+            if m.warm_start:
+                first = L.wd_method.from_buffer_copy(m)
+                first.max_iter = min(probe, m.max_iter)
+                out = self.solve(prep, first, phi=phi, hist_cap=1, check=False)
+                spent = out["iters"]
+                bad = out["status"] == L.WD_ERR_DIVERGED or bool(
+                    phi.min() < -0.1 * phi.abs().max())
+                if not bad and out["status"] == L.WD_NOT_CONVERGED and spent < m.max_iter:
+                    rest = L.wd_method.from_buffer_copy(m)
+                    rest.max_iter = m.max_iter - spent
+                    out = self.solve(prep, rest, phi=phi, hist_cap=1, check=False)
+                    out["iters"] += spent
+                    spent = out["iters"]
+                if bad or out["status"] not in (0, L.WD_STAGNATED):
+                    restarted = True
+                    m.warm_start = 0
+            if not m.warm_start:
+                out = self.solve(prep, m, phi=phi, hist_cap=1)
+                out["iters"] += spent
+            steps.append((out["status"], out["iters"], restarted))
             if on_step is not None:
                 on_step(k, spec, out)
         return steps, out

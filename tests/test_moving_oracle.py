@@ -130,3 +130,24 @@ def test_piston_converged_follows_wall(oracle, h):
     k = np.arange(spec.n[2])
     near_head = k * h / (spec.n[2] - 1) < 0.3
     assert err[near_head, 4, :].max() < 0.25 * cell
+
+
+@pytest.mark.parametrize("n,level,runaway", [(129, 0.3, True), (65, 0.3, False),
+                                              (129, 0.1, False)])
+def test_steep_warm_estimate_runs_away(oracle, n, level, runaway):
+    """A warm estimate that jumps from the wall's zero to `level` within one
+    cell: with a jump of 0.3 over 1/128 the central march undershoots below
+    zero beside the wall, Gamma = max(0, eps phi) vanishes there and the
+    point runs away (far below -0.1 of the field's maximum within 300
+    pseudo-steps, the bound the moving-wall sequences restart at); half the
+    jump per cell, or a third of it, recovers and stays non-negative."""
+    spec = G.box2d(n)
+    phi, st, it, hist = oracle.solve(spec, lad(oracle, fixed=300),
+                                     phi0=np.full(spec.shape, level))
+    assert it == 300
+    if runaway:
+        assert phi.min() < -0.1 * np.abs(phi).max()
+        assert hist[-1, 0] > 10 * hist[100, 0]
+    else:
+        assert phi.min() >= 0.0
+        assert hist[-1, 0] < hist[100, 0]
