@@ -48,6 +48,12 @@ constexpr int kLsChunk = 4096;  // most points per work item of a level-set stag
 // chunk: points per work item, kThreads .. kLsChunk
 void launch_ls_stage(int fp64, const GridDev *g, const Item *it, int nitems, int stage,
                      double fdt, int chunk, int nwg, hipStream_t s);
+// 2D grids (grids[0], n0 x n1): lanes along x, kLsRows rows per thread;
+// -1 (nothing launched) when the launch grid would not fit
+constexpr int kLsLanes = 256;
+constexpr int kLsRows = 4;
+int launch_ls_stage2d(int fp64, const GridDev *g, int n0, int n1, int stage, double fdt,
+                      hipStream_t s);
 void launch_ls_face(int fp64, const GridDev *g, const Item *it, int nitems, int l, int stage,
                     int nwg, hipStream_t s);
 void launch_ls_signed(int fp64, long long n, const unsigned char *solid, const void *ds,

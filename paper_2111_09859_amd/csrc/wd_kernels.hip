@@ -356,6 +356,84 @@ k_ls_stage(const GridDev *__restrict__ grids, const Item *__restrict__ items, in
     }
 }
 
+// Upwind-switched one-sided difference of one direction (the choice of
+// ls_grad), scaled by 1/h: b = f0 - f_minus, fw = f_plus - f0; a missing
+// side copies the other (none: zero).
+template <typename T>
+__device__ inline T ls_side(T b, T fw, bool hm, bool hp, T ih)
+{
+    if (!hm && !hp) return (T)0;
+    if (!hm) b = fw;
+    if (!hp) fw = b;
+    T d;
+    if (fw + b >= (T)0) d = b >= (T)0 ? b : (T)0;
+    else d = fw < (T)0 ? fw : (T)0;
+    return d * ih;
+}
+
+// One RK4 stage on a 2D grid: lanes along x (one point per thread and
+// row, every load coalesced), each thread walking kLsRows rows with the
+// rows below and above held in registers, so a point costs its own row's
+// three loads and no index division.  Same arithmetic as k_ls_stage.
+template <typename T>
+__global__ void __launch_bounds__(kLsLanes)
+k_ls_stage2d(const GridDev *__restrict__ grids, int stage, double fdt)
+{
+    const GridDev &g = grids[0];
+    const int n0 = g.n[0], n1 = g.n[1];
+    const int x = blockIdx.x * kLsLanes + threadIdx.x;
+    const int y0 = blockIdx.y * kLsRows;
+    if (x >= n0 || y0 >= n1) return;
+    gptr<const T> src;
+    gptr<T> dst;
+    ls_buffers<T>(g, stage, src, dst);
+    gptr<const T> phi = gcast<const T>(g.phi);
+    gptr<T> acc = gcast<T>(g.acc);
+    const T h = (T)fdt;
+    const bool px = g.periodic[0] != 0, py = g.periodic[1] != 0;
+    const bool hm0 = x > 0 || px, hp0 = x < n0 - 1 || px;
+    const int xm = x > 0 ? x - 1 : n0 - 1, xp = x < n0 - 1 ? x + 1 : 0;
+    const T ih0 = (T)g.invh[0], ih1 = (T)g.invh[1];
+    const long long s1 = g.stride[1];
+    // rolling column: below (y - 1), here (y)
+    int y = y0;
+    T here = src[(long long)y * s1 + x];
+    T below = (T)0;
+    if (y > 0) below = src[(long long)(y - 1) * s1 + x];
+    else if (py) below = src[(long long)(n1 - 1) * s1 + x];
+    const int y1 = min(n1, y0 + kLsRows);
+    for (; y < y1; ++y) {
+        const long long row = (long long)y * s1;
+        const long long q = row + x;
+        T above = (T)0;
+        if (y < n1 - 1) above = src[row + s1 + x];
+        else if (py) above = src[x];
+        const T left = src[row + xm], right = src[row + xp];
+        const bool hm1 = y > 0 || py, hp1 = y < n1 - 1 || py;
+        const T d0 = ls_side<T>(here - left, right - here, hm0, hp0, ih0);
+        const T d1 = ls_side<T>(here - below, above - here, hm1, hp1, ih1);
+        T s2 = (T)0;
+        s2 += d0 * d0;
+        s2 += d1 * d1;
+        const T gm = sqrt(s2);
+        if (stage == 0) {
+            const T pn = here;
+            acc[q] = pn - h * (T)(1.0 / 6.0) * gm;
+            dst[q] = pn - h * (T)0.5 * gm;
+        } else if (stage == 1) {
+            acc[q] = acc[q] - h * (T)(1.0 / 3.0) * gm;
+            dst[q] = phi[q] - h * (T)0.5 * gm;
+        } else if (stage == 2) {
+            acc[q] = acc[q] - h * (T)(1.0 / 3.0) * gm;
+            dst[q] = phi[q] - h * gm;
+        } else {
+            dst[q] = acc[q] - h * (T)(1.0 / 6.0) * gm;
+        }
+        below = here;
+        here = above;
+    }
+}
+
 // zero normal gradient on both faces normal to l of the stage's output:
 // f_b = (4 f_1 - f_2) / 3 along the grid line
 template <typename T>
@@ -480,6 +558,20 @@ void launch_ls_stage(int fp64, const GridDev *g, const Item *it, int nitems, int
     else
         hipLaunchKernelGGL(k_ls_stage<float>, dim3(nwg), dim3(kThreads), 0, s, g, it, nitems,
                            stage, fdt, chunk);
+}
+
+int launch_ls_stage2d(int fp64, const GridDev *g, int n0, int n1, int stage, double fdt,
+                      hipStream_t s)
+{
+    const long long bx = (n0 + kLsLanes - 1) / kLsLanes;
+    const long long by = (n1 + kLsRows - 1) / kLsRows;
+    if (bx < 1 || by < 1 || bx > 0x7fffffffLL || by > 65535) return -1;
+    dim3 grid((unsigned)bx, (unsigned)by), block(kLsLanes);
+    if (fp64)
+        hipLaunchKernelGGL(k_ls_stage2d<double>, grid, block, 0, s, g, stage, fdt);
+    else
+        hipLaunchKernelGGL(k_ls_stage2d<float>, grid, block, 0, s, g, stage, fdt);
+    return 0;
 }
 
 void launch_ls_face(int fp64, const GridDev *g, const Item *it, int nitems, int l, int stage,
