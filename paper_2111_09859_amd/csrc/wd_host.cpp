@@ -1685,11 +1685,18 @@ int wd_levelset_advance(wd_ctx *ctx, const wd_grid_desc *desc, int precision, do
     const int chunk = g.N >= 8LL * ctx->cus * kLsChunk ? kLsChunk : kChunk;
     // 2D grids take the row-walking stage kernel
     const bool rows2d = g.ndim == 2 && (g.n[1] + kLsRows - 1) / kLsRows <= 65535;
+    // and both directions' faces in one launch (none when both are periodic)
+    const bool faces2d = g.ndim == 2 && g.n[0] >= 4 && g.n[1] >= 4 &&
+                         !(g.periodic[0] && g.periodic[1]);
     auto one_step = [&]() {
         for (int st = 0; st < 4; ++st) {
             if (!rows2d || launch_ls_stage2d(P.fp64, P.d_grids, g.n[0], g.n[1], st, fdt, s))
                 launch_ls_stage(P.fp64, P.d_grids, items, (int)((g.N + chunk - 1) / chunk), st,
                                 fdt, chunk, nwg, s);
+            if (faces2d) {
+                launch_ls_face2d(P.fp64, P.d_grids, g.n[0], g.n[1], st, s);
+                continue;
+            }
             for (int l = 0; l < g.ndim; ++l) {
                 if (g.periodic[l]) continue;
                 const int nf = (int)((g.N / g.n[l] + kChunk - 1) / kChunk);

@@ -54,6 +54,8 @@ constexpr int kLsLanes = 256;
 constexpr int kLsRows = 4;
 int launch_ls_stage2d(int fp64, const GridDev *g, int n0, int n1, int stage, double fdt,
                       hipStream_t s);
+// both directions' faces of a 2D grid (grids[0], n0, n1 >= 4) in one launch
+void launch_ls_face2d(int fp64, const GridDev *g, int n0, int n1, int stage, hipStream_t s);
 void launch_ls_face(int fp64, const GridDev *g, const Item *it, int nitems, int l, int stage,
                     int nwg, hipStream_t s);
 void launch_ls_signed(int fp64, long long n, const unsigned char *solid, const void *ds,

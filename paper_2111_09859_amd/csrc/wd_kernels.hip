@@ -467,6 +467,47 @@ k_ls_face(const GridDev *__restrict__ grids, const Item *__restrict__ items, int
     }
 }
 
+// The zero-gradient faces of a 2D stage output (both directions, at least
+// 4 x 4 points) in one launch, with the result of the x faces followed by
+// the y faces: thread t < n1 takes the x faces of row t (rows 1 .. n1 - 2;
+// the y faces overwrite rows 0 and n1 - 1, so with y faces present those
+// rows are skipped), thread n1 + i the y faces of column i.  A corner
+// column's y face reads rows 1, 2 (n1 - 2, n1 - 3) after their x faces, so
+// it forms those two values itself from the same interior points.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_ls_face2d(const GridDev *__restrict__ grids, int stage)
+{
+    const GridDev &g = grids[0];
+    gptr<const T> src;
+    gptr<T> f;
+    ls_buffers<T>(g, stage, src, f);
+    const int n0 = g.n[0], n1 = g.n[1];
+    const bool xf = !g.periodic[0], yf = !g.periodic[1];
+    const long long s1 = g.stride[1];
+    const T third = (T)(1.0 / 3.0);
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (t < n1) {
+        const int y = (int)t;
+        if (!xf || (yf && (y == 0 || y == n1 - 1))) return;
+        const long long r = (long long)y * s1;
+        f[r] = ((T)4 * f[r + 1] - f[r + 2]) * third;
+        f[r + n0 - 1] = ((T)4 * f[r + n0 - 2] - f[r + n0 - 3]) * third;
+        return;
+    }
+    if (t >= (long long)n1 + n0 || !yf) return;
+    const int x = (int)(t - n1);
+    // value of row y at column x as the x faces leave it
+    auto at = [&](int y) -> T {
+        const long long r = (long long)y * s1;
+        if (xf && x == 0) return ((T)4 * f[r + 1] - f[r + 2]) * third;
+        if (xf && x == n0 - 1) return ((T)4 * f[r + n0 - 2] - f[r + n0 - 3]) * third;
+        return f[r + x];
+    };
+    f[x] = ((T)4 * at(1) - at(2)) * third;
+    f[(long long)(n1 - 1) * s1 + x] = ((T)4 * at(n1 - 2) - at(n1 - 3)) * third;
+}
+
 // phi_s = d_solid on solid points, -d_gas elsewhere
 template <typename T>
 __global__ void k_ls_signed(long long n, const unsigned char *__restrict__ solid,
@@ -572,6 +613,16 @@ int launch_ls_stage2d(int fp64, const GridDev *g, int n0, int n1, int stage, dou
     else
         hipLaunchKernelGGL(k_ls_stage2d<float>, grid, block, 0, s, g, stage, fdt);
     return 0;
+}
+
+void launch_ls_face2d(int fp64, const GridDev *g, int n0, int n1, int stage, hipStream_t s)
+{
+    const long long n = (long long)n0 + n1;
+    dim3 grid((unsigned)((n + kThreads - 1) / kThreads)), block(kThreads);
+    if (fp64)
+        hipLaunchKernelGGL(k_ls_face2d<double>, grid, block, 0, s, g, stage);
+    else
+        hipLaunchKernelGGL(k_ls_face2d<float>, grid, block, 0, s, g, stage);
 }
 
 void launch_ls_face(int fp64, const GridDev *g, const Item *it, int nitems, int l, int stage,
