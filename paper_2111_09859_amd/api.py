@@ -173,9 +173,10 @@ class Solver:
         warm step first runs `probe` pseudo-steps; a field that has gone
         below -0.1 of its maximum there (a transient undershoot beside a
         new wall is a small fraction of that and recovers), or a warm solve
-        that does not end converged or stagnated, is solved again from zero.  Returns the list
-        of (status, iterations, restarted) -- iterations include a failed
-        warm attempt -- and the last step's result."""
+        that does not end converged or stagnated, is solved again from
+        zero.  Returns the list of (status, iterations, restarted) --
+        iterations include a failed warm attempt -- and the last step's
+        result."""
         torch = self.torch
         phi, out, steps = None, None, []
         for k, spec in enumerate(specs):
