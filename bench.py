@@ -408,8 +408,9 @@ def run_burnback(args):
     paper's 1e-5), then RK4 steps of d phi_s/dt + F |grad phi_s| = 0 at
     F = 0.3 with dt = h / (2 F), the lengths of the levels 0, 0.05, 0.1 and
     -0.02 every 50 steps (the burning perimeter S_b per unit depth is the
-    level 0).  A second, march-only run on a 4096^2 grid from the analytic
-    six-lobed front gives the stage kernels' bandwidth."""
+    level 0).  March-only runs on a 4096^2 grid from the analytic six-lobed
+    front and on a 256^3 grid (x periodic) from a wavy tube give the stage
+    kernels' bandwidth in 2D and 3D."""
     import torch
     from paper_2111_09859_amd import api, grids as G
     s = api.Solver(0)
@@ -464,6 +465,23 @@ def run_burnback(args):
     nb = big.npoints
     step_bytes = 16.0 * 4 * nb
     bw = step_bytes * args.burn_big_steps / t_big / 1e9
+    # and a 3D march: the 256^3 duct grid (x periodic) from a wavy tube
+    cube = G.duct(args.burn_big3)
+    k, j, i = np.meshgrid(*(np.arange(n) for n in reversed(cube.n)), indexing="ij")
+    tube = (np.hypot(j * cube.h[1] - 0.5, k * cube.h[2] - 0.5) - 0.25
+            + 0.05 * np.sin(2 * np.pi * i / cube.n[0]))
+    del k, j, i
+    pc = s.prepare(cube, "UW", "fp32")
+    p3 = torch.as_tensor(tube, dtype=torch.float32, device=s.device).contiguous()
+    del tube
+    cdt = 0.5 * min(cube.h) / F
+    s.levelset_advance(pc, p3, F, cdt, 4)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    s.levelset_advance(pc, p3, F, cdt, args.burn_big_steps)
+    torch.cuda.synchronize()
+    t_3d = time.perf_counter() - t3
+    bw3 = 16.0 * 4 * cube.npoints * args.burn_big_steps / t_3d / 1e9
     return {
         "metric": "level-set point-updates/s", "value": gas.npoints * done / t_march,
         "unit": "point-updates/s", "n_gpus": 1, "steps": done, "warmup": 0,
@@ -476,7 +494,10 @@ def run_burnback(args):
                    "levels": levels, "lengths": [[t, l] for t, l in series],
                    "march_4096_ms_per_step": 1e3 * t_big / args.burn_big_steps,
                    "march_4096_point_updates_per_s": nb * args.burn_big_steps / t_big,
-                   "march_4096_stage_GBps": bw, "march_4096_frac_of_8TBps": bw / HBM_PEAK_GBS}}
+                   "march_4096_stage_GBps": bw, "march_4096_frac_of_8TBps": bw / HBM_PEAK_GBS,
+                   "march_3d_grid": list(cube.n),
+                   "march_3d_ms_per_step": 1e3 * t_3d / args.burn_big_steps,
+                   "march_3d_stage_GBps": bw3, "march_3d_frac_of_8TBps": bw3 / HBM_PEAK_GBS}}
 
 
 def run_moving(args):
@@ -684,6 +705,7 @@ def main():
     ap.add_argument("--burn-steps", type=int, default=500)
     ap.add_argument("--burn-big", type=int, default=4096)
     ap.add_argument("--burn-big-steps", type=int, default=40)
+    ap.add_argument("--burn-big3", type=int, default=256)
     ap.add_argument("--moving-steps", type=int, default=24)
     args = ap.parse_args()
     global ALPHA_F

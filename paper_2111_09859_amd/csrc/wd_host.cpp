@@ -1683,14 +1683,15 @@ int wd_levelset_advance(wd_ctx *ctx, const wd_grid_desc *desc, int precision, do
     // large grids: 4096-point work items (more loads in flight per thread)
     // while there are still 8 per compute unit; else 1024-point ones
     const int chunk = g.N >= 8LL * ctx->cus * kLsChunk ? kLsChunk : kChunk;
-    // 2D grids take the row-walking stage kernel
-    const bool rows2d = g.ndim == 2 && (g.n[1] + kLsRows - 1) / kLsRows <= 65535;
+    // the row-walking stage kernel (falls back to the work-item one when
+    // its launch grid would not fit)
+    const int n2 = g.ndim == 3 ? g.n[2] : 1;
     // and both directions' faces in one launch (none when both are periodic)
     const bool faces2d = g.ndim == 2 && g.n[0] >= 4 && g.n[1] >= 4 &&
                          !(g.periodic[0] && g.periodic[1]);
     auto one_step = [&]() {
         for (int st = 0; st < 4; ++st) {
-            if (!rows2d || launch_ls_stage2d(P.fp64, P.d_grids, g.n[0], g.n[1], st, fdt, s))
+            if (launch_ls_stage_rows(P.fp64, P.d_grids, g.n[0], g.n[1], n2, st, fdt, s))
                 launch_ls_stage(P.fp64, P.d_grids, items, (int)((g.N + chunk - 1) / chunk), st,
                                 fdt, chunk, nwg, s);
             if (faces2d) {

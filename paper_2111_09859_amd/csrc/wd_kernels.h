@@ -48,12 +48,13 @@ constexpr int kLsChunk = 4096;  // most points per work item of a level-set stag
 // chunk: points per work item, kThreads .. kLsChunk
 void launch_ls_stage(int fp64, const GridDev *g, const Item *it, int nitems, int stage,
                      double fdt, int chunk, int nwg, hipStream_t s);
-// 2D grids (grids[0], n0 x n1): lanes along x, kLsRows rows per thread;
-// -1 (nothing launched) when the launch grid would not fit
+// 2D/3D grids (grids[0], n0 x n1 x n2, n2 = 1 in 2D): lanes along x,
+// kLsRows rows per thread, one z plane per launch-grid layer; -1 (nothing
+// launched) when the launch grid would not fit
 constexpr int kLsLanes = 256;
 constexpr int kLsRows = 4;
-int launch_ls_stage2d(int fp64, const GridDev *g, int n0, int n1, int stage, double fdt,
-                      hipStream_t s);
+int launch_ls_stage_rows(int fp64, const GridDev *g, int n0, int n1, int n2, int stage,
+                         double fdt, hipStream_t s);
 // both directions' faces of a 2D grid (grids[0], n0, n1 >= 4) in one launch
 void launch_ls_face2d(int fp64, const GridDev *g, int n0, int n1, int stage, hipStream_t s);
 void launch_ls_face(int fp64, const GridDev *g, const Item *it, int nitems, int l, int stage,

@@ -371,13 +371,14 @@ __device__ inline T ls_side(T b, T fw, bool hm, bool hp, T ih)
     return d * ih;
 }
 
-// One RK4 stage on a 2D grid: lanes along x (one point per thread and
-// row, every load coalesced), each thread walking kLsRows rows with the
-// rows below and above held in registers, so a point costs its own row's
-// three loads and no index division.  Same arithmetic as k_ls_stage.
+// One RK4 stage on a 2D or 3D grid: lanes along x (one point per thread
+// and row, every load coalesced), each thread walking kLsRows rows of one
+// z plane (blockIdx.z) with the rows below and above held in registers,
+// so a point costs three loads of its own row (and two of the planes
+// beside it in 3D) and no index division.  Same arithmetic as k_ls_stage.
 template <typename T>
 __global__ void __launch_bounds__(kLsLanes)
-k_ls_stage2d(const GridDev *__restrict__ grids, int stage, double fdt)
+k_ls_stage_rows(const GridDev *__restrict__ grids, int stage, double fdt)
 {
     const GridDev &g = grids[0];
     const int n0 = g.n[0], n1 = g.n[1];
@@ -395,27 +396,42 @@ k_ls_stage2d(const GridDev *__restrict__ grids, int stage, double fdt)
     const int xm = x > 0 ? x - 1 : n0 - 1, xp = x < n0 - 1 ? x + 1 : 0;
     const T ih0 = (T)g.invh[0], ih1 = (T)g.invh[1];
     const long long s1 = g.stride[1];
+    // third direction: this plane and its neighbours' offsets
+    const bool three = g.ndim == 3;
+    const int z = blockIdx.z, n2 = three ? g.n[2] : 1;
+    const long long s2 = three ? g.stride[2] : 0;
+    const bool pz = three && g.periodic[2] != 0;
+    const bool hm2 = z > 0 || pz, hp2 = z < n2 - 1 || pz;
+    const long long plane = (long long)z * s2;
+    const long long dzm = z > 0 ? -s2 : (long long)(n2 - 1) * s2;
+    const long long dzp = z < n2 - 1 ? s2 : -(long long)(n2 - 1) * s2;
+    const T ih2 = three ? (T)g.invh[2] : (T)0;
     // rolling column: below (y - 1), here (y)
     int y = y0;
-    T here = src[(long long)y * s1 + x];
+    T here = src[plane + (long long)y * s1 + x];
     T below = (T)0;
-    if (y > 0) below = src[(long long)(y - 1) * s1 + x];
-    else if (py) below = src[(long long)(n1 - 1) * s1 + x];
+    if (y > 0) below = src[plane + (long long)(y - 1) * s1 + x];
+    else if (py) below = src[plane + (long long)(n1 - 1) * s1 + x];
     const int y1 = min(n1, y0 + kLsRows);
     for (; y < y1; ++y) {
-        const long long row = (long long)y * s1;
+        const long long row = plane + (long long)y * s1;
         const long long q = row + x;
         T above = (T)0;
         if (y < n1 - 1) above = src[row + s1 + x];
-        else if (py) above = src[x];
+        else if (py) above = src[plane + x];
         const T left = src[row + xm], right = src[row + xp];
         const bool hm1 = y > 0 || py, hp1 = y < n1 - 1 || py;
         const T d0 = ls_side<T>(here - left, right - here, hm0, hp0, ih0);
         const T d1 = ls_side<T>(here - below, above - here, hm1, hp1, ih1);
-        T s2 = (T)0;
-        s2 += d0 * d0;
-        s2 += d1 * d1;
-        const T gm = sqrt(s2);
+        T s2sum = (T)0;
+        s2sum += d0 * d0;
+        s2sum += d1 * d1;
+        if (three) {
+            const T back = src[q + dzm], front = src[q + dzp];
+            const T d2 = ls_side<T>(here - back, front - here, hm2, hp2, ih2);
+            s2sum += d2 * d2;
+        }
+        const T gm = sqrt(s2sum);
         if (stage == 0) {
             const T pn = here;
             acc[q] = pn - h * (T)(1.0 / 6.0) * gm;
@@ -601,17 +617,18 @@ void launch_ls_stage(int fp64, const GridDev *g, const Item *it, int nitems, int
                            stage, fdt, chunk);
 }
 
-int launch_ls_stage2d(int fp64, const GridDev *g, int n0, int n1, int stage, double fdt,
-                      hipStream_t s)
+int launch_ls_stage_rows(int fp64, const GridDev *g, int n0, int n1, int n2, int stage,
+                         double fdt, hipStream_t s)
 {
     const long long bx = (n0 + kLsLanes - 1) / kLsLanes;
     const long long by = (n1 + kLsRows - 1) / kLsRows;
-    if (bx < 1 || by < 1 || bx > 0x7fffffffLL || by > 65535) return -1;
-    dim3 grid((unsigned)bx, (unsigned)by), block(kLsLanes);
+    if (bx < 1 || by < 1 || n2 < 1 || bx > 0x7fffffffLL || by > 65535 || n2 > 65535)
+        return -1;
+    dim3 grid((unsigned)bx, (unsigned)by, (unsigned)n2), block(kLsLanes);
     if (fp64)
-        hipLaunchKernelGGL(k_ls_stage2d<double>, grid, block, 0, s, g, stage, fdt);
+        hipLaunchKernelGGL(k_ls_stage_rows<double>, grid, block, 0, s, g, stage, fdt);
     else
-        hipLaunchKernelGGL(k_ls_stage2d<float>, grid, block, 0, s, g, stage, fdt);
+        hipLaunchKernelGGL(k_ls_stage_rows<float>, grid, block, 0, s, g, stage, fdt);
     return 0;
 }
 

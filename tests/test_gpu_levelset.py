@@ -46,6 +46,14 @@ CASES = [
     ("channel300x37_periodic_x", lambda: G.channel(300, 37),
      lambda s: np.fromfunction(lambda j, i: j / 36 - 0.5 + 0.1 * np.sin(2 * np.pi * i / 300),
                                s.shape), 0.3, 15),
+    # 3D with no periodic face and ragged rows; 3D with two lane blocks
+    ("cube19_sphere", lambda: G.bouncing_cube(19, 0.3),
+     lambda s: np.fromfunction(lambda k, j, i: np.sqrt((i / 18 - 0.5) ** 2 + (j / 18 - 0.5) ** 2
+                                                       + (k / 18 - 0.45) ** 2) - 0.3, s.shape),
+     0.3, 10),
+    ("duct9x9x300_periodic_x", lambda: G.duct(9, nx=300),
+     lambda s: np.fromfunction(lambda k, j, i: np.hypot(j / 8 - 0.5, k / 8 - 0.5) - 0.25
+                               + 0.05 * np.sin(2 * np.pi * i / 300), s.shape), 0.3, 8),
     ("duct17x17x12_periodic_x", lambda: G.duct(17, nx=12),
      lambda s: np.fromfunction(lambda k, j, i: np.hypot(j / 16 - 0.5, k / 16 - 0.45) - 0.2
                                + 0.05 * np.sin(2 * np.pi * i / 12), s.shape), 0.3, 20),
