@@ -310,6 +310,9 @@ int wd_server_create(wd_ctx *ctx, size_t budget_bytes, int max_slots,
  * phi (device) must stay valid until the request finishes.  session >= 0
  * serialises requests of one session in submission order (an unsteady
  * sequence re-solved with warm_start from its previous field); -1 = none.
+ * A warm start far from the new walls can run away below zero (see
+ * wd_method.warm_start): such a request ends WD_ERR_DIVERGED or
+ * WD_NOT_CONVERGED, and the caller resubmits it cold.
  * hist_cap (>= 0) FP64 history pairs are kept for wd_server_history.
  * *req_id receives the request id. */
 int wd_server_submit(wd_server *srv, const wd_grid_desc *desc,
