@@ -372,10 +372,10 @@ __device__ inline T ls_side(T b, T fw, bool hm, bool hp, T ih)
 }
 
 // One RK4 stage on a 2D or 3D grid: lanes along x (one point per thread
-// and row, every load coalesced), each thread walking kLsRows rows of one
-// z plane (blockIdx.z) with the rows below and above held in registers,
-// so a point costs three loads of its own row (and two of the planes
-// beside it in 3D) and no index division.  Same arithmetic as k_ls_stage.
+// and row, every load coalesced), each thread taking kLsRows rows of one
+// z plane (blockIdx.z) with the column of rows shared between them, so a
+// point costs three loads of its own row (and two of the planes beside it
+// in 3D) and no index division.  Same arithmetic as k_ls_stage.
 template <typename T>
 __global__ void __launch_bounds__(kLsLanes)
 k_ls_stage_rows(const GridDev *__restrict__ grids, int stage, double fdt)
@@ -406,47 +406,70 @@ k_ls_stage_rows(const GridDev *__restrict__ grids, int stage, double fdt)
     const long long dzm = z > 0 ? -s2 : (long long)(n2 - 1) * s2;
     const long long dzp = z < n2 - 1 ? s2 : -(long long)(n2 - 1) * s2;
     const T ih2 = three ? (T)g.invh[2] : (T)0;
-    // rolling column: below (y - 1), here (y)
-    int y = y0;
-    T here = src[plane + (long long)y * s1 + x];
-    T below = (T)0;
-    if (y > 0) below = src[plane + (long long)(y - 1) * s1 + x];
-    else if (py) below = src[plane + (long long)(n1 - 1) * s1 + x];
-    const int y1 = min(n1, y0 + kLsRows);
-    for (; y < y1; ++y) {
-        const long long row = plane + (long long)y * s1;
-        const long long q = row + x;
-        T above = (T)0;
-        if (y < n1 - 1) above = src[row + s1 + x];
-        else if (py) above = src[plane + x];
-        const T left = src[row + xm], right = src[row + xp];
+    // every load before the first store (the stage buffers could alias as
+    // far as the compiler knows): the thread's column of rows y0 - 1 ..
+    // y0 + nr, then each row's other operands; both loops fully unrolled,
+    // so every array index is a constant and the arrays stay in registers
+    // (no access past an array's end, not even on a path never taken)
+    const int nr = min(kLsRows, n1 - y0);
+    T col[kLsRows + 2], lft[kLsRows], rgt[kLsRows], bk[kLsRows], fr[kLsRows];
+    T p0[kLsRows], a0[kLsRows];
+    col[0] = (T)0;
+    if (y0 > 0) col[0] = src[plane + (long long)(y0 - 1) * s1 + x];
+    else if (py) col[0] = src[plane + (long long)(n1 - 1) * s1 + x];
+#pragma unroll
+    for (int r = 0; r <= kLsRows; ++r) {
+        const int y = y0 + r;
+        T v = (T)0;
+        if (r <= nr) {   // rows y0 .. y0 + nr - 1 and the row after them
+            if (y < n1) v = src[plane + (long long)y * s1 + x];
+            else if (py) v = src[plane + x];
+        }
+        col[r + 1] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < kLsRows; ++r) {
+        lft[r] = rgt[r] = bk[r] = fr[r] = p0[r] = a0[r] = (T)0;
+        if (r >= nr) continue;
+        const long long row = plane + (long long)(y0 + r) * s1;
+        lft[r] = src[row + xm];
+        rgt[r] = src[row + xp];
+        if (three) {
+            bk[r] = src[row + x + dzm];
+            fr[r] = src[row + x + dzp];
+        }
+        if (stage == 1 || stage == 2) p0[r] = phi[row + x];
+        if (stage > 0) a0[r] = acc[row + x];
+    }
+#pragma unroll
+    for (int r = 0; r < kLsRows; ++r) {
+        if (r >= nr) break;
+        const int y = y0 + r;
+        const long long q = plane + (long long)y * s1 + x;
+        const T here = col[r + 1], below = col[r], above = col[r + 2];
         const bool hm1 = y > 0 || py, hp1 = y < n1 - 1 || py;
-        const T d0 = ls_side<T>(here - left, right - here, hm0, hp0, ih0);
+        const T d0 = ls_side<T>(here - lft[r], rgt[r] - here, hm0, hp0, ih0);
         const T d1 = ls_side<T>(here - below, above - here, hm1, hp1, ih1);
         T s2sum = (T)0;
         s2sum += d0 * d0;
         s2sum += d1 * d1;
         if (three) {
-            const T back = src[q + dzm], front = src[q + dzp];
-            const T d2 = ls_side<T>(here - back, front - here, hm2, hp2, ih2);
+            const T d2 = ls_side<T>(here - bk[r], fr[r] - here, hm2, hp2, ih2);
             s2sum += d2 * d2;
         }
         const T gm = sqrt(s2sum);
         if (stage == 0) {
-            const T pn = here;
-            acc[q] = pn - h * (T)(1.0 / 6.0) * gm;
-            dst[q] = pn - h * (T)0.5 * gm;
+            acc[q] = here - h * (T)(1.0 / 6.0) * gm;
+            dst[q] = here - h * (T)0.5 * gm;
         } else if (stage == 1) {
-            acc[q] = acc[q] - h * (T)(1.0 / 3.0) * gm;
-            dst[q] = phi[q] - h * (T)0.5 * gm;
+            acc[q] = a0[r] - h * (T)(1.0 / 3.0) * gm;
+            dst[q] = p0[r] - h * (T)0.5 * gm;
         } else if (stage == 2) {
-            acc[q] = acc[q] - h * (T)(1.0 / 3.0) * gm;
-            dst[q] = phi[q] - h * gm;
+            acc[q] = a0[r] - h * (T)(1.0 / 3.0) * gm;
+            dst[q] = p0[r] - h * gm;
         } else {
-            dst[q] = acc[q] - h * (T)(1.0 / 6.0) * gm;
+            dst[q] = a0[r] - h * (T)(1.0 / 6.0) * gm;
         }
-        below = here;
-        here = above;
     }
 }
 
