@@ -66,6 +66,7 @@ def run_gpu(args, spec, kw, prec, profile=False):
     import torch
     from paper_2111_09859_amd import _lib as L, api
     s = api.Solver(0)
+    L.wd_ctx_set_segmented(s.ctx, args.seg)
     prep = s.prepare(spec, kw["scheme"], prec)
     m = api.make_method(precision=prec, **kw, **stop_rule(prec, args.fixed_iters))
     if args.tiles:
@@ -707,6 +708,8 @@ def main():
     ap.add_argument("--burn-big-steps", type=int, default=40)
     ap.add_argument("--burn-big3", type=int, default=256)
     ap.add_argument("--moving-steps", type=int, default=24)
+    ap.add_argument("--seg", type=int, default=1,
+                    help="segmented Cartesian passes: 0 off, 1 auto, 16/24/32 segment length")
     args = ap.parse_args()
     global ALPHA_F
     if args.alpha_f is not None:

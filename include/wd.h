@@ -277,6 +277,17 @@ int wd_ctx_profile(wd_ctx *ctx, int enable);
  * *n receives the number available. */
 int wd_ctx_profile_read(wd_ctx *ctx, wd_kernel_stat *out, int cap, int *n);
 
+/* enable != 0 (the default 1): uniform Cartesian grids without curvature
+ * whose lines all admit a segmentation (segments of 32, 24 or 16 points,
+ * at most 16 per line) run their directional, filter and LAD passes as
+ * segmented line passes (one wave per tile of whole lines; each lane solves
+ * one segment of a line by Thomas' algorithm and the segments are joined
+ * through a precomputed reduced system, Sec. 3.2 / Sec. 3.4 systems
+ * unchanged); enable = 16, 24 or 32 tries that segment length first;
+ * 0: the reduction-level line passes.  The results agree to rounding.
+ * Affects plans made after the call. */
+int wd_ctx_set_segmented(wd_ctx *ctx, int enable);
+
 /* ---- host-side diagnostics ------------------------------------------ */
 /* Applies, on the host and in FP64 arithmetic, the parallel-cyclic-reduction
  * multipliers the kernels use for a line system (Sec. 3.2 compact first
@@ -289,6 +300,19 @@ int wd_ctx_profile_read(wd_ctx *ctx, wd_kernel_stat *out, int cap, int *n);
 int wd_line_solve_host(int kind, int n, int periodic, int scheme,
                        double alpha_f, int fp64, const double *rhs, double *x,
                        int *nlev);
+
+/* The segmented solve of the same line systems, on the host in FP64: the
+ * line cut as the segmented passes cut it (segments of 32, 24 or 16
+ * positions, one possibly shorter), each segment solved locally and the
+ * segments joined through the reduced system.
+ *   M      : 0 (the FP32 passes' choice) or the segment length to try
+ *            first.
+ *   rhs, x : host arrays of n doubles (may alias).
+ *   *S_used: receives 100 * segments + segment length (may be NULL).
+ * Touches no GPU; WD_ERR_INVALID_ARG for bad sizes or codes,
+ * WD_ERR_UNSUPPORTED when no segmentation fits the line (or not M). */
+int wd_seg_solve_host(int kind, int n, int periodic, int scheme, double alpha_f, int M,
+                      const double *rhs, double *x, int *S_used);
 
 /* ---- serving (continuous batching) ---------------------------------- */
 /* A host thread owns a stream and a device arena of `budget_bytes`.  It

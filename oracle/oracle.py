@@ -73,6 +73,7 @@ def lib():
         L.wdo_eval.argtypes = [C.POINTER(_Grid), C.POINTER(_Method), dp, dp,
                                dp, dp, dp, dp, dp, dp, dp]
         L.wdo_lad_field.argtypes = [C.POINTER(_Grid), C.POINTER(_Method), dp, dp, dp]
+        L.wdo_gauss_line.argtypes = [C.c_int, C.c_int, dp, dp]
         L.wdo_apply_bc.argtypes = [C.POINTER(_Grid), dp]
         L.wdo_apply_bc.restype = None
         L.wdo_solve.argtypes = [C.POINTER(_Grid), C.POINTER(_Method), dp,
@@ -158,6 +159,15 @@ def filter_line(f, alpha_f, periodic=False):
     rc = lib().wdo_filter_line(f.size, int(periodic), alpha_f, _ptr(f), _ptr(out))
     if rc:
         raise ValueError("wdo_filter_line failed")
+    return out
+
+
+def gauss_line(f, periodic=False):
+    """The nine-point smoothing of the LAD diffusivity along one line."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.empty_like(f)
+    if lib().wdo_gauss_line(f.size, int(periodic), _ptr(f), _ptr(out)):
+        raise ValueError("wdo_gauss_line failed")
     return out
 
 

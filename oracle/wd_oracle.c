@@ -553,6 +553,26 @@ static void gauss_dir(const wdo_grid *g, int l, double *f, double *tmp)
     }
 }
 
+/* The smoothing of one line on its own (a test accessor of gauss_dir). */
+int wdo_gauss_line(int n, int periodic, const double *f, double *out)
+{
+    if (n < 9)
+        return -1;
+    wdo_grid g;
+    memset(&g, 0, sizeof g);
+    g.ndim = 2;
+    g.n[0] = n;
+    g.n[1] = 1;
+    g.n[2] = 1;
+    g.bc[0][0] = g.bc[0][1] = periodic ? WDO_PERIODIC : WDO_WALL;
+    g.uniform = 1;
+    double *tmp = malloc(sizeof(double) * n);
+    for (int i = 0; i < n; ++i) out[i] = f[i];
+    gauss_dir(&g, 0, out, tmp);
+    free(tmp);
+    return 0;
+}
+
 /* LAD diffusivity (second argument of Eq. Gamma_form2):
  *   C | sum_l (sum_m xi_{l,m}^2)^2 d4_l phi dx_l^3 |,  dx_l = 1/|grad xi_l|
  * (reading: dx_l from the metrics, d4 the five-point index difference).

@@ -91,6 +91,10 @@ int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
 int wdo_lad_field(const wdo_grid *g, const wdo_method *m, const double *met,
                   const double *phi, double *out);
 
+/* The nine-point smoothing of the LAD diffusivity applied to one line
+ * (ends clamped unless periodic); n >= 9. */
+int wdo_gauss_line(int n, int periodic, const double *f, double *out);
+
 /* Boundary conditions and solid mask, in place. */
 void wdo_apply_bc(const wdo_grid *g, double *phi);
 

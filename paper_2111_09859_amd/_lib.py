@@ -93,6 +93,9 @@ def lib():
         "wd_tune_set": ([vp, gd, C.c_int, ip], C.c_int),
         "wd_ctx_profile": ([vp, C.c_int], C.c_int),
         "wd_ctx_profile_read": ([vp, C.POINTER(wd_kernel_stat), C.c_int, ip], C.c_int),
+        "wd_ctx_set_segmented": ([vp, C.c_int], C.c_int),
+        "wd_seg_solve_host": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int,
+                               dp, dp, ip], C.c_int),
         "wd_line_solve_host": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, dp,
                                 dp, ip], C.c_int),
         "wd_server_create": ([vp, C.c_size_t, C.c_int, C.POINTER(vp)], C.c_int),
@@ -276,6 +279,27 @@ def wd_line_solve_host(kind, rhs, periodic, scheme="C6", alpha_f=0.495, fp64=Tru
                                     x.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nlev)),
            "wd_line_solve_host", ok=(WD_OK,))
     return x, nlev.value
+
+
+def wd_seg_solve_host(kind, rhs, periodic, scheme="C6", alpha_f=0.495, M=0):
+    """Host FP64 run of the segmented line solve; returns (x, (segments,
+    segment length))."""
+    import numpy as np
+    r = np.ascontiguousarray(rhs, dtype=np.float64)
+    x = np.empty_like(r)
+    su = C.c_int(0)
+    _check(lib().wd_seg_solve_host(kind, r.size, int(periodic), L_SCHEME(scheme), alpha_f,
+                                   M, r.ctypes.data_as(C.POINTER(C.c_double)),
+                                   x.ctypes.data_as(C.POINTER(C.c_double)), C.byref(su)),
+           "wd_seg_solve_host", ok=(WD_OK,))
+    return x, (su.value // 100, su.value % 100)
+
+
+def wd_ctx_set_segmented(ctx, enable) -> None:
+    """enable: False (reduction-level passes), True (segmented), or 16/24/32
+    (segmented, that segment length tried first)."""
+    v = int(enable) if not isinstance(enable, bool) else int(enable)
+    _check(lib().wd_ctx_set_segmented(ctx, v), "wd_ctx_set_segmented", ok=(WD_OK,))
 
 
 def L_SCHEME(s):

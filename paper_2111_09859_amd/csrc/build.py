@@ -29,6 +29,7 @@ FLAGS = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
 def _units():
     """(source, extra flags, object name) of every translation unit."""
     out = [("wd_kernels.hip", [], "wd_kernels.o"),
+           ("wd_seg.hip", [], "wd_seg.o"),
            ("wd_host.cpp", [], "wd_host.o"),
            ("wd_server.cpp", [], "wd_server.o")]
     for t, tag in (("float", "f32"), ("double", "f64")):

@@ -33,6 +33,37 @@ struct LineOpDev {
     double usc;               // uniform final scale
 };
 
+// A data-independent tridiagonal line system split into S segments (the
+// segmentation of SegGeo: M rows each, one of them possibly shorter).
+// Each segment is solved on its own by Thomas' algorithm with host-factored
+// rows, then corrected by its two coupling vectors (spikes) times the true
+// values at the neighbouring segments' ends, which the host-inverted
+// reduced system gives as linear combinations of all segments' local end
+// values.  tab (T): ell[n], ib[n], cb[n] (local LU: y_j = r_j - ell_j
+// y_{j-1}, x_j = ib_j y_j - cb_j x_{j+1}), vv[n], ww[n] (spikes on the
+// previous segment's last and the next segment's first value), then per
+// segment red[s][4][S]: the rows giving the previous segment's last value
+// and the next segment's first value from (local first values, local last
+// values).
+struct SegOpDev {
+    int n, S;
+    int periodic;
+    int solve;                // 0: explicit scheme (no system)
+    const void *tab;
+};
+
+// Segmentation and LDS geometry of the segmented passes along one
+// direction: a tile holds W whole lines, lane w S + s owns segment s of
+// line w.  Segments hold M positions except segment ks, which starts at bk
+// and holds r (ks = S, bk = n when all are full); a short segment is never
+// the last one, and is the first one only when it holds >= 5 positions.
+// The line buffer keeps line w at w P, position j at j + (segment of j).
+struct SegGeo {
+    int S, W, M;
+    int ks, bk, r;
+    int P, xsize;
+};
+
 enum GridMode { MODE_CART = 0, MODE_GENERAL = 1 };
 enum { XBC_NONE = 0, XBC_NEUMANN = 1, XBC_OUTFLOW = 2 };
 
@@ -93,6 +124,12 @@ struct GridDev {
     GridState *state;         // in the grid's own region
     GridState *mirror;        // copy in the batch's contiguous state array
 
+    int seg;                  // 1: the segmented passes serve this grid
+    int seg_split;            // 1: its last direction carries the sums on and
+                              // a pointwise pass finishes the stage
+    SegGeo sgeo[3];
+    SegOpDev sdop[3];         // segmented first-derivative operator
+    SegOpDev sfop[3];         // segmented filter-correction operator
     LineOpDev dop[3];         // first-derivative operator per direction
     LineOpDev fop[3];         // filter-correction operator per direction
     int tw[3];                // tile width (lines per tile) per direction

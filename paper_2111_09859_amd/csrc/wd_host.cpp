@@ -221,6 +221,250 @@ const LineOpDev *ctx_lineop(wd_ctx *ctx, int kind, int n, int periodic, int sche
 }
 
 // ---------------------------------------------------------------------
+// Segmented line systems.  The rows of a line (the same a, b, c as above)
+// are split into S segments of m = ceil(n / S) rows; every segment is
+// factored on its own (no coupling to its neighbours), and its two
+// coupling columns (the previous segment's last unknown through a_{b_s},
+// the next segment's first through c_{e_s - 1}) are solved against the
+// segment's block once: the spikes vv, ww.  The true end values of all
+// segments then solve a 2S x 2S reduced system whose right-hand side is
+// the segments' local end values; its inverse, computed here in FP64,
+// gives each segment the two neighbouring values it needs.
+
+// Segmentation of a line of n points (SegGeo): segments of M = 32, 24 or
+// 16 positions (FP64: 16, 24, 32, the first that fits), at most 16 of them; the one shorter segment (if M does not
+// divide n) holds >= 2 positions and sits second (>= 3 segments) or first
+// (2 segments, >= 5 positions), so the first and last segments hold the
+// line's five end rows at fixed positions; a single segment must be full.
+// Returns false when no M fits.
+bool seg_plan(int n, int fp64, SegGeo &sg, int prefer)
+{
+    std::memset(&sg, 0, sizeof sg);
+    // FP64 segments of 16 first (twice the registers per value); `prefer`
+    // (16, 24, 32) tries that length first
+    int order[4] = {32, 24, 16, 0};
+    if (fp64) {
+        order[0] = 16;
+        order[2] = 32;
+    }
+    if (prefer == 16 || prefer == 24 || prefer == 32) {
+        order[3] = order[0];
+        order[0] = prefer;
+    }
+    for (int M : order) {
+        if (M == 0) break;
+        const int S = (n + M - 1) / M;
+        const int r = n - (S - 1) * M;
+        if (S > 16) continue;
+        int ks, bk;
+        if (r == M) {
+            ks = S;
+            bk = n;
+        } else if (S == 1) {
+            continue;
+        } else if (S == 2) {
+            if (r < 5) continue;
+            ks = 0;
+            bk = 0;
+        } else {
+            if (r < 2) continue;
+            ks = 1;
+            bk = M;
+        }
+        sg.S = S;
+        sg.W = 64 / S;
+        sg.M = M;
+        sg.ks = ks;
+        sg.bk = bk;
+        sg.r = ks < S ? r : M;
+        // line pitch: >= n + S slots, = S (M + 1) mod 64, so lane w S + s
+        // starts its segment near (M + 1)(w S + s) mod 64: distinct banks
+        int P = n + S;
+        while ((P - S * (M + 1)) % 64 != 0) ++P;
+        sg.P = P;
+        sg.xsize = sg.W * P;
+        return true;
+    }
+    return false;
+}
+
+// first position and length of segment s
+static void seg_bounds(const SegGeo &sg, int s, int &b, int &len)
+{
+    if (s < sg.ks) {
+        b = s * sg.M;
+        len = sg.M;
+    } else if (s == sg.ks) {
+        b = sg.bk;
+        len = sg.r;
+    } else {
+        b = sg.bk + sg.r + (s - sg.ks - 1) * sg.M;
+        len = sg.M;
+    }
+}
+
+int build_seg_tables(int kind, int n, int periodic, int scheme, double af, const SegGeo &sg,
+                     std::vector<double> &out)
+{
+    std::vector<double> a, b, c;
+    if (kind == OP_FILTER)
+        filter_rows(n, periodic, af, a, b, c);
+    else
+        deriv_rows(n, periodic, scheme, a, b, c);
+    const int S = sg.S;
+    out.assign((size_t)5 * n + (size_t)4 * S * S, 0.0);
+    double *ell = &out[0], *ib = &out[n], *cb = &out[2 * (size_t)n];
+    double *vv = &out[3 * (size_t)n], *ww = &out[4 * (size_t)n], *red = &out[5 * (size_t)n];
+    std::vector<double> beta(n), y(n), x(n);
+    std::vector<int> sb(S), se(S);
+    for (int s = 0; s < S; ++s) {
+        int bs, len;
+        seg_bounds(sg, s, bs, len);
+        if (len < 2 || bs + len > n) return -1;
+        sb[s] = bs;
+        se[s] = bs + len;
+    }
+    if (se[S - 1] != n) return -1;
+    // local solve of segment [bs, es) for right-hand side y, result in x
+    auto local = [&](int bs, int es) {
+        for (int j = bs + 1; j < es; ++j) y[j] -= ell[j] * y[j - 1];
+        x[es - 1] = ib[es - 1] * y[es - 1];
+        for (int j = es - 2; j >= bs; --j) x[j] = ib[j] * y[j] - cb[j] * x[j + 1];
+    };
+    for (int s = 0; s < S; ++s) {
+        const int bs = sb[s], es = se[s];
+        beta[bs] = b[bs];
+        ell[bs] = 0.0;
+        for (int j = bs + 1; j < es; ++j) {
+            ell[j] = a[j] / beta[j - 1];
+            beta[j] = b[j] - ell[j] * c[j - 1];
+        }
+        for (int j = bs; j < es; ++j) {
+            if (beta[j] == 0.0) return -1;
+            ib[j] = 1.0 / beta[j];
+            cb[j] = j < es - 1 ? c[j] / beta[j] : 0.0;
+        }
+        const bool prev = s > 0 || periodic, next = s < S - 1 || periodic;
+        for (int j = bs; j < es; ++j) y[j] = 0.0;
+        y[bs] = prev ? a[bs] : 0.0;
+        local(bs, es);
+        for (int j = bs; j < es; ++j) vv[j] = x[j];
+        for (int j = bs; j < es; ++j) y[j] = 0.0;
+        y[es - 1] = next ? c[es - 1] : 0.0;
+        local(bs, es);
+        for (int j = bs; j < es; ++j) ww[j] = x[j];
+    }
+    // reduced system over u = (first_0..first_{S-1}, last_0..last_{S-1})
+    const int R = 2 * S;
+    std::vector<double> Mx((size_t)R * R, 0.0), Inv((size_t)R * R, 0.0);
+    for (int k = 0; k < R; ++k) Mx[(size_t)k * R + k] = 1.0;
+    for (int s = 0; s < S; ++s) {
+        const int bs = sb[s], es = se[s];
+        const int pv = s > 0 ? s - 1 : (periodic ? S - 1 : -1);
+        const int nx = s < S - 1 ? s + 1 : (periodic ? 0 : -1);
+        if (pv >= 0) {
+            Mx[(size_t)s * R + S + pv] += vv[bs];
+            Mx[(size_t)(S + s) * R + S + pv] += vv[es - 1];
+        }
+        if (nx >= 0) {
+            Mx[(size_t)s * R + nx] += ww[bs];
+            Mx[(size_t)(S + s) * R + nx] += ww[es - 1];
+        }
+    }
+    // Gauss-Jordan with partial pivoting
+    for (int k = 0; k < R; ++k) Inv[(size_t)k * R + k] = 1.0;
+    for (int col = 0; col < R; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < R; ++r)
+            if (std::fabs(Mx[(size_t)r * R + col]) > std::fabs(Mx[(size_t)piv * R + col])) piv = r;
+        if (Mx[(size_t)piv * R + col] == 0.0) return -1;
+        if (piv != col)
+            for (int k = 0; k < R; ++k) {
+                std::swap(Mx[(size_t)piv * R + k], Mx[(size_t)col * R + k]);
+                std::swap(Inv[(size_t)piv * R + k], Inv[(size_t)col * R + k]);
+            }
+        const double d = 1.0 / Mx[(size_t)col * R + col];
+        for (int k = 0; k < R; ++k) {
+            Mx[(size_t)col * R + k] *= d;
+            Inv[(size_t)col * R + k] *= d;
+        }
+        for (int r = 0; r < R; ++r) {
+            if (r == col) continue;
+            const double f = Mx[(size_t)r * R + col];
+            if (f == 0.0) continue;
+            for (int k = 0; k < R; ++k) {
+                Mx[(size_t)r * R + k] -= f * Mx[(size_t)col * R + k];
+                Inv[(size_t)r * R + k] -= f * Inv[(size_t)col * R + k];
+            }
+        }
+    }
+    for (int s = 0; s < S; ++s) {
+        const int pv = s > 0 ? s - 1 : (periodic ? S - 1 : -1);
+        const int nx = s < S - 1 ? s + 1 : (periodic ? 0 : -1);
+        double *rs = red + (size_t)s * 4 * S;
+        for (int k = 0; k < S; ++k) {
+            rs[k] = pv >= 0 ? Inv[(size_t)(S + pv) * R + k] : 0.0;
+            rs[S + k] = pv >= 0 ? Inv[(size_t)(S + pv) * R + S + k] : 0.0;
+            rs[2 * S + k] = nx >= 0 ? Inv[(size_t)nx * R + k] : 0.0;
+            rs[3 * S + k] = nx >= 0 ? Inv[(size_t)nx * R + S + k] : 0.0;
+        }
+    }
+    return 0;
+}
+
+const SegOpDev *ctx_segop(wd_ctx *ctx, int kind, int n, int periodic, int scheme, double af,
+                          int fp64, const SegGeo &sg)
+{
+    OpKey key{kind + 2 + 4 * (sg.M + 64 * sg.S), n, periodic, kind == OP_FILTER ? -1 : scheme,
+              fp64, kind == OP_FILTER ? af : 0.0};
+    auto it = ctx->segops.find(key);
+    if (it != ctx->segops.end()) return &it->second.dev;
+    SegEntry e;
+    e.dev.n = n;
+    e.dev.S = sg.S;
+    e.dev.periodic = periodic;
+    e.dev.solve = kind == OP_FILTER || scheme == SCHEME_C4 || scheme == SCHEME_C6;
+    e.dev.tab = nullptr;
+    if (e.dev.solve) {
+        std::vector<double> t;
+        if (build_seg_tables(kind, n, periodic, scheme, af, sg, t)) {
+            fail(WD_ERR_UNSUPPORTED, "segmented line system (n=%d, S=%d) is singular", n, sg.S);
+            return nullptr;
+        }
+        const size_t es = fp64 ? 8 : 4;
+        std::vector<unsigned char> host(t.size() * es);
+        for (size_t i = 0; i < t.size(); ++i) {
+            if (fp64) reinterpret_cast<double *>(host.data())[i] = t[i];
+            else reinterpret_cast<float *>(host.data())[i] = (float)t[i];
+        }
+        void *mem = nullptr;
+        if (hipMalloc(&mem, host.size()) != hipSuccess) {
+            fail(WD_ERR_NO_MEMORY, "hipMalloc of %zu bytes for a line operator failed", host.size());
+            return nullptr;
+        }
+        if (hipMemcpy(mem, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(mem);
+            fail(WD_ERR_HIP, "upload of a line operator failed");
+            return nullptr;
+        }
+        e.mem = mem;
+        e.dev.tab = mem;
+    }
+    auto ins = ctx->segops.emplace(key, e);
+    return &ins.first->second.dev;
+}
+
+// dynamic LDS bytes of a segmented pass (kind: PASS_SCART / SFILTER / SLAD)
+size_t seg_lds_bytes(const GridDev &g, int kind, int l, int fp64)
+{
+    const SegGeo &sg = g.sgeo[l];
+    const SegOpDev &op = kind == PASS_SFILTER ? g.sfop[l] : g.sdop[l];
+    size_t el = (size_t)sg.xsize * (kind == PASS_SCART_LAST ? 2 : 1);
+    if (kind != PASS_SLAD && op.solve) el += (size_t)5 * op.n + (size_t)4 * op.S * op.S;
+    return el * (fp64 ? 8 : 4);
+}
+
+// ---------------------------------------------------------------------
 // validation
 int check_desc(const wd_grid_desc *d)
 {
@@ -337,7 +581,7 @@ long long grid_items(const wd_grid_desc &d)
     const long long chunks = (N + kChunk - 1) / kChunk;
     long long face = 0;
     for (int l = 0; l < d.ndim; ++l) face += 2 * ((N / d.n[l] + kChunk - 1) / kChunk);
-    return 5 * lines + 4 * chunks + 2 * face + 8;
+    return 5 * lines + 5 * chunks + 2 * face + 8;
 }
 
 // batch tables: grid array, state mirrors, two one-grid views, items
@@ -502,6 +746,35 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     g.hist_cap = hist_dev_cap(m);
     g.hist = static_cast<double *>(take((size_t)g.hist_cap * 16));
     g.state = static_cast<GridState *>(take(sizeof(GridState)));
+    // segmented passes: uniform Cartesian grids whose lines all have >= 16
+    // points and whose tiles fit the LDS budget
+    g.seg = 0;
+    if (ctx->use_seg && g.mode == MODE_CART) {
+        bool ok = true;
+        for (int l = 0; l < d.ndim; ++l) ok &= d.n[l] >= 16;
+        for (int l = 0; l < d.ndim && ok; ++l) {
+            if (!seg_plan(d.n[l], fp64, g.sgeo[l], ctx->use_seg)) {
+                ok = false;
+                break;
+            }
+            const SegOpDev *sd = ctx_segop(ctx, OP_DERIV, d.n[l], g.periodic[l], dscheme, 0.0, fp64,
+                                           g.sgeo[l]);
+            if (!sd) return WD_ERR_NO_MEMORY;
+            g.sdop[l] = *sd;
+            if (m.filter) {
+                const SegOpDev *sf = ctx_segop(ctx, OP_FILTER, d.n[l], g.periodic[l], dscheme,
+                                               m.alpha_f, fp64, g.sgeo[l]);
+                if (!sf) return WD_ERR_NO_MEMORY;
+                g.sfop[l] = *sf;
+            }
+            for (int kind : {PASS_SCART, PASS_SCART_LAST, PASS_SFILTER, PASS_SLAD})
+                ok &= seg_lds_bytes(g, kind, l, fp64) <= (size_t)65536;
+        }
+        g.seg = ok ? 1 : 0;
+        // without extrapolated faces the last direction carries the sums
+        // on and a pointwise pass finishes the stage
+        g.seg_split = g.seg && !has_x;
+    }
     for (int l = 0; l < d.ndim; ++l) {
         const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, d.n[l], g.periodic[l], dscheme, 0.0, fp64);
         if (!dop) return WD_ERR_NO_MEMORY;
@@ -511,7 +784,7 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
             if (!fop) return WD_ERR_NO_MEMORY;
             g.fop[l] = *fop;
         }
-        g.tw[l] = pick_tile(ctx, d, l, fp64);
+        g.tw[l] = g.seg ? g.sgeo[l].W : pick_tile(ctx, d, l, fp64);
         if (l == 0)
             g.ntiles[l] = (int)((N / d.n[0] + g.tw[0] - 1) / g.tw[0]);
         else
@@ -632,7 +905,44 @@ void build_items(Plan &P)
         }
         return li;
     };
-    auto cart = [](const GridDev &g) { return g.mode == MODE_CART; };
+    auto cart = [](const GridDev &g) { return g.mode == MODE_CART && !g.seg; };
+    // segmented pass: one list of the tiles of every segmented grid
+    // segmented pass: one list per segment length M (16, 24, 32) present
+    // among the segmented grids (the list's np field holds M)
+    auto seg_list = [&](Slot &Sl, int kind, int l, int arg, auto use) {
+        const int Ms[3] = {16, 24, 32};
+        for (int c = 0; c < 4; ++c) Sl.list[c] = -1;
+        for (int c = 0; c < 3; ++c) {
+            int li = -1;
+            for (int i = 0; i < n; ++i) {
+                const GridDev &g = P.grids[i];
+                if (!g.seg || l >= g.ndim || !use(g) || g.sgeo[l].M != Ms[c]) continue;
+                if (li < 0) li = add_list(kind, l, arg, Ms[c]);
+                for (int t = 0; t < g.ntiles[l]; ++t) P.items.push_back(Item{i, t});
+                P.lists[li].count += g.ntiles[l];
+            }
+            Sl.list[c] = li;
+        }
+    };
+    for (int l = 0; l < 3; ++l)
+        seg_list(P.scart[l], PASS_SCART, l, 0, [l](const GridDev &g) {
+            return l < g.ndim - 1 || g.seg_split;
+        });
+    for (int l = 0; l < 3; ++l)
+        seg_list(P.scartl[l], PASS_SCART_LAST, l, 0, [l](const GridDev &g) {
+            return l == g.ndim - 1 && !g.seg_split;
+        });
+    P.cfin = point_list(PASS_CFIN, 0, 0, [&](int i) {
+        return P.grids[i].seg_split ? P.grids[i].nchunks : 0;
+    });
+    for (int l = 0; l < 3; ++l)
+        seg_list(P.slad0[l], PASS_SLAD, l, 0, [](const GridDev &g) { return g.lad != 0; });
+    for (int l = 0; l < 3; ++l)
+        seg_list(P.slad1[l], PASS_SLAD, l, 1, [l](const GridDev &g) {
+            return g.lad != 0 && l < g.ndim - 1;
+        });
+    for (int l = 0; l < 3; ++l)
+        seg_list(P.sfilt[l], PASS_SFILTER, l, 0, [](const GridDev &g) { return g.filter != 0; });
     auto gen_lap = [](const GridDev &g) { return g.mode == MODE_GENERAL && g.need_lap; };
     auto gen_eik = [](const GridDev &g) { return g.mode == MODE_GENERAL && !g.need_lap; };
     // first-derivative fields: every general grid but the upwind Eikonal
@@ -664,14 +974,16 @@ void build_items(Plan &P)
     // grids form the field inside their stage-0 passes.
     for (int l = 0; l < 3; ++l)
         line_slot(P.lad0[l], PASS_LAD, l, 0, [](const GridDev &g) {
-            return g.lad != 0 && g.mode == MODE_CART;
+            return g.lad != 0 && g.mode == MODE_CART && !g.seg;
         });
     for (int l = 0; l < 3; ++l)
         line_slot(P.lad1[l], PASS_LAD, l, 1, [l](const GridDev &g) {
-            return g.lad != 0 && g.mode == MODE_CART && l < g.ndim - 1;
+            return g.lad != 0 && g.mode == MODE_CART && !g.seg && l < g.ndim - 1;
         });
     for (int l = 0; l < 3; ++l)
-        line_slot(P.filt[l], PASS_FILTER, l, 0, [](const GridDev &g) { return g.filter != 0; });
+        line_slot(P.filt[l], PASS_FILTER, l, 0, [](const GridDev &g) {
+            return g.filter != 0 && !g.seg;
+        });
     P.resid = point_list(PASS_RESID, 0, 0, [&](int i) {
         return P.grids[i].fused_resid ? 0 : P.grids[i].nchunks;
     });
@@ -709,6 +1021,11 @@ static const char *kind_name(int kind)
     case PASS_FACE: return "k_face";
     case PASS_INIT: return "k_init";
     case PASS_LAD: return "k_lad";
+    case PASS_SCART: return "k_seg_cart";
+    case PASS_SCART_LAST: return "k_seg_cart_fin";
+    case PASS_CFIN: return "k_cart_finish";
+    case PASS_SFILTER: return "k_seg_filter";
+    case PASS_SLAD: return "k_seg_lad";
     default: return "k_finalize";
     }
 }
@@ -733,15 +1050,20 @@ static double point_accesses(const GridDev &g, int kind, int l, int stage)
         if (g.lad) r += 1;                         // LAD field
         return r + w;
     };
+    if (kind == PASS_SCART || kind == PASS_SCART_LAST) kind = PASS_CART;
+    if (kind == PASS_SFILTER) kind = PASS_FILTER;
+    if (kind == PASS_SLAD) kind = PASS_LAD;
     switch (kind) {
     case PASS_CART: {
         const int np = 1 + g.need_lap;             // partial sums
         double a = 1;                              // source line
         if (l > 0) a += np;
-        if (!last) a += np;
+        if (!last || g.seg_split) a += np;
         else a += finish(1) - (g.lad ? 0 : 0);
         return a;
     }
+    case PASS_CFIN:
+        return (1 + g.need_lap) + finish(0);       // the two sums + the finish's fields
     case PASS_D1:
         // phi in, F_l out; at stage 0 of an LAD grid the sensor part:
         // metrics in, sensor sum in (after the first direction) and out
@@ -867,9 +1189,34 @@ void issue_list(wd_ctx *ctx, const Plan &P, int li, int stage, hipStream_t s)
     const int arg = (L.kind == PASS_FACE || L.kind == PASS_INIT) ? L.arg : stage;
     PendingLaunch pl;
     if (ctx->profile) prof_begin(ctx, pl, kind_name(L.kind), launch_bytes(P, L, stage), s);
-    launch_pass(L.kind, P.fp64, L.np, P.d_grids, P.d_items + L.first, L.count, L.l, arg,
-                nwg_for(ctx, P.fp64, L.kind, L.np, L.count), s);
+    if (L.kind == PASS_SCART || L.kind == PASS_SCART_LAST || L.kind == PASS_SFILTER ||
+        L.kind == PASS_SLAD) {
+        size_t lds = 0;
+        int last = -1;
+        for (int i = 0; i < L.count; ++i) {
+            const int gi = P.items[L.first + i].grid;
+            if (gi == last) continue;
+            last = gi;
+            lds = std::max(lds, seg_lds_bytes(P.grids[gi], L.kind, L.l, P.fp64));
+        }
+        // workgroups the chip holds at once: registers and LDS (160 KiB per
+        // compute unit) permitting
+        int per = seg_blocks_per_cu_regs(L.kind, P.fp64, L.np);
+        per = std::max(1, std::min(per, (int)(163840 / std::max<size_t>(lds, 1))));
+        int nwg = std::min(L.count, std::max(8, (ctx->cus * per) & ~7));
+        launch_seg(L.kind, P.fp64, L.np, P.d_grids, P.d_items + L.first, L.count, L.l, arg, nwg,
+                   lds, s);
+    } else {
+        launch_pass(L.kind, P.fp64, L.np, P.d_grids, P.d_items + L.first, L.count, L.l, arg,
+                    nwg_for(ctx, P.fp64, L.kind, L.np, L.count), s);
+    }
     if (ctx->profile) prof_end(ctx, pl, s);
+}
+
+static void issue_seg(wd_ctx *ctx, const Plan &P, const Slot &Sl, int stage, hipStream_t s)
+{
+    for (int c = 0; c < 4; ++c)
+        if (Sl.list[c] >= 0) issue_list(ctx, P, Sl.list[c], stage, s);
 }
 
 void issue_slot(wd_ctx *ctx, const Plan &P, const Slot &S, int stage, hipStream_t s)
@@ -896,9 +1243,16 @@ void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s)
     // LAD diffusivity from phi^n: sensor per direction (the last one also
     // smooths along itself), then smoothing along the other directions
     for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.lad0[l], 0, s);
+    for (int l = 0; l < P.maxdim; ++l) issue_seg(ctx, P, P.slad0[l], 0, s);
     for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.lad1[l], 1, s);
+    for (int l = 0; l < P.maxdim; ++l) issue_seg(ctx, P, P.slad1[l], 1, s);
     for (int st = 0; st < P.stages; ++st) {
         for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.cart[l], st, s);
+        for (int l = 0; l < P.maxdim; ++l) {
+            issue_seg(ctx, P, P.scart[l], st, s);
+            issue_seg(ctx, P, P.scartl[l], st, s);
+        }
+        issue_list(ctx, P, P.cfin, st, s);
         for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, st == 0 ? P.d1[l] : P.d1n[l], st, s);
         issue_slot(ctx, P, P.d12, st, s);
         for (int l = 1; l < P.maxdim; ++l) issue_slot(ctx, P, P.d2[l], st, s);
@@ -907,6 +1261,7 @@ void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s)
         issue_faces(ctx, P, 1, s);
     }
     for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.filt[l], 0, s);
+    for (int l = 0; l < P.maxdim; ++l) issue_seg(ctx, P, P.sfilt[l], 0, s);
     issue_faces(ctx, P, 1, s);
     issue_list(ctx, P, P.resid, 0, s);
     PendingLaunch pl;
@@ -1220,6 +1575,9 @@ int wd_ctx_create(int device, wd_ctx **out)
         for (int np = 1; np <= 8; np *= 2)
             for (int kind : {PASS_CART, PASS_D1, PASS_D2, PASS_D12, PASS_FILTER, PASS_LAD})
                 (void)line_blocks_per_cu(kind, fp64, np);
+    for (int fp64 = 0; fp64 < 2; ++fp64)
+        for (int kind : {PASS_SCART, PASS_SCART_LAST, PASS_SFILTER, PASS_SLAD})
+            for (int M : {16, 24, 32}) (void)seg_blocks_per_cu_regs(kind, fp64, M);
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
@@ -1244,6 +1602,8 @@ int wd_ctx_destroy(wd_ctx *ctx)
     prof_collect(ctx);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (auto &kv : ctx->ops) (void)hipFree(kv.second.mem);
+    for (auto &kv : ctx->segops)
+        if (kv.second.mem) (void)hipFree(kv.second.mem);
     if (ctx->pinned_states) (void)hipHostFree(ctx->pinned_states);
     (void)hipEventDestroy(ctx->ev_in);
     (void)hipEventDestroy(ctx->ev_out);
@@ -1559,6 +1919,68 @@ int wd_line_solve_host(int kind, int n, int periodic, int scheme, double alpha_f
     }
     for (int i = 0; i < n; ++i) x[i] = d[i];
     if (nlev) *nlev = lev;
+    return WD_OK;
+}
+
+int wd_seg_solve_host(int kind, int n, int periodic, int scheme, double alpha_f, int M,
+                      const double *rhs, double *x, int *S_used)
+{
+    if (!rhs || !x || n < 8 || n > kMaxLine || (kind != OP_DERIV && kind != OP_FILTER) ||
+        scheme < WD_E2 || scheme > WD_C6)
+        return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    SegGeo sg;
+    if (!seg_plan(n, 0, sg, M) || (M != 0 && M != sg.M))
+        return fail(WD_ERR_UNSUPPORTED, "no segmentation of a %d-point line", n);
+    if (S_used) *S_used = sg.S * 100 + sg.M;
+    const bool solve = kind == OP_FILTER || scheme == WD_C4 || scheme == WD_C6;
+    std::vector<double> r(rhs, rhs + n);
+    if (!solve) {
+        for (int i = 0; i < n; ++i) x[i] = r[i];
+        return WD_OK;
+    }
+    std::vector<double> t;
+    if (build_seg_tables(kind, n, periodic, scheme, alpha_f, sg, t))
+        return fail(WD_ERR_UNSUPPORTED, "segmented line system (n=%d) is singular", n);
+    const int S = sg.S;
+    const double *ell = &t[0], *ib = &t[n], *cb = &t[2 * (size_t)n];
+    const double *vv = &t[3 * (size_t)n], *ww = &t[4 * (size_t)n], *red = &t[5 * (size_t)n];
+    std::vector<double> xl(n), f0(S), l0(S);
+    for (int s = 0; s < S; ++s) {
+        int bs, len;
+        seg_bounds(sg, s, bs, len);
+        const int es = bs + len;
+        double y = 0.0;
+        for (int j = bs; j < es; ++j) {
+            y = r[j] - ell[j] * y;
+            xl[j] = y;
+        }
+        double v = 0.0;
+        for (int j = es - 1; j >= bs; --j) {
+            v = ib[j] * xl[j] - cb[j] * v;
+            xl[j] = v;
+        }
+        f0[s] = xl[bs];
+        l0[s] = xl[es - 1];
+    }
+    for (int s = 0; s < S; ++s) {
+        int bs, len;
+        seg_bounds(sg, s, bs, len);
+        const double *rs = red + (size_t)s * 4 * S;
+        double lp = 0.0, fn = 0.0;
+        for (int k = 0; k < S; ++k) {
+            lp += rs[k] * f0[k] + rs[S + k] * l0[k];
+            fn += rs[2 * S + k] * f0[k] + rs[3 * S + k] * l0[k];
+        }
+        for (int j = bs; j < bs + len; ++j) x[j] = xl[j] - vv[j] * lp - ww[j] * fn;
+    }
+    return WD_OK;
+}
+
+int wd_ctx_set_segmented(wd_ctx *ctx, int enable)
+{
+    if (!ctx) return fail(WD_ERR_INVALID_ARG, "null context");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->use_seg = enable;
     return WD_OK;
 }
 

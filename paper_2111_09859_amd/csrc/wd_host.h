@@ -31,6 +31,11 @@ struct OpEntry {
     void *mem = nullptr;
 };
 
+struct SegEntry {
+    SegOpDev dev;
+    void *mem = nullptr;
+};
+
 struct TuneKey {
     int ndim, n0, n1, n2, dir, fp64;
     bool operator<(const TuneKey &o) const
@@ -89,8 +94,9 @@ struct Plan {
     std::vector<Item> items;
     std::vector<ItemList> lists;
     Slot cart[3], d1[3], d1n[3], d12, d2[3], filt[3], lad0[3], lad1[3];   // d1n: stages > 0
+    Slot scart[3], scartl[3], sfilt[3], slad0[3], slad1[3];  // segmented passes, one list per M
     int face[6], face_init[6];
-    int fin = 0, resid = 0, init = 0, uwadv = 0;
+    int fin = 0, resid = 0, init = 0, uwadv = 0, cfin = 0;
     GridDev *d_grids = nullptr;
     GridDev *d_aux = nullptr, *d_aux2 = nullptr;
     GridState *d_states = nullptr;
@@ -113,6 +119,12 @@ int pcr_reduce(int n, int periodic, std::vector<double> a, std::vector<double> b
 int build_line_system(int kind, int n, int periodic, int scheme, double af, int fp64,
                       std::vector<int> &smod, std::vector<double> &left,
                       std::vector<double> &right, std::vector<double> &scale);
+bool seg_plan(int n, int fp64, SegGeo &sg, int prefer = 0);
+int build_seg_tables(int kind, int n, int periodic, int scheme, double af, const SegGeo &sg,
+                     std::vector<double> &out);
+const SegOpDev *ctx_segop(wd_ctx *ctx, int kind, int n, int periodic, int scheme, double af,
+                          int fp64, const SegGeo &sg);
+size_t seg_lds_bytes(const GridDev &g, int kind, int l, int fp64);
 const LineOpDev *ctx_lineop(wd_ctx *ctx, int kind, int n, int periodic, int scheme,
                             double af, int fp64);
 size_t grid_region_bytes(const wd_grid_desc &d, const wd_method &m);
@@ -149,6 +161,9 @@ struct wd_ctx {
     int use_graphs = 1;
     int graph_iters = 32;
     std::map<wd::OpKey, wd::OpEntry> ops;
+    std::map<wd::OpKey, wd::SegEntry> segops;
+    int use_seg = 1;                     // segmented passes on Cartesian grids
+                                         // (16, 24, 32: segment length tried first)
     std::map<wd::TuneKey, int> tune;
     std::vector<wd::CachedGraph> graphs;
     int profile = 0;

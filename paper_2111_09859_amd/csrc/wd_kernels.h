@@ -18,7 +18,19 @@ enum PassKind {
                       // 1 smoothing)
     PASS_D12 = 9,     // pass 2 along direction 0 that also forms F_0
     PASS_UWADV = 10,  // pointwise upwind advective term (Eikonal grids)
+    PASS_SCART = 11,  // segmented Cartesian pass (one wave per tile)
+    PASS_SFILTER = 12,
+    PASS_SLAD = 13,
+    PASS_SCART_LAST = 14,   // segmented Cartesian pass that finishes the stage
+    PASS_CFIN = 15,         // pointwise stage finish of a segmented Cartesian grid
 };
+
+// Segmented passes (segment length M = 16, 24 or 32): workgroups of one
+// wave, `lds` bytes of dynamic LDS.
+void launch_seg(int kind, int fp64, int M, const GridDev *grids, const Item *items, int nitems,
+                int l, int stage, int nwg, size_t lds, hipStream_t s);
+// workgroups of a segmented kernel one compute unit holds by its registers
+int seg_blocks_per_cu_regs(int kind, int fp64, int M);
 
 // One launch of a pass over `nitems` work items with at most `nwg`
 // workgroups (a persistent loop covers the rest).  Line passes run the

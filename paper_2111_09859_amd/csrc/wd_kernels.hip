@@ -58,6 +58,61 @@ k_final(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     }
 }
 
+// Pointwise stage finish (Sec. 3.3) of a uniform Cartesian grid whose
+// directional passes carried the whole |grad phi|^2 and Laplacian on
+// (segmented passes, no extrapolated faces): every operand a plain field,
+// the loads of a thread's points issued before any use.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_cart_finish(const GridDev *__restrict__ grids, const Item *__restrict__ items,
+              int nitems, int stage)
+{
+    constexpr int K = kChunk / kThreads;
+    int step, end;
+    for (int it = item_begin(nitems, step, end); it < end; it += step) {
+        const Item item = items[it];
+        const GridDev &g = grids[item.grid];
+        if (gmem(g.state)->done) continue;
+        T S1 = (T)0, S2 = (T)0;
+        for (int d = 0; d < g.ndim; ++d) {
+            S1 += (T)g.invh[d];
+            S2 += (T)g.invh[d] * (T)g.invh[d];
+        }
+        gptr<const T> src = gcast<const T>(stage == 0 ? g.phi : g.ps);
+        gptr<const T> P0 = gcast<const T>(g.P[0]);
+        gptr<const T> P1 = gcast<const T>(g.P[1]);
+        gptr<const T> P2 = gcast<const T>(g.P[2]);
+        gptr<const unsigned char> mk = gmem(g.mask);
+        const long long q0 = (long long)item.tile * kChunk;
+        int qv[K];
+        T ph[K], g2[K], lap[K], lad[K];
+        FinIn<T> fin[K];
+        unsigned char solid[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const long long qq = q0 + threadIdx.x + k * kThreads;
+            qv[k] = qq < g.N ? (int)qq : -1;
+            if (qv[k] < 0) continue;
+            const int q = qv[k];
+            ph[k] = src[q];
+            g2[k] = P0[q];
+            lap[k] = g.need_lap ? P1[q] : (T)0;
+            lad[k] = g.lad ? P2[q] : (T)0;
+            fin[k] = fin_load<T>(g, stage, q, ph[k]);
+            solid[k] = g.mask ? mk[q] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (qv[k] < 0) continue;
+            int idx[3];
+            index_of(g, qv[k], idx);
+            const bool zero = solid[k] || wall_point(g, idx);
+            gcast<T>(g.ps)[qv[k]] = finish_point<T>(g, stage, qv[k], zero, ph[k], g2[k], g2[k],
+                                                    lap[k], (T)0, lad[k], S1, S2, fin[k]);
+        }
+    }
+}
+
 // Advective term of the upwind baseline for grids whose stage finish is
 // pointwise (Eikonal): P[1] <- U.grad(phi) of Eqs. UW1-UW5, uw2 <- |U|^2,
 // from the stage value, before the finish overwrites it.
@@ -809,6 +864,7 @@ static void point_launch(int kind, const GridDev *g, const Item *it, int nitems,
     dim3 grid(nwg), block(kThreads);
     switch (kind) {
     case PASS_FINAL: hipLaunchKernelGGL(k_final<T>, grid, block, 0, s, g, it, nitems, stage); break;
+    case PASS_CFIN: hipLaunchKernelGGL(k_cart_finish<T>, grid, block, 0, s, g, it, nitems, stage); break;
     case PASS_UWADV: hipLaunchKernelGGL(k_uwadv<T>, grid, block, 0, s, g, it, nitems, stage); break;
     case PASS_RESID: hipLaunchKernelGGL(k_resid<T>, grid, block, 0, s, g, it, nitems); break;
     case PASS_FACE: hipLaunchKernelGGL(k_face<T>, grid, block, 0, s, g, it, nitems, l, stage); break;
@@ -824,6 +880,7 @@ void launch_pass(int kind, int fp64, int np, const GridDev *g, const Item *it, i
     if (nwg > nitems) nwg = nitems;
     switch (kind) {
     case PASS_FINAL:
+    case PASS_CFIN:
     case PASS_UWADV:
     case PASS_RESID:
     case PASS_FACE:

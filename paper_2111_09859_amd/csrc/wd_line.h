@@ -630,7 +630,7 @@ __device__ inline FinIn<T> fin_load(const GridDev &g, int stage, int q, T phis)
 // stage value (the caller stores it).  g2 = |U|^2, adv = U.grad(phi)
 // (= g2 for the central schemes; the upwind product for the baseline).
 template <typename T>
-__device__ T finish_point(const GridDev &g, int stage, int q, bool zero, T phis,
+__device__ __forceinline__ T finish_point(const GridDev &g, int stage, int q, bool zero, T phis,
                           T g2, T adv, T lap, T kap, T lads, T S1, T S2, const FinIn<T> &in)
 {
     const T gm = sqrt(g2);

@@ -1,10 +1,13 @@
-"""GPU parity across the line-pass tile variants.
+"""GPU parity across the tile variants of the reduction-level line passes.
 
 The same grid is solved with tile widths that put 1, 2, 4 and 8 points on
 each thread (every compiled variant of the line passes, in both
 precisions, with ragged last tiles), each result is compared element-wise
 with the FP64 oracle after the same number of pseudo iterations, and the
-variants are compared with each other.
+variants are compared with each other.  The segmented passes, which
+uniform Cartesian grids take by default, are switched off here so these
+passes are the ones tested on every grid (test_gpu_seg.py covers the
+segmented ones).
 """
 import numpy as np
 import pytest
@@ -68,8 +71,9 @@ def fresh_solver():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
-    from paper_2111_09859_amd import api
+    from paper_2111_09859_amd import _lib as L, api
     s = api.Solver(0)
+    L.wd_ctx_set_segmented(s.ctx, False)
     yield s
     s.close()
 

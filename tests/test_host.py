@@ -105,3 +105,56 @@ def test_tile_quotient_by_reciprocal_is_exact():
         rb = np.float32(1.0) / np.float32(b)
         q = ((a + np.float32(0.5)) * rb).astype(np.int64)
         assert np.array_equal(q, ai // b), b
+
+
+def seg_plan(n):
+    """(segments, segment length) the segmented passes use for a line of n
+    points (None when no segmentation fits): segments of 32, 24 or 16,
+    at most 16, the one shorter segment holding >= 2 positions (>= 5 when
+    it is the first of two), a single segment full."""
+    for M in (32, 24, 16):
+        S = -(-n // M)
+        r = n - (S - 1) * M
+        if S > 16:
+            continue
+        if r == M or (S == 2 and r >= 5) or (S >= 3 and r >= 2):
+            return S, M
+    return None
+
+
+@pytest.mark.parametrize("n", [16, 32, 33, 40, 48, 65, 96, 100, 129, 256, 257, 500])
+@pytest.mark.parametrize("periodic", [0, 1])
+def test_segmented_solve_matches_dense(L, n, periodic):
+    """The segmented line solve (segments factored on their own, joined by
+    the host-inverted reduced system) reproduces the dense solution of the
+    compact-derivative and filter systems, with the segmentation the
+    kernels use."""
+    plan = seg_plan(n)
+    rng = np.random.default_rng(7 * n + periodic)
+    r = rng.standard_normal(n)
+    for scheme in ("C4", "C6"):
+        want = np.linalg.solve(dense_deriv(n, periodic, scheme), r)
+        x, su = L.wd_seg_solve_host(0, r, periodic, scheme, 0.48)
+        assert su == plan
+        assert np.abs(x - want).max() < 1e-13 * max(1, np.abs(want).max()), (scheme, su)
+    for a in (0.48, 0.495):
+        rr = r.copy()
+        if not periodic:
+            rr[0] = rr[-1] = 0.0
+        want = np.linalg.solve(dense_filter(n, periodic, a), rr)
+        x, su = L.wd_seg_solve_host(1, rr, periodic, "C6", a)
+        assert np.abs(x - want).max() < 1e-12 * max(1, np.abs(want).max()), (a, su)
+
+
+def test_segmentation_choices(L):
+    """Lines the segmented passes take, and lines they leave to the
+    reduction-level passes (no segmentation fits)."""
+    for n, want in ((256, (8, 32)), (129, (6, 24)), (65, (3, 24)), (16, (1, 16)), (100, (4, 32)),
+                    (40, (2, 32)), (512, (16, 32)), (96, (3, 32))):
+        assert seg_plan(n) == want
+        _, su = L.wd_seg_solve_host(0, np.ones(n), 0, "C6", 0.48)
+        assert su == want, (n, su)
+    for n in (17, 20, 600, 4096):
+        assert seg_plan(n) is None
+        with pytest.raises(L.WDError):
+            L.wd_seg_solve_host(0, np.ones(n), 0, "C6", 0.48)

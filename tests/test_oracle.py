@@ -476,3 +476,206 @@ def test_signed_distance_combination(oracle):
     ds = np.array([[9.0, 2.0], [3.0, 9.0]])
     dg = np.array([[4.0, 9.0], [9.0, 5.0]])
     assert np.array_equal(oracle.signed_distance(solid, ds, dg), np.array([[-4.0, 2.0], [3.0, -5.0]]))
+
+
+# ---------------------------------------------------------------------------
+# Pins of the LAD smoothing weights, the local time step, nu and the 3x3
+# metric inverse.
+
+def _gauss_weights_from_moments():
+    """The symmetric nine-point smoothing stencil (b0, b1..b4 at offsets 0,
+    +-1..+-4) fixed by five conditions: unit sum; second, fourth and sixth
+    moments those of a Gaussian of variance 4/3 (4/3, 16/3, 320/9); and no
+    response to the odd-even mode (omega = pi)."""
+    A = np.zeros((5, 5))
+    rhs = np.array([1.0, 4 / 3, 16 / 3, 320 / 9, 0.0])
+    A[0] = [1, 2, 2, 2, 2]
+    for r, p in enumerate((2, 4, 6), start=1):
+        A[r] = [0] + [2 * k ** p for k in range(1, 5)]
+    A[4] = [1] + [2 * (-1) ** k for k in range(1, 5)]
+    return np.linalg.solve(A, rhs)
+
+
+def test_lad_smoothing_weights_from_moments(oracle):
+    """The oracle's smoothing of the LAD diffusivity (reading of Kawai &
+    Lele's filter, Eq. Gamma_form2) returns, for a unit impulse on a
+    periodic line, the weights the moment conditions fix; a swapped or
+    mistyped weight that keeps the sum breaks a moment."""
+    b = _gauss_weights_from_moments()
+    n = 32
+    e = np.zeros(n)
+    e[10] = 1.0
+    out = oracle.gauss_line(e, periodic=True)
+    want = np.zeros(n)
+    for k in range(-4, 5):
+        want[10 + k] = b[abs(k)]
+    assert np.abs(out - want).max() < 1e-15
+
+
+@pytest.mark.parametrize("mode", [1, 3, 7, 16])
+def test_lad_smoothing_transfer_function(oracle, mode):
+    """On a periodic line a cosine mode comes back scaled by the stencil's
+    transfer function b0 + 2 sum_k b_k cos(k w); the pi mode vanishes."""
+    b = _gauss_weights_from_moments()
+    n = 32
+    w = 2 * np.pi * mode / n
+    j = np.arange(n)
+    T = b[0] + 2 * sum(b[k] * np.cos(k * w) for k in range(1, 5))
+    out = oracle.gauss_line(np.cos(w * j + 0.3), periodic=True)
+    assert np.abs(out - T * np.cos(w * j + 0.3)).max() < 1e-14
+    if mode == 16:
+        assert np.abs(out).max() < 1e-14
+
+
+def test_lad_smoothing_clamped_ends(oracle):
+    """Non-periodic lines: constants stay constant, the interior keeps
+    linear functions (symmetric weights), and the ends see the end value
+    repeated beyond the line (a ramp's first point moves up by
+    sum_k k b_k over the missing side)."""
+    b = _gauss_weights_from_moments()
+    n = 20
+    assert np.abs(oracle.gauss_line(np.full(n, 2.5)) - 2.5).max() < 1e-15
+    ramp = np.arange(n, dtype=float)
+    out = oracle.gauss_line(ramp)
+    assert np.abs(out[4:-4] - ramp[4:-4]).max() < 1e-13
+    assert abs(out[0] - sum(k * b[k] for k in range(1, 5))) < 1e-14
+
+
+def test_lad_field_is_smoothed_sensor(oracle):
+    """LAD diffusivity (Eq. Gamma_form2 with the smoothing reading) on a
+    channel (x periodic, walls in y): phi = s j^4/24 + A cos(w i) has index
+    fourth differences s along y (copied inward at the walls) and
+    16 A sin^4(w/2) cos(w i) along x, so the sensor
+    |grad eta| s + |grad xi| 16 A sin^4(w/2) cos(w i) stays positive, the
+    smoothing scales the cosine by the transfer function and leaves the
+    y-constant part alone."""
+    b = _gauss_weights_from_moments()
+    nx, ny = 32, 17
+    spec = G.channel(nx, ny)
+    dx, dy = 2.0 / nx, 1.0 / (ny - 1)
+    s, A, mode = 2.0, 0.05, 3
+    w = 2 * np.pi * mode / nx
+    i = np.arange(nx)
+    j = np.arange(ny)
+    phi = s * (j ** 4 / 24.0)[:, None] + A * np.cos(w * i)[None, :]
+    m = oracle.make_method(equation=oracle.HJ, gamma=oracle.GAMMA_LAD, eps=0.2, C_lad=0.1)
+    lad = oracle.lad_field(spec, m, phi)
+    T = b[0] + 2 * sum(b[k] * np.cos(k * w) for k in range(1, 5))
+    amp = 16 * A * np.sin(w / 2) ** 4
+    want = 0.1 * (s / dy + amp * T * np.cos(w * i) / dx)
+    assert s / dy > amp / dx
+    assert np.abs(lad - want[None, :]).max() < 1e-10 * np.abs(want).max()
+
+
+def _kprime(scheme):
+    w = np.linspace(0, np.pi, 200001)
+    return round(float(np.max(symbol(scheme, w))), 3)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_kprime_is_the_largest_modified_wavenumber(oracle, scheme):
+    """The local step's k' (reading of Sec. 3.3's local time stepping) is
+    the scheme's largest modified wavenumber to three decimals: Poisson on a
+    doubly periodic grid without filter takes dt = 1/(k'^2 sum 1/h^2), so a
+    Fourier mode is multiplied by the RK4 polynomial of
+    z = -k'(w)^2 dt / h^2 and the mean grows by dt."""
+    n0, n1, h = 16, 8, 0.1
+    spec = G.GridSpec("periodic", 2, (n0, n1, 1),
+                      ((G.PERIODIC, G.PERIODIC), (G.PERIODIC, G.PERIODIC), (0, 0)),
+                      h=(h, h, 1.0))
+    w = 2 * np.pi * 3 / n0
+    x = np.arange(n0)
+    phi0 = np.broadcast_to(0.5 + 0.1 * np.cos(w * x)[None, :], (n1, n0)).copy()
+    m = oracle.make_method(equation=oracle.POISSON, scheme=scheme, filter=0, rk=oracle.RK4,
+                           fixed_iters=1)
+    out, st, it, hist = oracle.solve(spec, m, phi0=phi0)
+    kp = _kprime(scheme)
+    dt = 1.0 / (kp * kp * 2 / h ** 2)
+    z = -symbol(scheme, w) ** 2 * dt / h ** 2
+    P = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    want = 0.5 + dt + 0.1 * P * np.cos(w * x)
+    assert np.abs(out - want[None, :]).max() < 1e-13
+
+
+@pytest.mark.parametrize("scheme", SCHEMES + ["UW"])
+@pytest.mark.parametrize("form", ["eikonal", "hj", "hj_lad", "hj_curv"])
+def test_local_step_on_a_constant_field(oracle, scheme, form):
+    """At a constant field c on a doubly periodic grid every residual is 1
+    (|grad phi| = 0, no Laplacian, no curvature, LAD sensor 0), so one
+    pseudo step adds exactly the local step
+      dt = sigma / (2 k_adv S1 max(|grad phi|, 1) + k'^2 (Gamma + nu) S2),
+    S1 = sum 1/h_l, S2 = sum 1/h_l^2, Gamma = eps c (0 for LAD: its sensor
+    vanishes), nu = nu0 (1 - 0)^2 with curvature; the Eikonal drops the
+    second term.  k' from the symbol; the upwind baseline uses k_adv = 2 and
+    k' = 1.  The filter leaves constants alone."""
+    if scheme == "UW" and form == "hj_curv":
+        pytest.skip("curvature is not paired with the upwind scheme")
+    hx, hy = 0.1, 0.05
+    spec = G.GridSpec("periodic", 2, (12, 10, 1),
+                      ((G.PERIODIC, G.PERIODIC), (G.PERIODIC, G.PERIODIC), (0, 0)),
+                      h=(hx, hy, 1.0))
+    c, eps, nu0, sigma = 0.8, 0.3, 0.02, 0.7
+    eq = oracle.EIKONAL if form == "eikonal" else oracle.HJ
+    gam = oracle.GAMMA_LAD if form == "hj_lad" else oracle.GAMMA_LINEAR
+    m = oracle.make_method(equation=eq, gamma=gam, curvature=int(form == "hj_curv"),
+                           eps=eps, nu0=nu0, sigma=sigma, scheme=scheme, rk=oracle.RK4,
+                           alpha_f=0.48, fixed_iters=1)
+    out, st, it, hist = oracle.solve(spec, m, phi0=np.full((10, 12), c))
+    kp = 1.0 if scheme == "UW" else _kprime(scheme)
+    kadv = 2.0 if scheme == "UW" else kp
+    S1, S2 = 1 / hx + 1 / hy, 1 / hx ** 2 + 1 / hy ** 2
+    diff = {"eikonal": 0.0, "hj": eps * c, "hj_lad": 0.0, "hj_curv": eps * c + nu0}[form]
+    dt = sigma / (2 * kadv * S1 + kp * kp * diff * S2)
+    assert np.abs(out - (c + dt)).max() < 1e-14
+
+
+@pytest.mark.parametrize("c", [0.6, 1.7])
+def test_nu_on_an_ogrid(oracle, c):
+    """Curvature form with nu = nu0 (1 - |grad phi|)^2 (Sec. 5.4): on a
+    uniform-theta O-grid phi = c (r_out - r) has discrete |grad phi| = c,
+    Laplacian -c/r and |grad phi| kappa = -c^2/((c + eps0) r) < 0 exactly
+    (the O-grid identities), so with eps = 0
+      R = 1 - nu0 (1 - c)^2 c / r - c^2."""
+    spec = G.cylinder(48, 20, rout=6.0, dr1=2e-2, ratio=1.15)
+    r = spec.exact + 0.5
+    nu0 = 0.05
+    m = oracle.make_method(equation=oracle.HJ, gamma=oracle.GAMMA_LINEAR, curvature=1,
+                           eps=0.0, nu0=nu0, eps0=1e-6, scheme="C6")
+    ev = oracle.evaluate(spec, m, c * (6.0 - r))
+    want = 1 - nu0 * (1 - c) ** 2 * c / r - c * c
+    assert np.abs(ev["g"] - c).max() < 1e-11
+    assert np.abs(ev["R"] - want).max() < 1e-9
+
+
+def _affine3d(n=(9, 10, 11), periodic0=False):
+    M = np.array([[0.11, 0.03, -0.02],
+                  [-0.04, 0.09, 0.025],
+                  [0.015, -0.035, 0.13]])
+    x0 = np.array([0.3, -0.2, 0.5])
+    k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    X = [x0[m] + M[m, 0] * i + M[m, 1] * j + M[m, 2] * k for m in range(3)]
+    bc0 = (G.PERIODIC, G.PERIODIC) if periodic0 else (G.WALL, G.NEUMANN)
+    period = None
+    if periodic0:
+        period = tuple(tuple((n[0] * M[m, 0]) if l == 0 else 0.0 for m in range(3))
+                       for l in range(3))
+    spec = G.GridSpec("affine3d", 3, n, (bc0, (G.WALL, G.OUTFLOW), (G.NEUMANN, G.WALL)),
+                      coords=np.stack(X), period=period)
+    return spec, M
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("periodic0", [False, True])
+def test_metrics_3d_affine_grid(oracle, scheme, periodic0):
+    """An affine 3D grid x = x0 + M (i, j, k) with a full matrix M: every
+    scheme and closure differentiates linear functions exactly, so the
+    coordinate derivatives are M at every point and the metrics
+    d xi_l / d x_m are the entries of M^-1 -- every cofactor of the 3x3
+    inverse, off-block terms included.  With direction 0 periodic the seam
+    jump n0 M[:, 0] must be added across the seam."""
+    spec, M = _affine3d(periodic0=periodic0)
+    met = oracle.metrics(spec, scheme)
+    inv = np.linalg.inv(M)
+    for l in range(3):
+        for mm in range(3):
+            assert np.abs(met[3 * l + mm] - inv[l, mm]).max() < 1e-11 * np.abs(inv).max()
