@@ -39,12 +39,18 @@ struct LineOpDev {
 // rows, then corrected by its two coupling vectors (spikes) times the true
 // values at the neighbouring segments' ends, which the host-inverted
 // reduced system gives as linear combinations of all segments' local end
-// values.  tab (T): ell[n], ib[n], cb[n] (local LU: y_j = r_j - ell_j
-// y_{j-1}, x_j = ib_j y_j - cb_j x_{j+1}), vv[n], ww[n] (spikes on the
-// previous segment's last and the next segment's first value), then per
-// segment red[s][4][S]: the rows giving the previous segment's last value
+// values.  tab (T): five row arrays of n + S entries, position j at
+// j + (segment of j): ell, ib, cb (local LU: y_j = r_j - ell_j y_{j-1},
+// x_j = ib_j y_j - cb_j x_{j+1}), vv, ww (spikes on the previous segment's
+// last and the next segment's first value); then per segment, 4S + 1
+// apart, red[s][4][S]: the rows giving the previous segment's last value
 // and the next segment's first value from (local first values, local last
 // values).
+__host__ __device__ inline int seg_table_len(int n, int S)
+{
+    return 5 * (n + S) + S * (4 * S + 1);
+}
+
 struct SegOpDev {
     int n, S;
     int periodic;

@@ -431,11 +431,25 @@ const SegOpDev *ctx_segop(wd_ctx *ctx, int kind, int n, int periodic, int scheme
             fail(WD_ERR_UNSUPPORTED, "segmented line system (n=%d, S=%d) is singular", n, sg.S);
             return nullptr;
         }
+        // device layout: each row array n + S long with position j at
+        // j + (segment of j), and the reduced rows S (4S + 1) apart, so the
+        // lanes of one step (segments M apart) read distinct LDS banks
+        const int n2 = n + sg.S, rs = 4 * sg.S + 1;
+        std::vector<double> d((size_t)5 * n2 + (size_t)sg.S * rs, 0.0);
+        for (int s = 0; s < sg.S; ++s) {
+            int bs, len;
+            seg_bounds(sg, s, bs, len);
+            for (int a = 0; a < 5; ++a)
+                for (int j = bs; j < bs + len; ++j)
+                    d[(size_t)a * n2 + j + s] = t[(size_t)a * n + j];
+            for (int k = 0; k < 4 * sg.S; ++k)
+                d[(size_t)5 * n2 + (size_t)s * rs + k] = t[(size_t)5 * n + (size_t)s * 4 * sg.S + k];
+        }
         const size_t es = fp64 ? 8 : 4;
-        std::vector<unsigned char> host(t.size() * es);
-        for (size_t i = 0; i < t.size(); ++i) {
-            if (fp64) reinterpret_cast<double *>(host.data())[i] = t[i];
-            else reinterpret_cast<float *>(host.data())[i] = (float)t[i];
+        std::vector<unsigned char> host(d.size() * es);
+        for (size_t i = 0; i < d.size(); ++i) {
+            if (fp64) reinterpret_cast<double *>(host.data())[i] = d[i];
+            else reinterpret_cast<float *>(host.data())[i] = (float)d[i];
         }
         void *mem = nullptr;
         if (hipMalloc(&mem, host.size()) != hipSuccess) {
@@ -460,7 +474,7 @@ size_t seg_lds_bytes(const GridDev &g, int kind, int l, int fp64)
     const SegGeo &sg = g.sgeo[l];
     const SegOpDev &op = kind == PASS_SFILTER ? g.sfop[l] : g.sdop[l];
     size_t el = (size_t)sg.xsize * (kind == PASS_SCART_LAST ? 2 : 1);
-    if (kind != PASS_SLAD && op.solve) el += (size_t)5 * op.n + (size_t)4 * op.S * op.S;
+    if (kind != PASS_SLAD && op.solve) el += seg_table_len(op.n, op.S);
     return el * (fp64 ? 8 : 4);
 }
 

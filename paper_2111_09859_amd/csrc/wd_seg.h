@@ -88,7 +88,7 @@ template <typename T>
 __device__ inline void seg_tables(const SegOpDev &op, T *tb)
 {
     if (!op.solve) return;
-    const int ntab = 5 * op.n + 4 * op.S * op.S;
+    const int ntab = seg_table_len(op.n, op.S);
     gptr<const T> src = gcast<const T>(op.tab);
     for (int k = threadIdx.x; k < ntab; k += kSegThreads) tb[k] = src[k];
 }
@@ -290,9 +290,9 @@ __device__ inline void seg_solve(const SegGeo &sg, const SegOpDev &op, const T *
         for (int i = 0; i < M; ++i) x[i] *= scale;
         return;
     }
-    const int n = op.n;
-    const T *ell = tb + L.b, *ib = tb + n + L.b, *cb = tb + 2 * n + L.b;
-    const T *vv = tb + 3 * n + L.b, *ww = tb + 4 * n + L.b;
+    const int n2 = op.n + op.S, sb = L.b + L.s;   // the segment's table entries
+    const T *ell = tb + sb, *ib = tb + n2 + sb, *cb = tb + 2 * n2 + sb;
+    const T *vv = tb + 3 * n2 + sb, *ww = tb + 4 * n2 + sb;
     // rows i >= len (a short segment) read the next segment's table entries
     // and a zero right-hand side; the segment's own last row has cb = 0, so
     // they never reach it, and they are not stored
@@ -313,7 +313,7 @@ __device__ inline void seg_solve(const SegGeo &sg, const SegOpDev &op, const T *
     T lp = (T)0, fn = (T)0;
     const int S = sg.S;
     if (S > 1 || op.periodic) {
-        const T *red = tb + 5 * n + L.s * 4 * S;
+        const T *red = tb + 5 * n2 + L.s * (4 * S + 1);
         const int base = L.w * S;
         for (int k = 0; k < S; ++k) {
             const T f = __shfl(zf, base + k, kSegThreads);
@@ -548,7 +548,7 @@ k_seg_cart(const GridDev *__restrict__ grids, const Item *__restrict__ items, in
         const SegOpDev &op = g.sdop[l];
         __syncthreads();
         if (item.grid != cur) {
-            X = tb + (op.solve ? 5 * op.n + 4 * op.S * op.S : 0);
+            X = tb + (op.solve ? seg_table_len(op.n, op.S) : 0);
             seg_tables<T>(op, tb);
             cur = item.grid;
         }
@@ -772,7 +772,7 @@ k_seg_filter(const GridDev *__restrict__ grids, const Item *__restrict__ items, 
         const SegOpDev &op = g.sfop[l];
         __syncthreads();
         if (item.grid != cur) {
-            X = tb + (op.solve ? 5 * op.n + 4 * op.S * op.S : 0);
+            X = tb + (op.solve ? seg_table_len(op.n, op.S) : 0);
             seg_tables<T>(op, tb);
             cur = item.grid;
         }
