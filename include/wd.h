@@ -174,6 +174,22 @@ int wd_solve(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method,
              void *phi, void *phi_aux, double *hist, int hist_cap, int *iters,
              void *ws, size_t ws_bytes, void *stream);
 
+/* wd_solve for callers that cannot allocate device memory (code that must
+ * not call hipMalloc, such as tight serving loops or harnesses that forbid
+ * it): the same solve with the workspace and the line-operator tables placed
+ * in a library-owned static device array of 64 MiB on each GPU, held until
+ * the process ends; no hipMalloc, hipFree or other allocating call and no
+ * graph capture (kernels are launched directly).  Arguments as for wd_solve
+ * without ws / ws_bytes.  A grid whose workspace (wd_workspace_bytes) plus
+ * tables exceed 64 MiB is rejected with WD_ERR_NO_MEMORY (about 2.5 M
+ * points in FP32 with RK4 and LAD, half that in FP64).  Every call on one
+ * GPU uses that GPU's one array: calls that overlap on one GPU (two
+ * contexts, two threads) race and corrupt each other; calls on one
+ * context are serialised by the context.  Returns like wd_solve. */
+int wd_solve_noalloc(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method,
+                     void *phi, void *phi_aux, double *hist, int hist_cap, int *iters,
+                     void *stream);
+
 /* Batched solve of n independent grids in one set of launches per RK
  * stage.  All grids share ndim, precision and rk; everything else (size,
  * scheme, equation, Gamma, metrics, faces, tolerances) may differ.  Each

@@ -94,6 +94,8 @@ def lib():
         "wd_ctx_profile": ([vp, C.c_int], C.c_int),
         "wd_ctx_profile_read": ([vp, C.POINTER(wd_kernel_stat), C.c_int, ip], C.c_int),
         "wd_ctx_set_segmented": ([vp, C.c_int], C.c_int),
+        "wd_solve_noalloc": ([vp, C.POINTER(wd_grid_desc), C.POINTER(wd_method), vp, vp, dp,
+                              C.c_int, ip, vp], C.c_int),
         "wd_seg_solve_host": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int,
                                dp, dp, ip], C.c_int),
         "wd_line_solve_host": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, dp,
@@ -180,6 +182,19 @@ def wd_solve(ctx, desc, method, phi_ptr, aux_ptr, hist, hist_cap, ws_ptr, ws_byt
                         C.byref(it), ws_ptr, ws_bytes, stream)
     if check:
         _check(rc, "wd_solve")
+    return rc, it.value
+
+
+def wd_solve_noalloc(ctx, desc, method, phi_ptr, aux_ptr, hist, hist_cap, stream=None,
+                     check=True):
+    """wd_solve without any device allocation (the library's static scratch
+    holds workspace and tables).  Returns (rc, iters)."""
+    it = C.c_int(0)
+    hp = C.cast(hist, C.POINTER(C.c_double)) if hist is not None else None
+    rc = lib().wd_solve_noalloc(ctx, C.byref(desc), C.byref(method), phi_ptr, aux_ptr, hp,
+                                hist_cap, C.byref(it), stream)
+    if check:
+        _check(rc, "wd_solve_noalloc")
     return rc, it.value
 
 

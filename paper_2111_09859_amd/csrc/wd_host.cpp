@@ -140,12 +140,17 @@ int build_line_system(int kind, int n, int periodic, int scheme, double af,
 }
 
 const LineOpDev *ctx_lineop(wd_ctx *ctx, int kind, int n, int periodic, int scheme,
-                            double af, int fp64)
+                            double af, int fp64, TableArena *ar)
 {
     OpKey key{kind, n, periodic, kind == OP_FILTER ? -1 : scheme, fp64,
               kind == OP_FILTER ? af : 0.0};
-    auto it = ctx->ops.find(key);
-    if (it != ctx->ops.end()) return &it->second.dev;
+    if (ar) {
+        for (auto &kv : ar->ops)
+            if (!(kv.first < key) && !(key < kv.first)) return &kv.second.dev;
+    } else {
+        auto it = ctx->ops.find(key);
+        if (it != ctx->ops.end()) return &it->second.dev;
+    }
     OpEntry e;
     std::memset(&e.dev, 0, sizeof e.dev);
     e.dev.n = n;
@@ -184,11 +189,6 @@ const LineOpDev *ctx_lineop(wd_ctx *ctx, int kind, int n, int periodic, int sche
     const size_t es = fp64 ? 8 : 4;
     const size_t tab_bytes = (size_t)nlev * n * 2 * es;
     const size_t bytes = tab_bytes + (size_t)n * es + 256;
-    void *mem = nullptr;
-    if (hipMalloc(&mem, bytes) != hipSuccess) {
-        fail(WD_ERR_NO_MEMORY, "hipMalloc of %zu bytes for a line operator failed", bytes);
-        return nullptr;
-    }
     std::vector<unsigned char> host(bytes, 0);
     for (size_t i = 0; i < (size_t)nlev * n; ++i) {
         if (fp64) {
@@ -208,14 +208,37 @@ const LineOpDev *ctx_lineop(wd_ctx *ctx, int kind, int n, int periodic, int sche
         else
             reinterpret_cast<float *>(host.data() + soff)[i] = (float)scale[i];
     }
-    if (hipMemcpy(mem, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(mem);
-        fail(WD_ERR_HIP, "upload of a line operator failed");
-        return nullptr;
+    void *mem = nullptr;
+    if (ar) {
+        mem = ar->carve(bytes);
+        if (!mem) {
+            fail(WD_ERR_NO_MEMORY, "line-operator tables exceed the %zu-byte scratch", ar->cap);
+            return nullptr;
+        }
+        ar->host.push_back(std::move(host));
+        if (hipMemcpyAsync(mem, ar->host.back().data(), bytes, hipMemcpyHostToDevice, ar->stream) !=
+            hipSuccess) {
+            fail(WD_ERR_HIP, "upload of a line operator failed");
+            return nullptr;
+        }
+    } else {
+        if (hipMalloc(&mem, bytes) != hipSuccess) {
+            fail(WD_ERR_NO_MEMORY, "hipMalloc of %zu bytes for a line operator failed", bytes);
+            return nullptr;
+        }
+        if (hipMemcpy(mem, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(mem);
+            fail(WD_ERR_HIP, "upload of a line operator failed");
+            return nullptr;
+        }
     }
-    e.mem = mem;
+    e.mem = ar ? nullptr : mem;
     e.dev.tab = mem;
     e.dev.scale = static_cast<unsigned char *>(mem) + soff;
+    if (ar) {
+        ar->ops.emplace_back(key, e);
+        return &ar->ops.back().second.dev;
+    }
     auto ins = ctx->ops.emplace(key, e);
     return &ins.first->second.dev;
 }
@@ -413,12 +436,17 @@ int build_seg_tables(int kind, int n, int periodic, int scheme, double af, const
 }
 
 const SegOpDev *ctx_segop(wd_ctx *ctx, int kind, int n, int periodic, int scheme, double af,
-                          int fp64, const SegGeo &sg)
+                          int fp64, const SegGeo &sg, TableArena *ar)
 {
     OpKey key{kind + 2 + 4 * (sg.M + 64 * sg.S), n, periodic, kind == OP_FILTER ? -1 : scheme,
               fp64, kind == OP_FILTER ? af : 0.0};
-    auto it = ctx->segops.find(key);
-    if (it != ctx->segops.end()) return &it->second.dev;
+    if (ar) {
+        for (auto &kv : ar->segops)
+            if (!(kv.first < key) && !(key < kv.first)) return &kv.second.dev;
+    } else {
+        auto it = ctx->segops.find(key);
+        if (it != ctx->segops.end()) return &it->second.dev;
+    }
     SegEntry e;
     e.dev.n = n;
     e.dev.S = sg.S;
@@ -452,17 +480,37 @@ const SegOpDev *ctx_segop(wd_ctx *ctx, int kind, int n, int periodic, int scheme
             else reinterpret_cast<float *>(host.data())[i] = (float)d[i];
         }
         void *mem = nullptr;
-        if (hipMalloc(&mem, host.size()) != hipSuccess) {
-            fail(WD_ERR_NO_MEMORY, "hipMalloc of %zu bytes for a line operator failed", host.size());
-            return nullptr;
+        if (ar) {
+            mem = ar->carve(host.size());
+            if (!mem) {
+                fail(WD_ERR_NO_MEMORY, "line-operator tables exceed the %zu-byte scratch", ar->cap);
+                return nullptr;
+            }
+            const size_t bytes = host.size();
+            ar->host.push_back(std::move(host));
+            if (hipMemcpyAsync(mem, ar->host.back().data(), bytes, hipMemcpyHostToDevice,
+                               ar->stream) != hipSuccess) {
+                fail(WD_ERR_HIP, "upload of a line operator failed");
+                return nullptr;
+            }
+        } else {
+            if (hipMalloc(&mem, host.size()) != hipSuccess) {
+                fail(WD_ERR_NO_MEMORY, "hipMalloc of %zu bytes for a line operator failed",
+                     host.size());
+                return nullptr;
+            }
+            if (hipMemcpy(mem, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+                (void)hipFree(mem);
+                fail(WD_ERR_HIP, "upload of a line operator failed");
+                return nullptr;
+            }
+            e.mem = mem;
         }
-        if (hipMemcpy(mem, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(mem);
-            fail(WD_ERR_HIP, "upload of a line operator failed");
-            return nullptr;
-        }
-        e.mem = mem;
         e.dev.tab = mem;
+    }
+    if (ar) {
+        ar->segops.emplace_back(key, e);
+        return &ar->segops.back().second.dev;
     }
     auto ins = ctx->segops.emplace(key, e);
     return &ins.first->second.dev;
@@ -659,7 +707,7 @@ static double kprime(int scheme)
 // grid_region_bytes).  The stopping state lives in the region, so a grid
 // keeps its progress when the batch around it changes.
 int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *phi,
-                void *region, GridDev &g, GridHost &h)
+                void *region, GridDev &g, GridHost &h, TableArena *ar)
 {
     std::memset(&g, 0, sizeof g);
     h = GridHost();
@@ -772,12 +820,12 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
                 break;
             }
             const SegOpDev *sd = ctx_segop(ctx, OP_DERIV, d.n[l], g.periodic[l], dscheme, 0.0, fp64,
-                                           g.sgeo[l]);
+                                           g.sgeo[l], ar);
             if (!sd) return WD_ERR_NO_MEMORY;
             g.sdop[l] = *sd;
             if (m.filter) {
                 const SegOpDev *sf = ctx_segop(ctx, OP_FILTER, d.n[l], g.periodic[l], dscheme,
-                                               m.alpha_f, fp64, g.sgeo[l]);
+                                               m.alpha_f, fp64, g.sgeo[l], ar);
                 if (!sf) return WD_ERR_NO_MEMORY;
                 g.sfop[l] = *sf;
             }
@@ -790,11 +838,11 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
         g.seg_split = g.seg && !has_x;
     }
     for (int l = 0; l < d.ndim; ++l) {
-        const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, d.n[l], g.periodic[l], dscheme, 0.0, fp64);
+        const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, d.n[l], g.periodic[l], dscheme, 0.0, fp64, ar);
         if (!dop) return WD_ERR_NO_MEMORY;
         g.dop[l] = *dop;
         if (m.filter) {
-            const LineOpDev *fop = ctx_lineop(ctx, OP_FILTER, d.n[l], g.periodic[l], dscheme, m.alpha_f, fp64);
+            const LineOpDev *fop = ctx_lineop(ctx, OP_FILTER, d.n[l], g.periodic[l], dscheme, m.alpha_f, fp64, ar);
             if (!fop) return WD_ERR_NO_MEMORY;
             g.fop[l] = *fop;
         }
@@ -842,9 +890,10 @@ int plan_tables(Plan &P, void *tables, size_t bytes, long long items_cap)
 
 // one workspace: tables first, then each grid's region
 int plan_batch(wd_ctx *ctx, int n, const wd_grid_desc *descs, const wd_method *meths,
-               void *const *phis, void *ws, size_t ws_bytes, Plan &P)
+               void *const *phis, void *ws, size_t ws_bytes, Plan &P, TableArena *ar)
 {
     P = Plan();
+    P.arena = ar;
     P.fp64 = meths[0].precision == WD_FP64;
     P.rk = meths[0].rk;
     P.stages = P.rk == WD_RK4 ? 4 : 3;
@@ -860,7 +909,7 @@ int plan_batch(wd_ctx *ctx, int n, const wd_grid_desc *descs, const wd_method *m
     P.host.resize(n);
     for (int i = 0; i < n; ++i) {
         int rc = layout_grid(ctx, descs[i], meths[i], phis ? phis[i] : nullptr, base + off,
-                             P.grids[i], P.host[i]);
+                             P.grids[i], P.host[i], ar);
         if (rc) return rc;
         off += grid_region_bytes(descs[i], meths[i]);
     }
@@ -1389,7 +1438,7 @@ int run_plan(wd_ctx *ctx, const Plan &P, int K, std::vector<GridState> &states)
     int maxit = 0;
     for (int i = 0; i < P.n; ++i) maxit = std::max(maxit, P.grids[i].max_iter);
     // profiling mode launches directly, each kernel bracketed by events
-    const int use_graph = ctx->use_graphs && !ctx->profile;
+    const int use_graph = ctx->use_graphs && !ctx->profile && !P.arena;
     CachedGraph *cg = use_graph ? graph_for(ctx, P, K) : nullptr;
     if (use_graph && !cg) return WD_ERR_HIP;
     states.resize(P.n);
@@ -1447,7 +1496,8 @@ int poisson_convert(wd_ctx *ctx, const Plan &P, int i, void *aux, hipStream_t s)
     v.lad = 0;
     for (int l = 0; l < g.ndim; ++l) {
         v.F[l] = gh.pois_F[l];
-        const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, g.n[l], g.periodic[l], g.scheme, 0.0, 1);
+        const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, g.n[l], g.periodic[l], g.scheme, 0.0, 1,
+                                          P.arena);
         if (!dop) return WD_ERR_NO_MEMORY;
         v.dop[l] = *dop;
     }
@@ -1600,6 +1650,17 @@ int wd_ctx_create(int device, wd_ctx **out)
         return fail(WD_ERR_HIP, "stream/event/pinned allocation failed");
     }
     c->pinned_cap = 4096;
+    // the device's static scratch for calls that allocate nothing
+    if (noalloc_scratch(device, &c->noalloc) != 0) {
+        (void)hipStreamDestroy(c->stream);
+        (void)hipEventDestroy(c->ev_in);
+        (void)hipEventDestroy(c->ev_out);
+        (void)hipHostFree(c->pinned_states);
+        delete c;
+        return fail(WD_ERR_HIP, "hipGetSymbolAddress of the scratch array failed on device %d",
+                    device);
+    }
+    c->noalloc_bytes = kNoAllocBytes;
     const char *g = std::getenv("WD_NO_GRAPHS");
     c->use_graphs = !(g && g[0] == '1');
     c->graph_iters = 32;
@@ -1675,6 +1736,43 @@ int wd_solve(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method, voi
     int st = 0;
     int rc = wd_solve_batched(ctx, 1, desc, method, phis, auxs, hs, hist_cap, iters, &st, ws,
                               ws_bytes, stream);
+    return rc;
+}
+
+int wd_solve_noalloc(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method, void *phi,
+                     void *phi_aux, double *hist, int hist_cap, int *iters, void *stream)
+{
+    if (!ctx || !desc || !method || !phi) return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    int rc = check_desc(desc);
+    if (!rc) rc = check_walls(desc);
+    if (!rc) rc = check_method(method);
+    if (rc) return rc;
+    if (!ctx->noalloc) return fail(WD_ERR_HIP, "no scratch on this context");
+    // workspace first, the line-operator tables after it
+    const size_t ws = batch_bytes(1, desc, method);
+    if (ws > ctx->noalloc_bytes)
+        return fail(WD_ERR_NO_MEMORY,
+                    "the grid needs a %zu-byte workspace; the scratch of calls that allocate "
+                    "nothing holds %zu bytes", ws, ctx->noalloc_bytes);
+    (void)hipSetDevice(ctx->device);
+    StreamJoin join(ctx, stream);
+    TableArena ar;
+    ar.base = static_cast<unsigned char *>(ctx->noalloc) + ((ws + 255) & ~(size_t)255);
+    ar.cap = ctx->noalloc_bytes - ((ws + 255) & ~(size_t)255);
+    ar.stream = ctx->stream;
+    Plan P;
+    void *phis[1] = {phi};
+    void *auxs[1] = {phi_aux};
+    double *hs[1] = {hist};
+    int st = 0;
+    rc = plan_batch(ctx, 1, desc, method, phis, ctx->noalloc, ws, P, &ar);
+    if (rc) {
+        (void)hipStreamSynchronize(ctx->stream);   // table uploads read host memory held here
+        return rc;
+    }
+    rc = solve_plan(ctx, P, auxs, hs, hist_cap, iters, &st);
+    (void)hipStreamSynchronize(ctx->stream);
     return rc;
 }
 

@@ -5,6 +5,7 @@
 #include "wd_common.h"
 #include "wd_kernels.h"
 
+#include <list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -42,6 +43,25 @@ struct TuneKey {
     {
         return std::tie(ndim, n0, n1, n2, dir, fp64) <
                std::tie(o.ndim, o.n0, o.n1, o.n2, o.dir, o.fp64);
+    }
+};
+
+// Device memory for the line-operator tables of one call that must not
+// allocate: carved from a caller-provided region, filled by stream-ordered
+// copies whose host sources live here until the call ends.
+struct TableArena {
+    unsigned char *base = nullptr;
+    size_t cap = 0, used = 0;
+    hipStream_t stream = nullptr;
+    std::list<std::vector<unsigned char>> host;
+    std::list<std::pair<OpKey, OpEntry>> ops;
+    std::list<std::pair<OpKey, SegEntry>> segops;
+    void *carve(size_t bytes)
+    {
+        const size_t off = (used + 255) & ~(size_t)255;
+        if (off + bytes > cap) return nullptr;
+        used = off + bytes;
+        return base + off;
     }
 };
 
@@ -97,6 +117,7 @@ struct Plan {
     Slot scart[3], scartl[3], sfilt[3], slad0[3], slad1[3];  // segmented passes, one list per M
     int face[6], face_init[6];
     int fin = 0, resid = 0, init = 0, uwadv = 0, cfin = 0;
+    TableArena *arena = nullptr;   // line-operator tables of a call that allocates nothing
     GridDev *d_grids = nullptr;
     GridDev *d_aux = nullptr, *d_aux2 = nullptr;
     GridState *d_states = nullptr;
@@ -123,18 +144,18 @@ bool seg_plan(int n, int fp64, SegGeo &sg, int prefer = 0);
 int build_seg_tables(int kind, int n, int periodic, int scheme, double af, const SegGeo &sg,
                      std::vector<double> &out);
 const SegOpDev *ctx_segop(wd_ctx *ctx, int kind, int n, int periodic, int scheme, double af,
-                          int fp64, const SegGeo &sg);
+                          int fp64, const SegGeo &sg, TableArena *ar = nullptr);
 size_t seg_lds_bytes(const GridDev &g, int kind, int l, int fp64);
 const LineOpDev *ctx_lineop(wd_ctx *ctx, int kind, int n, int periodic, int scheme,
-                            double af, int fp64);
+                            double af, int fp64, TableArena *ar = nullptr);
 size_t grid_region_bytes(const wd_grid_desc &d, const wd_method &m);
 long long grid_items(const wd_grid_desc &d);
 size_t table_bytes(int n, long long items);
 int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *phi,
-                void *region, GridDev &g, GridHost &h);
+                void *region, GridDev &g, GridHost &h, TableArena *ar = nullptr);
 int plan_tables(Plan &P, void *tables, size_t bytes, long long items_cap);
 int plan_batch(wd_ctx *ctx, int n, const wd_grid_desc *descs, const wd_method *meths,
-               void *const *phis, void *ws, size_t ws_bytes, Plan &P);
+               void *const *phis, void *ws, size_t ws_bytes, Plan &P, TableArena *ar = nullptr);
 int tile_np(const GridDev &g, int l);
 void build_items(Plan &P);
 int upload_plan(wd_ctx *ctx, const Plan &P, hipStream_t s);
@@ -162,6 +183,8 @@ struct wd_ctx {
     int graph_iters = 32;
     std::map<wd::OpKey, wd::OpEntry> ops;
     std::map<wd::OpKey, wd::SegEntry> segops;
+    void *noalloc = nullptr;             // the device's static scratch (calls that allocate nothing)
+    size_t noalloc_bytes = 0;
     int use_seg = 1;                     // segmented passes on Cartesian grids
                                          // (16, 24, 32: segment length tried first)
     std::map<wd::TuneKey, int> tune;

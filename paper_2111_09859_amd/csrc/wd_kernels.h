@@ -76,6 +76,11 @@ void launch_ls_signed(int fp64, long long n, const unsigned char *solid, const v
 // partials [nb][kMaxLevels] (FP64, device)
 void launch_ls_length(int fp64, const void *phi, int nx, int ny, double hx, double hy,
                       const double *levels, int nlev, double *part, int nb, hipStream_t s);
+// The device's copy of the library's static scratch array (calls that
+// allocate nothing): its device address, looked up once per device with that
+// device current; WD_OK or WD_ERR_HIP.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+int noalloc_scratch(int device, void **ptr);
 void launch_finalize(const GridDev *grids, int ngrids, hipStream_t s);
 void launch_mirror(const GridDev *grids, int ngrids, hipStream_t s);
 // field-major metrics [c][q] into the point-major array [q][c] (dd = ndim^2)

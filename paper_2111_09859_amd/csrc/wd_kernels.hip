@@ -9,6 +9,7 @@
 #include "wd_kernels.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace wd {
 
@@ -943,6 +944,29 @@ void launch_mirror(const GridDev *g, int ngrids, hipStream_t s)
 {
     if (ngrids <= 0) return;
     hipLaunchKernelGGL(k_mirror, dim3((ngrids + 255) / 256), dim3(256), 0, s, g, ngrids);
+}
+
+// Scratch of the calls that allocate nothing: workspace and line-operator
+// tables of one solve, one copy per GPU the library runs on, held until the
+// process ends.  Host code must use the address hipGetSymbolAddress gives
+// for the current device, never the array's name.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+int noalloc_scratch(int device, void **ptr)
+{
+    static std::mutex mu;
+    static void *addr[64] = {nullptr};
+    if (device < 0 || device >= 64) return -5;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != device) return -5;
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -5;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return 0;
 }
 
 void launch_finalize(const GridDev *g, int ngrids, hipStream_t s)
