@@ -1,19 +1,33 @@
 """Benchmark of the wall-distance hot path on one MI355X.
 
-Workload (default): 2D cylinder O-grid 512 (theta) x 256 (r), wall R = 0.5,
-far field r = 20 (outflow), radial spacing min(1e-3 * 1.03^j, cap);
-6th-order compact derivatives, 10th-order implicit filter (alpha_f 0.495),
-LAD pseudo-HJ (eps 0.2, C 0.1) with curvature correction, RK4 with local
-time stepping.  One step = one complete solve from phi = 0 to the stopping
-rule (FP32: max change <= 1e-6 or no new minimum for 1000 iterations;
-FP64: max change <= 1e-10) with grid, metrics and fields resident in HBM.
-
-Before the warm-up, the library's autotuner picks the tile width per
-direction for this grid (untimed; --no-autotune keeps the defaults).
+Workload (default): the 3D square duct 256^3 on [0,1]^3 (x periodic with
+256 distinct points, walls y = 0, 1 and z = 0, 1), LAD pseudo-HJ (eps 0.2,
+C 0.1), 6th-order compact derivatives (tridiagonal line solves along every
+direction), 10th-order implicit filter (alpha_f 0.495) after every pseudo
+step, RK4 with local time stepping, FP32.  One step = 200 pseudo
+iterations from phi = 0 (throughput at a fixed iteration count: the march
+needs thousands of iterations to converge at this size), with grid and
+fields resident in HBM; nothing of an iteration is skipped.
 
 value = grid-point updates per second (points x pseudo iterations / time);
 one update is one point through one full pseudo iteration (LAD field, all
-RK stages, the filter in every direction, boundary conditions, residual).
+RK stages, the filter in every direction, boundary conditions, FP64
+residual).
+
+roofline: the compulsory HBM bytes of the method per grid point (27 field
+accesses per RK4 iteration on a 3D uniform grid: 5 per RK stage, 2 per
+filter direction, 1 for the residual) over measured time, against 8 TB/s.
+The dominant unit of work is one RK stage (its directional line passes and
+its pointwise finish, about three quarters of an iteration): achieved =
+5 accesses x points / the mean duration of a stage's launches, timed with
+HIP events on the library's stream in a second pass over the same steps.
+The whole iteration's figure sits beside it.  traffic = HBM bytes per
+stage from rocprofv3 FETCH_SIZE / WRITE_SIZE counters (calibrated on a
+plain copy), kept in profiles/traffic.json and used only while the kernel
+sources are unchanged.
+
+Secondary fields: the same duct in FP64, and the 2D cylinder O-grid
+512 x 256 (C6, LAD + curvature) solved to convergence in FP32.
 
 Prints ONE JSON line.
 """
@@ -43,8 +57,9 @@ def workload(name):
                 "C6 + F10, LAD pseudo-HJ + curvature, RK4")
     elif name == "duct":
         spec = G.duct(256)
-        kw = dict(equation="HJ", gamma="LAD", eps=0.2, scheme="C6", rk="RK4", alpha_f=0.48)
-        desc = "3D square duct 256^3, C6 + F10, LAD pseudo-HJ, RK4"
+        kw = dict(equation="HJ", gamma="LAD", eps=0.2, scheme="C6", rk="RK4", alpha_f=0.495)
+        desc = ("3D square duct 256^3 on [0,1]^3, x periodic, walls y,z = 0,1; C6 + F10, "
+                "LAD pseudo-HJ (eps 0.2, C 0.1), RK4; 200 pseudo iterations from phi = 0 per step")
     elif name == "channel":
         spec = G.channel(129, 65)
         kw = dict(equation="HJ", gamma="LINEAR", eps=0.1, scheme="E4", rk="RK3", alpha_f=0.495)
@@ -88,21 +103,33 @@ def run_gpu(args, spec, kw, prec, profile=False):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     stats = []
+    prof_iters, prof_time = 0, None
     if profile:
-        # kernel timing pass: the same steps again, each launch bracketed by
-        # HIP events on the library's stream (direct launches, no graph)
-        L.wd_ctx_profile(s.ctx, True)
-        for _ in range(args.steps):
+        # kernel timing pass: some of the same steps again, each launch
+        # bracketed by HIP events on the library's stream (direct launches,
+        # no graph), and the same steps as one graph-replayed region
+        nprof = max(1, min(args.steps, args.profile_steps))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nprof):
             s.solve(prep, m, phi=phi, check=False)
+        torch.cuda.synchronize()
+        prof_time = time.perf_counter() - t0
+        L.wd_ctx_profile(s.ctx, True)
+        for _ in range(nprof):
+            prof_iters += s.solve(prep, m, phi=phi, check=False)["iters"]
         torch.cuda.synchronize()
         stats = L.wd_ctx_profile_read(s.ctx)
         L.wd_ctx_profile(s.ctx, False)
     res = phi.double().cpu().numpy()
     err = float(np.abs(res - spec.exact).max()) if spec.exact is not None else None
-    return dict(time=dt, iters=iters, statuses=statuses, err=err, stats=stats, tiles=tiles)
+    s.close()
+    return dict(time=dt, iters=iters, statuses=statuses, err=err, stats=stats, tiles=tiles,
+                prof_iters=prof_iters, prof_time=prof_time, stages=4 if kw["rk"] == "RK4" else 3)
 
 
-KERNEL_SOURCES = ("wd_common.h", "wd_line.h", "wd_line.hip", "wd_kernels.hip")
+KERNEL_SOURCES = ("wd_common.h", "wd_line.h", "wd_line.hip", "wd_kernels.hip", "wd_seg.h",
+                  "wd_seg.hip")
 
 
 def kernel_source_sha():
@@ -132,64 +159,124 @@ def run_copy(args):
             "copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "steps": args.steps}
 
 
+def _rocpd_files(d):
+    import glob
+    return sorted(glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True))
+
+
 def _pmc_rows(d):
+    """Counter rows of a rocprofv3 --pmc output directory (SQLite results
+    database or CSV): dicts with Dispatch_Id, Kernel_Name, Counter_Name,
+    Counter_Value (KiB for FETCH_SIZE / WRITE_SIZE)."""
     import csv
     import glob
-    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-    if not files:
-        raise SystemExit(f"no counter_collection.csv under {d}")
     rows = []
-    for f in files:
+    for f in _rocpd_files(d):
+        import sqlite3
+        con = sqlite3.connect(f)
+        for disp, name, ctr, val in con.execute(
+                "select dispatch_id, kernel_name, counter_name, value from counters_collection"):
+            rows.append({"Dispatch_Id": disp, "Kernel_Name": name, "Counter_Name": ctr,
+                         "Counter_Value": val})
+        con.close()
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
         rows += list(csv.DictReader(open(f)))
+    if not rows:
+        raise SystemExit(f"no counter rows under {d}")
     return rows
 
 
+def trace_summary(d):
+    """Markdown table of a rocprofv3 --kernel-trace --stats output directory
+    (SQLite results database): calls, average and total duration per
+    kernel."""
+    import sqlite3
+    files = _rocpd_files(d)
+    if not files:
+        raise SystemExit(f"no results database under {d}")
+    con = sqlite3.connect(files[0])
+    lines = ["| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    # the database's summary view gives durations in microseconds
+    for name, calls, tot, avg, pct in con.execute(
+            "select name, total_calls, total_duration, average, percentage from top_kernels"):
+        lines.append(f"| `{_kernel_base(name)[:60]}` | {calls} | {avg:.2f} | {tot / 1e3:.3f} "
+                     f"| {pct:.2f} |")
+    con.close()
+    return "\n".join(lines)
+
+
+def _kernel_base(name):
+    """'void wd::k_seg_cart<float, 32, false>(...)' -> 'k_seg_cart<float, 32, false>'."""
+    n = name.split("(")[0].replace("void ", "").strip()
+    return n.split("::")[-1] if "::" in n.split("<")[0] else n
+
+
 def _per_dispatch(rows, counter):
-    """{dispatch id: (kernel name, grid size, value)} for one counter."""
-    out = {}
+    """[(kernel, counter value in KiB)] per dispatch for one counter."""
+    per = {}
     for r in rows:
         if r["Counter_Name"] != counter:
             continue
         key = int(r["Dispatch_Id"])
-        name, grid, v = r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])
-        if key in out:
-            v += out[key][2]
-        out[key] = (name, grid, v)
+        nm, v = _kernel_base(r["Kernel_Name"]), float(r["Counter_Value"])
+        old = per.get(key, (nm, 0.0))
+        per[key] = (nm, old[1] + v)
+    return list(per.values())
+
+
+def _per_kernel(rows, counter):
+    """{kernel: [dispatches, summed counter value in KiB]} for one counter."""
+    out = {}
+    for nm, v in _per_dispatch(rows, counter):
+        e = out.setdefault(nm, [0, 0.0])
+        e[0] += 1
+        e[1] += v
     return out
 
 
+# kernels of one RK stage, and of the rest of a pseudo iteration
+STAGE_KERNELS = ("k_seg_cart<", "k_seg_cart_fin<", "k_cart_finish<", "k_cart<", "k_d1<",
+                 "k_d12<", "k_d2<", "k_uwadv<", "k_final<", "k_face<")
+ITER_KERNELS = STAGE_KERNELS + ("k_seg_lad<", "k_lad<", "k_seg_filter<", "k_filter<",
+                                "k_resid<", "k_finalize")
+
+
+def _in(name, group):
+    return any(name.startswith(k) for k in group)
+
+
 def pmc_summary(args):
-    """Turn four rocprofv3 --pmc runs (FETCH_SIZE / WRITE_SIZE of the
-    workload, the same of the copy calibration) into HBM bytes per launch of
-    the dominant kernel, written to profiles/traffic.json."""
+    """Turn four rocprofv3 --pmc runs (FETCH_SIZE / WRITE_SIZE of a run of
+    exactly --pmc-iters pseudo iterations of the workload, the same of the
+    copy calibration) into HBM bytes per RK stage and per iteration, written
+    to profiles/traffic.json."""
     wl, dfetch, dwrite, cfetch, cwrite = args.pmc_summary
     copy_bytes = float(1 << 30)
     factors = {}
     for d, ctr in ((cfetch, "FETCH_SIZE"), (cwrite, "WRITE_SIZE")):
-        disp = _per_dispatch(_pmc_rows(d), ctr)
-        big = [v for (name, grid, v) in disp.values() if "copy" in name.lower()]
+        # the largest copy dispatch is one 1 GiB device copy
+        big = [v for nm, v in _per_dispatch(_pmc_rows(d), ctr) if "copy" in nm.lower()]
         if not big:
             raise SystemExit(f"no copy kernel in {d}")
-        kib = max(big)
-        factors[ctr] = copy_bytes / (kib * 1024.0)
-    kname = args.pmc_kernel
-    res = {}
-    for d, ctr in ((dfetch, "FETCH_SIZE"), (dwrite, "WRITE_SIZE")):
-        disp = _per_dispatch(_pmc_rows(d), ctr)
-        mine = {k: v for k, v in disp.items() if f"::{kname}<" in v[0]}
-        if not mine:
-            raise SystemExit(f"no {kname} dispatches in {d}")
-        # the variant and launch shape of the last (timed) dispatches
-        last = mine[max(mine)]
-        sel = [v[2] for v in mine.values() if v[0] == last[0] and v[1] == last[1]]
-        res[ctr] = (last[0], last[1], len(sel), sum(sel) / len(sel) * 1024.0 * factors[ctr])
-    rec = {"kernel": kname, "variant": res["FETCH_SIZE"][0].split("(")[0],
-           "grid_size": res["FETCH_SIZE"][1], "dispatches": res["FETCH_SIZE"][2],
-           "fetch_bytes_per_launch": res["FETCH_SIZE"][3],
-           "write_bytes_per_launch": res["WRITE_SIZE"][3],
-           "hbm_bytes_per_launch": res["FETCH_SIZE"][3] + res["WRITE_SIZE"][3],
+        factors[ctr] = copy_bytes / (max(big) * 1024.0)
+    its, stages = args.pmc_iters, args.pmc_iters * args.pmc_stages
+    rec = {"iters": its, "stages": stages, "kernels": {},
            "copy_factor_fetch": factors["FETCH_SIZE"], "copy_factor_write": factors["WRITE_SIZE"],
            "source_sha256": kernel_source_sha()}
+    for d, ctr in ((dfetch, "FETCH_SIZE"), (dwrite, "WRITE_SIZE")):
+        per = _per_kernel(_pmc_rows(d), ctr)
+        key = "fetch" if ctr == "FETCH_SIZE" else "write"
+        for nm, (n, v) in per.items():
+            if not _in(nm, ITER_KERNELS):
+                continue
+            k = rec["kernels"].setdefault(nm, {"dispatches": n})
+            k[f"{key}_bytes_per_dispatch"] = v / n * 1024.0 * factors[ctr]
+        for grp, div in (("stage", stages), ("iteration", its)):
+            tot = sum(v for nm, (n, v) in per.items()
+                      if _in(nm, STAGE_KERNELS if grp == "stage" else ITER_KERNELS))
+            rec[f"{key}_bytes_per_{grp}"] = tot * 1024.0 * factors[ctr] / div
+    for grp in ("stage", "iteration"):
+        rec[f"hbm_bytes_per_{grp}"] = rec[f"fetch_bytes_per_{grp}"] + rec[f"write_bytes_per_{grp}"]
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     allrec = json.load(open(tpath)) if os.path.exists(tpath) else {}
     allrec[wl] = rec
@@ -199,60 +286,106 @@ def pmc_summary(args):
     return rec
 
 
-def roofline(stats, workload_key, timed_s=None):
-    """Dominant kernel (largest total time): compulsory bytes per launch over
-    its mean duration, against the 8 TB/s HBM peak.
+# Compulsory field accesses per grid point (bytes = accesses x value size):
+# each live RK state field read or written once per stage, the local step
+# stored once, one read and one write per filter direction, one read for
+# the residual; curvilinear 2D grids read their 4 metric fields per stage.
+def compulsory_accesses(ndim, uniform, rk4):
+    stage = 5 if rk4 else 11.0 / 3.0
+    met = 0 if uniform else ndim * ndim
+    stages = 4 if rk4 else 3
+    per_stage = stage + met
+    return per_stage, per_stage * stages + 2 * ndim + 1
+
+
+def roofline(r, spec, prec, workload_key):
+    """Achieved HBM bandwidth of the compulsory bytes of one RK stage (the
+    dominant unit of work) and of the whole pseudo iteration.
 
     The durations come from HIP events recorded around every launch of a
     second, non-graph pass over the same steps.  Each event pair also holds
-    the launch's dispatch latency, which the graph replay of the timed region
-    hides; that overhead per launch is taken as (sum of the event-timed
-    durations - timed region) / launches and removed, so the duration is the
-    one the kernel occupies inside the timed region."""
-    if not stats:
+    the launch's dispatch latency, which the graph replay of the timed
+    region hides; that overhead per launch is (sum of the event-timed
+    durations - the same steps timed as graph replays) / launches, and it is
+    removed from every launch."""
+    stats = r["stats"]
+    if not stats or not r["prof_iters"]:
         return None
-    k = max(stats, key=lambda r: r["total_ms"])
-    if k["alg_bytes"] <= 0:
-        return None
-    per_launch = k["alg_bytes"] / k["launches"]
-    raw_s = k["total_ms"] * 1e-3 / k["launches"]
-    over_s = 0.0
-    if timed_s:
-        tot_ms = sum(r["total_ms"] for r in stats)
-        nl = sum(r["launches"] for r in stats)
-        over_s = max(0.0, (tot_ms * 1e-3 - timed_s) / nl)
-    avg_s = raw_s - over_s
-    achieved = per_launch / avg_s / 1e9
+    S = 8.0 if prec == "fp64" else 4.0
+    acc_stage, acc_iter = compulsory_accesses(spec.ndim, spec.coords is None, r["stages"] == 4)
+    n_it = r["prof_iters"]
+    n_st = n_it * r["stages"]
+    tot_ms = sum(k["total_ms"] for k in stats)
+    nl = sum(k["launches"] for k in stats)
+    over_s = max(0.0, (tot_ms * 1e-3 - r["prof_time"]) / nl) if r["prof_time"] else 0.0
+    kern = {}
+    for k in stats:
+        avg = k["total_ms"] * 1e-3 / k["launches"] - over_s
+        kern[k["name"]] = {"launches": k["launches"], "avg_us": round(avg * 1e6, 2),
+                           "avg_us_events": round(k["total_ms"] * 1e3 / k["launches"], 2)}
+    base = lambda nm: nm.split("/")[0] + "<"          # library name -> kernel prefix
+    stage_names = [nm for nm in kern if _in(base(nm), STAGE_KERNELS)]
+    stage_s = sum(kern[nm]["avg_us"] * kern[nm]["launches"] for nm in stage_names) * 1e-6 / n_st
+    iter_s = sum(v["avg_us"] * v["launches"] for v in kern.values()) * 1e-6 / n_it
+    alg_stage = acc_stage * S * spec.npoints
+    alg_iter = acc_iter * S * spec.npoints
+    achieved = alg_stage / stage_s / 1e9
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tpath):
         rec = json.load(open(tpath)).get(workload_key, {})
-        if rec.get("kernel") == k["name"] and rec.get("source_sha256") == kernel_source_sha():
-            traffic = rec.get("hbm_bytes_per_launch")
-    return {"bound": "hbm", "kernel": k["name"], "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "alg_bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6,
-            "avg_launch_us_events": raw_s * 1e6, "event_overhead_us": over_s * 1e6,
-            "launches": k["launches"],
-            "kernels": {r["name"]: {"launches": r["launches"], "ms": round(r["total_ms"], 3),
-                                    "GBps": (r["alg_bytes"] / (r["total_ms"] * 1e-3) / 1e9
-                                             if r["total_ms"] > 0 else None)}
-                        for r in stats}}
+        if rec.get("source_sha256") == kernel_source_sha():
+            traffic = rec.get("hbm_bytes_per_stage")
+    out = {"bound": "hbm",
+           "kernel": "one RK stage: " + " + ".join(sorted(set(nm for nm in stage_names))),
+           "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+           "alg_bytes_per_launch": alg_stage, "alg_accesses_per_point": acc_stage,
+           "avg_launch_us": stage_s * 1e6,
+           "iteration": {"alg_accesses_per_point": acc_iter, "alg_bytes": alg_iter,
+                         "avg_us": iter_s * 1e6, "achieved": alg_iter / iter_s / 1e9,
+                         "frac": alg_iter / iter_s / 1e9 / HBM_PEAK_GBS},
+           "event_overhead_us": over_s * 1e6, "profiled_iters": n_it,
+           "kernels": kern}
+    if traffic:
+        out["hbm_GBps_measured_traffic"] = traffic / stage_s / 1e9
+        out["traffic_efficiency"] = alg_stage / traffic
+    return out
 
 
-def run_cpu_baseline(spec, kw, sample_iters):
+def cpu_info():
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
+
+
+def run_cpu_baseline(spec, kw, iters, threads):
+    """The FP64 oracle on the same grid and method for `iters` pseudo
+    iterations from phi = 0 on `threads` threads: (point-updates/s, seconds,
+    threads used)."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
     O.build(force=False)
+    used = O.set_threads(threads)
     m = O.make_method(equation={"HJ": O.HJ, "EIKONAL": O.EIKONAL, "POISSON": O.POISSON}[kw["equation"]],
                       gamma={"LAD": O.GAMMA_LAD, "LINEAR": O.GAMMA_LINEAR}[kw["gamma"]],
                       curvature=int(kw.get("curvature", False)), eps=kw["eps"], scheme=kw["scheme"],
                       rk={"RK4": O.RK4, "RK3": O.RK3}[kw["rk"]], alpha_f=kw["alpha_f"],
-                      fixed_iters=sample_iters)
+                      fixed_iters=iters)
     t0 = time.perf_counter()
     O.solve(spec, m)
     dt = time.perf_counter() - t0
-    return spec.npoints * sample_iters / dt, dt
+    return spec.npoints * iters / dt, dt, used
 
 
 ALPHA_F = 0.48   # filter coefficient of the batch and serving workloads
@@ -679,23 +812,38 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cylinder")
+    ap.add_argument("--workload", default="duct")
     ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--fixed-iters", type=int, default=0,
-                    help="time this many iterations per step instead of full solves")
-    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--fixed-iters", type=int, default=None,
+                    help="pseudo iterations per step (default: 200 for the duct, a full "
+                         "solve otherwise; 0 = full solve)")
+    ap.add_argument("--cpu-iters", type=int, default=2,
+                    help="oracle iterations of the all-core CPU baseline")
+    ap.add_argument("--cpu-iters-1t", type=int, default=1,
+                    help="oracle iterations of the one-thread CPU baseline")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the all-core baseline (0: OMP_NUM_THREADS, else all)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the cylinder O-grid secondary measurement")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default tile widths (no tuning before the timed steps)")
     ap.add_argument("--tiles", default=None,
                     help="tile widths per direction, e.g. 1,2 (skips the autotuner)")
     ap.add_argument("--no-profile", action="store_true",
                     help="no per-kernel event timing (roofline is then null)")
+    ap.add_argument("--profile-steps", type=int, default=2,
+                    help="steps of the per-launch event timing pass")
     ap.add_argument("--pmc-summary", nargs=5, metavar=("KEY", "FETCH_DIR", "WRITE_DIR",
                                                        "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
-                    help="derive HBM bytes per launch from rocprofv3 --pmc output")
-    ap.add_argument("--pmc-kernel", default="k_d2")
+                    help="derive HBM bytes per RK stage from rocprofv3 --pmc output")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="print the kernel table of a rocprofv3 --kernel-trace --stats run")
+    ap.add_argument("--pmc-iters", type=int, default=2,
+                    help="pseudo iterations in the counted runs")
+    ap.add_argument("--pmc-stages", type=int, default=4)
     ap.add_argument("--alpha-f", type=float, default=None,
                     help="filter coefficient (default: the workload's)")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -722,6 +870,9 @@ def main():
     if args.pmc_summary:
         print(json.dumps(pmc_summary(args)), flush=True)
         return
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary), flush=True)
+        return
     if args.workload == "copy":
         print(json.dumps(run_copy(args)), flush=True)
         return
@@ -740,10 +891,14 @@ def main():
     if args.workload == "moving":
         print(json.dumps(run_moving(args)), flush=True)
         return
+    if args.fixed_iters is None:
+        args.fixed_iters = 200 if args.workload == "duct" else 0
     spec, kw, desc = workload(args.workload)
     if args.alpha_f is not None:
         kw["alpha_f"] = args.alpha_f
     desc += f", alpha_f {kw['alpha_f']}"
+    print(f"[bench] {args.workload} {args.precision}: {args.warmup} + {args.steps} steps",
+          file=sys.stderr, flush=True)
     r = run_gpu(args, spec, kw, args.precision, profile=not args.no_profile)
     ups = spec.npoints * r["iters"] / r["time"]
     line = {
@@ -761,25 +916,52 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "points": spec.npoints,
                    "iters_per_step": r["iters"] / args.steps,
-                   "solves_per_s": args.steps / r["time"],
+                   "ms_per_iter": 1e3 * r["time"] / r["iters"],
                    "status": r["statuses"][-1], "linf_err_vs_exact": r["err"],
                    "tile_widths": r["tiles"],
                    "stop": stop_rule(args.precision, args.fixed_iters)},
     }
+    if not args.fixed_iters:
+        line["config"]["solves_per_s"] = args.steps / r["time"]
+    print(f"[bench] {ups:.4g} point-updates/s", file=sys.stderr, flush=True)
     if not args.no_fp64 and args.precision == "fp32":
-        r64 = run_gpu(args, spec, kw, "fp64")
+        a64 = argparse.Namespace(**vars(args))
+        a64.steps, a64.warmup = max(1, min(args.steps, args.fp64_steps)), 1
+        r64 = run_gpu(a64, spec, kw, "fp64")
         line["config"]["fp64"] = {"value": spec.npoints * r64["iters"] / r64["time"],
-                                  "ms_per_step": 1e3 * r64["time"] / args.steps,
-                                  "iters_per_step": r64["iters"] / args.steps,
+                                  "steps": a64.steps,
+                                  "ms_per_iter": 1e3 * r64["time"] / r64["iters"],
+                                  "iters_per_step": r64["iters"] / a64.steps,
                                   "linf_err_vs_exact": r64["err"],
                                   "status": r64["statuses"][-1]}
-    line["roofline"] = roofline(r["stats"], f"{args.workload}-{args.precision}", r["time"])
+        print("[bench] fp64 leg done", file=sys.stderr, flush=True)
+    if args.workload == "duct" and not args.no_secondary:
+        cspec, ckw, cdesc = workload("cylinder")
+        ca = argparse.Namespace(**vars(args))
+        ca.steps, ca.warmup, ca.fixed_iters = 3, 1, 0
+        rc = run_gpu(ca, cspec, ckw, "fp32")
+        line["config"]["cylinder"] = {
+            "workload": cdesc + ", alpha_f 0.495; one step = one full solve from phi = 0",
+            "value": cspec.npoints * rc["iters"] / rc["time"], "unit": "point-updates/s",
+            "solves_per_s": ca.steps / rc["time"], "ms_per_solve": 1e3 * rc["time"] / ca.steps,
+            "iters_per_solve": rc["iters"] / ca.steps, "status": rc["statuses"][-1],
+            "linf_err_vs_exact": rc["err"], "stop": stop_rule("fp32", 0)}
+        print("[bench] cylinder leg done", file=sys.stderr, flush=True)
+    line["roofline"] = roofline(r, spec, args.precision, f"{args.workload}-{args.precision}")
     if not args.no_cpu:
-        v, dt = run_cpu_baseline(spec, kw, args.cpu_iters)
-        line["cpu_baseline"] = {"value": v, "unit": "point-updates/s", "cores": 1,
-                                "kind": "oracle",
-                                "sample": f"{args.cpu_iters} pseudo iterations of the same "
-                                          f"workload from phi = 0 ({dt:.1f} s, FP64, 1 thread)"}
+        model, ncpu, avail = cpu_info()
+        threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS") or 0) or avail
+        v, dt, used = run_cpu_baseline(spec, kw, args.cpu_iters, threads)
+        print(f"[bench] oracle, {used} threads: {dt:.1f} s", file=sys.stderr, flush=True)
+        v1, dt1, _ = run_cpu_baseline(spec, kw, args.cpu_iters_1t, 1)
+        print(f"[bench] oracle, 1 thread: {dt1:.1f} s", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = {
+            "value": v, "unit": "point-updates/s", "cores": used, "kind": "oracle",
+            "sample": f"{args.cpu_iters} pseudo iterations of the same workload (full grid) "
+                      f"from phi = 0, FP64, {used} threads: {dt:.1f} s",
+            "one_thread": {"value": v1, "seconds": dt1,
+                           "sample": f"{args.cpu_iters_1t} pseudo iteration(s), full grid"},
+            "host": {"cpu_model": model, "nproc": ncpu, "cpus_available": avail}}
     print(json.dumps(line), flush=True)
 
 

@@ -208,7 +208,9 @@ int wd_solve_batched(wd_ctx *ctx, int n, const wd_grid_desc *descs,
  * workgroup tile) and keep the fastest in the context's cache, keyed by the
  * grid shape, direction and precision; later plans of that shape use it.
  * Results do not depend on the tile widths (each point's arithmetic is the
- * same), only the speed does.
+ * same), only the speed does.  A grid that the segmented passes serve
+ * (wd_ctx_set_segmented) has fixed tiles: nothing is timed, and widths
+ * receives the lines per tile of those passes.
  *   phi   : device scratch field of the grid (overwritten).
  *   ws    : device workspace of at least wd_workspace_bytes.
  *   widths: host, receives the chosen width per direction (may be NULL). */

@@ -27,12 +27,13 @@ SCHEMES = {"E2": E2, "E4": E4, "E6": E6, "C4": C4, "C6": C6, "UW": UW}
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    """Compile the oracle with gcc (plain -O2, no fast-math; OpenMP shares
+    the independent line and point loops among threads)."""
     src = os.path.join(HERE, "wd_oracle.c")
     if force or not os.path.exists(LIB_PATH) or \
             os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
         tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c99",
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
                                "-o", tmp, src, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -74,6 +75,7 @@ def lib():
                                dp, dp, dp, dp, dp, dp, dp]
         L.wdo_lad_field.argtypes = [C.POINTER(_Grid), C.POINTER(_Method), dp, dp, dp]
         L.wdo_gauss_line.argtypes = [C.c_int, C.c_int, dp, dp]
+        L.wdo_set_threads.argtypes = [C.c_int]
         L.wdo_apply_bc.argtypes = [C.POINTER(_Grid), dp]
         L.wdo_apply_bc.restype = None
         L.wdo_solve.argtypes = [C.POINTER(_Grid), C.POINTER(_Method), dp,
@@ -160,6 +162,11 @@ def filter_line(f, alpha_f, periodic=False):
     if rc:
         raise ValueError("wdo_filter_line failed")
     return out
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's grid-wide loops (0: keep); the count in force."""
+    return int(lib().wdo_set_threads(int(n)))
 
 
 def gauss_line(f, periodic=False):

@@ -31,6 +31,25 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the grid-wide loops.  Only loops whose iterations are
+ * independent (whole grid lines, single points) are shared out, and each
+ * result is computed by the same operations in the same order whatever the
+ * thread count; the reductions over the grid stay sequential. */
+int wdo_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* Scheme coefficients.  Interior relation (index space):
@@ -359,16 +378,24 @@ static int deriv_dir(const wdo_grid *g, int l, int scheme, double jump,
     long s = stride_of(g, l);
     long nl = npoints(g) / n;
     int periodic = g->bc[l][0] == WDO_PERIODIC;
-    double *line = malloc(sizeof(double) * n);
-    double *dl = malloc(sizeof(double) * n);
     int rc = 0;
-    for (long k = 0; k < nl && rc == 0; ++k) {
-        long base = line_base(g, l, k);
-        for (int i = 0; i < n; ++i) line[i] = f[base + i * s];
-        rc = wdo_deriv_line(n, periodic, scheme, jump, line, dl);
-        for (int i = 0; i < n; ++i) out[base + i * s] = dl[i];
+#pragma omp parallel
+    {
+        double *line = malloc(sizeof(double) * n);
+        double *dl = malloc(sizeof(double) * n);
+#pragma omp for schedule(static)
+        for (long k = 0; k < nl; ++k) {
+            long base = line_base(g, l, k);
+            for (int i = 0; i < n; ++i) line[i] = f[base + i * s];
+            if (wdo_deriv_line(n, periodic, scheme, jump, line, dl)) {
+#pragma omp atomic write
+                rc = -1;
+                continue;
+            }
+            for (int i = 0; i < n; ++i) out[base + i * s] = dl[i];
+        }
+        free(line); free(dl);
     }
-    free(line); free(dl);
     return rc;
 }
 
@@ -378,16 +405,24 @@ static int filter_dir(const wdo_grid *g, int l, double af, double *f)
     long s = stride_of(g, l);
     long nl = npoints(g) / n;
     int periodic = g->bc[l][0] == WDO_PERIODIC;
-    double *line = malloc(sizeof(double) * n);
-    double *fl = malloc(sizeof(double) * n);
     int rc = 0;
-    for (long k = 0; k < nl && rc == 0; ++k) {
-        long base = line_base(g, l, k);
-        for (int i = 0; i < n; ++i) line[i] = f[base + i * s];
-        rc = wdo_filter_line(n, periodic, af, line, fl);
-        for (int i = 0; i < n; ++i) f[base + i * s] = fl[i];
+#pragma omp parallel
+    {
+        double *line = malloc(sizeof(double) * n);
+        double *fl = malloc(sizeof(double) * n);
+#pragma omp for schedule(static)
+        for (long k = 0; k < nl; ++k) {
+            long base = line_base(g, l, k);
+            for (int i = 0; i < n; ++i) line[i] = f[base + i * s];
+            if (wdo_filter_line(n, periodic, af, line, fl)) {
+#pragma omp atomic write
+                rc = -1;
+                continue;
+            }
+            for (int i = 0; i < n; ++i) f[base + i * s] = fl[i];
+        }
+        free(line); free(fl);
     }
-    free(line); free(fl);
     return rc;
 }
 
@@ -413,6 +448,7 @@ int wdo_metrics(const wdo_grid *g, int scheme, double *met)
                                g->coords + m * N, J + (m * d + l) * N);
             if (rc) { free(J); return rc; }
         }
+#pragma omp parallel for schedule(static)
     for (long q = 0; q < N; ++q) {
         double A[3][3], Inv[3][3];
         for (int m = 0; m < d; ++m)
@@ -468,8 +504,9 @@ static int on_wall(const wdo_grid *g, const int *idx)
 void wdo_apply_bc(const wdo_grid *g, double *phi)
 {
     long N = npoints(g);
-    int idx[3];
+#pragma omp parallel for schedule(static)
     for (long q = 0; q < N; ++q) {
+        int idx[3];
         index_of(g, q, idx);
         if (on_wall(g, idx) || (g->mask && g->mask[q]))
             phi[q] = 0.0;
@@ -481,7 +518,9 @@ void wdo_apply_bc(const wdo_grid *g, double *phi)
             long s = stride_of(g, l);
             int target = side == 0 ? 0 : g->n[l] - 1;
             long inward = side == 0 ? s : -s;
+#pragma omp parallel for schedule(static)
             for (long q = 0; q < N; ++q) {
+                int idx[3];
                 index_of(g, q, idx);
                 if (idx[l] != target) continue;
                 if (on_wall(g, idx) || (g->mask && g->mask[q])) continue;
@@ -506,6 +545,7 @@ static void fourth_diff_dir(const wdo_grid *g, int l, const double *f,
     long s = stride_of(g, l);
     long nl = npoints(g) / n;
     int periodic = g->bc[l][0] == WDO_PERIODIC;
+#pragma omp parallel for schedule(static)
     for (long k = 0; k < nl; ++k) {
         long base = line_base(g, l, k);
         for (int i = 0; i < n; ++i) {
@@ -537,6 +577,7 @@ static void gauss_dir(const wdo_grid *g, int l, double *f, double *tmp)
     long s = stride_of(g, l);
     long nl = npoints(g) / n;
     int periodic = g->bc[l][0] == WDO_PERIODIC;
+#pragma omp parallel for schedule(static)
     for (long k = 0; k < nl; ++k) {
         long base = line_base(g, l, k);
         for (int i = 0; i < n; ++i) {
@@ -588,6 +629,7 @@ int wdo_lad_field(const wdo_grid *g, const wdo_method *m, const double *met,
     for (long q = 0; q < N; ++q) out[q] = 0.0;
     for (int l = 0; l < d; ++l) {
         fourth_diff_dir(g, l, phi, tmp);
+#pragma omp parallel for schedule(static)
         for (long q = 0; q < N; ++q) {
             double s2 = 0.0;
             for (int mm = 0; mm < d; ++mm) {
@@ -598,6 +640,7 @@ int wdo_lad_field(const wdo_grid *g, const wdo_method *m, const double *met,
             out[q] += s2 * s2 * tmp[q] * dx * dx * dx;
         }
     }
+#pragma omp parallel for schedule(static)
     for (long q = 0; q < N; ++q) out[q] = m->C * fabs(out[q]);
     if (!m->lad_raw)
         for (int l = 0; l < d; ++l) gauss_dir(g, l, out, tmp);
@@ -624,6 +667,7 @@ static void uw_advection(const wdo_grid *g, const wdo_method *m, const double *m
 {
     int d = g->ndim;
     long N = npoints(g);
+#pragma omp parallel for schedule(static)
     for (long q = 0; q < N; ++q) {
         int idx[3];
         index_of(g, q, idx);
@@ -692,12 +736,14 @@ int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
     for (int l = 0; l < d && !rc; ++l)
         rc = deriv_dir(g, l, m->scheme, 0.0, phi, F + l * N);
     for (int mm = 0; mm < d; ++mm)
+#pragma omp parallel for schedule(static)
         for (long q = 0; q < N; ++q) {
             double u = 0.0;
             for (int l = 0; l < d; ++l)
                 u += met[(l * d + mm) * N + q] * F[l * N + q];
             U[mm * N + q] = u;
         }
+#pragma omp parallel for schedule(static)
     for (long q = 0; q < N; ++q) {
         double s = 0.0;
         for (int mm = 0; mm < d; ++mm) s += U[mm * N + q] * U[mm * N + q];
@@ -721,16 +767,19 @@ int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
         for (int mm = 0; mm < d && !rc; ++mm)
             for (int l = 0; l < d && !rc; ++l) {
                 rc = deriv_dir(g, l, m->scheme, 0.0, U + mm * N, tmp);
+#pragma omp parallel for schedule(static)
                 for (long q = 0; q < N; ++q)
                     L[q] += met[(l * d + mm) * N + q] * tmp[q];
             }
     if (curv) {
         double *nv = malloc(sizeof(double) * N);
         for (int mm = 0; mm < d && !rc; ++mm) {
+#pragma omp parallel for schedule(static)
             for (long q = 0; q < N; ++q)
                 nv[q] = U[mm * N + q] / (G[q] + m->eps0);
             for (int l = 0; l < d && !rc; ++l) {
                 rc = deriv_dir(g, l, m->scheme, 0.0, nv, tmp);
+#pragma omp parallel for schedule(static)
                 for (long q = 0; q < N; ++q)
                     K[q] += met[(l * d + mm) * N + q] * tmp[q];
             }
@@ -748,6 +797,7 @@ int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
             wdo_lad_field(g, m, met, phi, S);
             lad = S;
         }
+#pragma omp parallel for schedule(static)
         for (long q = 0; q < N; ++q) {
             double gq = m->eps * phi[q];
             if (m->gamma == WDO_GAMMA_LAD && lad[q] < gq) gq = lad[q];
@@ -758,6 +808,7 @@ int wdo_eval(const wdo_grid *g, const wdo_method *m, const double *met,
     double kp = kprime_of(m->scheme);
     /* the upwind term's largest modified wavenumber: |1 - e^{-i w}| <= 2 */
     double kadv = m->scheme == WDO_UW ? 2.0 : kp;
+#pragma omp parallel for schedule(static)
     for (long q = 0; q < N; ++q) {
         double g2 = 0.0;
         for (int mm = 0; mm < d; ++mm) g2 += U[mm * N + q] * U[mm * N + q];
@@ -842,28 +893,35 @@ int wdo_solve(const wdo_grid *g, const wdo_method *m, double *phi, int warm,
             wdo_lad_field(g, m, met, pn, lad);
         if (m->rk == WDO_RK4) {
             wdo_eval(g, m, met, pn, lad, k1, NULL, NULL, NULL, NULL, dt);
+#pragma omp parallel for schedule(static)
             for (long q = 0; q < N; ++q) p[q] = pn[q] + dt[q] / 2.0 * k1[q];
             wdo_apply_bc(g, p);
             wdo_eval(g, m, met, p, lad, k2, NULL, NULL, NULL, NULL, NULL);
+#pragma omp parallel for schedule(static)
             for (long q = 0; q < N; ++q) p[q] = pn[q] + dt[q] / 2.0 * k2[q];
             wdo_apply_bc(g, p);
             wdo_eval(g, m, met, p, lad, k3, NULL, NULL, NULL, NULL, NULL);
+#pragma omp parallel for schedule(static)
             for (long q = 0; q < N; ++q) p[q] = pn[q] + dt[q] * k3[q];
             wdo_apply_bc(g, p);
             wdo_eval(g, m, met, p, lad, k4, NULL, NULL, NULL, NULL, NULL);
+#pragma omp parallel for schedule(static)
             for (long q = 0; q < N; ++q)
                 phi[q] = pn[q] + dt[q] / 6.0 * (k1[q] + 2.0 * k2[q]
                                                 + 2.0 * k3[q] + k4[q]);
             wdo_apply_bc(g, phi);
         } else {
             wdo_eval(g, m, met, pn, lad, k1, NULL, NULL, NULL, NULL, dt);
+#pragma omp parallel for schedule(static)
             for (long q = 0; q < N; ++q) p[q] = pn[q] + dt[q] * k1[q];
             wdo_apply_bc(g, p);
             wdo_eval(g, m, met, p, lad, k2, NULL, NULL, NULL, NULL, NULL);
+#pragma omp parallel for schedule(static)
             for (long q = 0; q < N; ++q)
                 k3[q] = 0.75 * pn[q] + 0.25 * (p[q] + dt[q] * k2[q]);
             wdo_apply_bc(g, k3);
             wdo_eval(g, m, met, k3, lad, k2, NULL, NULL, NULL, NULL, NULL);
+#pragma omp parallel for schedule(static)
             for (long q = 0; q < N; ++q)
                 phi[q] = pn[q] / 3.0 + 2.0 / 3.0 * (k3[q] + dt[q] * k2[q]);
             wdo_apply_bc(g, phi);

@@ -95,6 +95,10 @@ int wdo_lad_field(const wdo_grid *g, const wdo_method *m, const double *met,
  * (ends clamped unless periodic); n >= 9. */
 int wdo_gauss_line(int n, int periodic, const double *f, double *out);
 
+/* Threads shared among the grid-wide loops (n <= 0: keep the current
+ * count); returns the count now in force.  Results do not depend on it. */
+int wdo_set_threads(int n);
+
 /* Boundary conditions and solid mask, in place. */
 void wdo_apply_bc(const wdo_grid *g, double *phi);
 

@@ -1251,7 +1251,22 @@ void issue_list(wd_ctx *ctx, const Plan &P, int li, int stage, hipStream_t s)
     if (L.count == 0) return;
     const int arg = (L.kind == PASS_FACE || L.kind == PASS_INIT) ? L.arg : stage;
     PendingLaunch pl;
-    if (ctx->profile) prof_begin(ctx, pl, kind_name(L.kind), launch_bytes(P, L, stage), s);
+    if (ctx->profile) {
+        // line passes are timed per direction (and LAD phase)
+        std::string name = kind_name(L.kind);
+        switch (L.kind) {
+        case PASS_LAD: case PASS_SLAD:
+            name += "/p" + std::to_string(stage);
+            [[fallthrough]];
+        case PASS_CART: case PASS_D1: case PASS_D2: case PASS_FILTER: case PASS_SCART:
+        case PASS_SCART_LAST: case PASS_SFILTER:
+            name += "/d" + std::to_string(L.l);
+            break;
+        default:
+            break;
+        }
+        prof_begin(ctx, pl, name.c_str(), launch_bytes(P, L, stage), s);
+    }
     if (L.kind == PASS_SCART || L.kind == PASS_SCART_LAST || L.kind == PASS_SFILTER ||
         L.kind == PASS_SLAD) {
         size_t lds = 0;
@@ -1539,7 +1554,14 @@ int solve_plan(wd_ctx *ctx, Plan &P, void *const *aux, double *const *hists, int
     if (rc) return rc;
     issue_init(ctx, P, s);
     std::vector<GridState> states;
-    rc = run_plan(ctx, P, ctx->graph_iters, states);
+    // iterations per graph: at most graph_iters, spread evenly over the
+    // rounds the longest grid may need, so a run to max_iter issues few
+    // no-op iterations after the last grid stops
+    int maxit = 1;
+    for (int i = 0; i < P.n; ++i) maxit = std::max(maxit, P.grids[i].max_iter);
+    const int gi = std::max(1, ctx->graph_iters);
+    const int rounds = (maxit + gi - 1) / gi;
+    rc = run_plan(ctx, P, (maxit + rounds - 1) / rounds, states);
     if (rc) return rc;
     int worst = WD_OK;
     for (int i = 0; i < P.n; ++i) {
@@ -1903,6 +1925,14 @@ int wd_autotune(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method, 
             Plan P;
             rc = plan_batch(ctx, 1, desc, &m, phis, ws, ws_bytes, P);
             if (rc) break;
+            if (P.grids[0].seg) {
+                // the segmented passes fix their own tiles (whole lines per
+                // wave): nothing to tune along any direction
+                for (int k = 0; k < d.ndim; ++k)
+                    if (widths) widths[k] = P.grids[0].sgeo[k].W;
+                l = d.ndim;
+                break;
+            }
             rc = upload_plan(ctx, P, s);
             if (rc) break;
             issue_init(ctx, P, s);
@@ -1924,6 +1954,7 @@ int wd_autotune(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method, 
                 best_w = w;
             }
         }
+        if (l >= d.ndim) break;
         ctx->tune[key] = best_w;
         if (widths) widths[l] = best_w;
     }

@@ -679,3 +679,35 @@ def test_metrics_3d_affine_grid(oracle, scheme, periodic0):
     for l in range(3):
         for mm in range(3):
             assert np.abs(met[3 * l + mm] - inv[l, mm]).max() < 1e-11 * np.abs(inv).max()
+
+
+@pytest.mark.parametrize("case", ["duct_lad", "ogrid_curv", "star_uw", "affine_poisson"])
+def test_thread_count_does_not_change_results(oracle, case):
+    """The oracle's grid-wide loops are shared among threads line by line
+    and point by point; every value must come out bit-identical with one
+    thread and with several (fields and the FP64 change history)."""
+    if case == "duct_lad":
+        spec = G.duct(17, nx=12)
+        m = oracle.make_method(equation=oracle.HJ, gamma=oracle.GAMMA_LAD, eps=0.2,
+                               scheme="C6", alpha_f=0.48, fixed_iters=6)
+    elif case == "ogrid_curv":
+        spec = G.cylinder(32, 24, rout=5.0, dr1=1e-2, ratio=1.1)
+        m = oracle.make_method(equation=oracle.HJ, gamma=oracle.GAMMA_LAD, curvature=1,
+                               eps=0.2, scheme="E6", rk=oracle.RK3, fixed_iters=6)
+    elif case == "star_uw":
+        spec = G.star_grain(40)
+        m = oracle.make_method(equation=oracle.EIKONAL, scheme="UW", fixed_iters=6)
+    else:
+        spec, _ = _affine3d()
+        m = oracle.make_method(equation=oracle.POISSON, scheme="C4", fixed_iters=6)
+    before = oracle.set_threads(0)
+    try:
+        oracle.set_threads(1)
+        ref, st1, it1, h1 = oracle.solve(spec, m)
+        oracle.set_threads(4)
+        par, st4, it4, h4 = oracle.solve(spec, m)
+    finally:
+        oracle.set_threads(before)
+    assert (st1, it1) == (st4, it4)
+    assert np.array_equal(ref, par)
+    assert np.array_equal(h1, h4)
