@@ -635,7 +635,7 @@ def run_burnback(args):
 
 
 def run_moving(args):
-    """Moving walls (the unsteady cases of Sec. 6), FP32, E4 LAD pseudo-HJ
+    """Moving walls (the unsteady cases of Sec. 5.5), FP32, E4 LAD pseudo-HJ
     at eps 0.15 and sigma 0.5, stopped at max change <= 1e-5: a piston in
     an annular bore (128 x 49 x 97 O-grid, half a stroke, h 1.4 -> 0.6 in
     24 physical steps) and a cube bouncing between a floor and a ceiling

@@ -46,6 +46,9 @@ extern "C" {
 #define WD_ERR_HIP (-5)        /* HIP runtime error, text in wd_last_error  */
 #define WD_ERR_CANCELLED (-6)
 #define WD_ERR_NOT_FOUND (-7)
+#define WD_ERR_WARM_RUNAWAY (-8) /* warm start abandoned by the runaway check
+                                  (wd_method.warm_probe); phi holds the
+                                  abandoned field: solve again cold        */
 
 /* ---- enumerations ---------------------------------------------------- */
 /* Face conditions (Sec. 3.5): WALL is the Dirichlet phi = 0 of Eq. eq7;
@@ -114,12 +117,18 @@ typedef struct wd_method {
                              convergence reductions are always FP64         */
     int warm_start;       /* 1: phi holds the initial guess (e.g. the
                              previous physical time step's field when walls
-                             move, Sec. 6); wall and solid points are set to
-                             zero first.  A guess that jumps by much more
-                             than the spacing beside a wall can undershoot
-                             below zero and run away (Gamma is 0 there):
-                             callers watch for phi < 0 and restart cold.
-                             0: phi = 0                                     */
+                             move, Sec. 5.5); wall and solid points are set
+                             to zero first.  0: phi = 0                     */
+    int warm_probe;       /* runaway check of a warm start: a guess that
+                             jumps by much more than the spacing beside a
+                             wall can make the central march undershoot
+                             below zero there, where Gamma = max(0, eps phi)
+                             vanishes and nothing damps it.  After this many
+                             iterations the device compares the field's
+                             minimum with its largest magnitude (FP64, after
+                             the filter); below -0.1 of it the solve stops
+                             with WD_ERR_WARM_RUNAWAY.  0 disables; ignored
+                             for cold starts                                 */
 } wd_method;
 
 typedef struct wd_ctx wd_ctx;
@@ -133,7 +142,8 @@ const char *wd_last_error(void);
 
 /* Fill *m with the defaults: HJ, LAD, no curvature, eps 0.2, C 0.1,
  * nu0 1e-3, eps0 1e-6, C6, filter on, alpha_f 0.48, RK4, sigma 1,
- * tol 1e-10, max_iter 100000, stall_window 0, FP64, cold start. */
+ * tol 1e-10, max_iter 100000, stall_window 0, FP64, cold start,
+ * warm_probe 300. */
 int wd_method_default(wd_method *m);
 
 /* Create a context on HIP device `device`: owns the line-operator tables
@@ -159,6 +169,8 @@ int wd_workspace_bytes(wd_ctx *ctx, int n_grids, const wd_grid_desc *descs,
                        const wd_method *methods, size_t *bytes);
 
 /* Plain per-grid solve (Sec. 3.3-3.5 pseudo-time march to steady state).
+ * A warm start that the runaway check stops returns WD_ERR_WARM_RUNAWAY
+ * (the caller solves again cold; the server does that itself).
  *   phi      : device, grid layout, method precision.  Initial guess when
  *              warm_start is set (else overwritten with zero); on return the
  *              wall distance.  For WD_EQ_POISSON the converted distance of
@@ -352,9 +364,10 @@ int wd_server_create(wd_ctx *ctx, size_t budget_bytes, int max_slots,
  * phi (device) must stay valid until the request finishes.  session >= 0
  * serialises requests of one session in submission order (an unsteady
  * sequence re-solved with warm_start from its previous field); -1 = none.
- * A warm start far from the new walls can run away below zero (see
- * wd_method.warm_start): such a request ends WD_ERR_DIVERGED or
- * WD_NOT_CONVERGED, and the caller resubmits it cold.
+ * A warm request that the runaway check stops (wd_method.warm_probe) is
+ * solved again from zero in its slot: its result is the cold solve's, its
+ * iteration count includes the abandoned ones, and wd_server_stats counts
+ * it among the restarts.
  * hist_cap (>= 0) FP64 history pairs are kept for wd_server_history.
  * *req_id receives the request id. */
 int wd_server_submit(wd_server *srv, const wd_grid_desc *desc,
@@ -380,9 +393,10 @@ int wd_server_history(wd_server *srv, long long req_id, double *hist, int cap,
 int wd_server_cancel(wd_server *srv, long long req_id);
 
 /* Counters: requests done, iterations advanced, peak arena bytes, peak
- * concurrent grids.  Any pointer may be NULL. */
+ * concurrent grids, warm requests restarted cold by the runaway check.
+ * Any pointer may be NULL. */
 int wd_server_stats(wd_server *srv, long long *done, long long *iterations,
-                    size_t *peak_bytes, int *peak_active);
+                    size_t *peak_bytes, int *peak_active, long long *restarts);
 
 /* Stop the thread (running requests are cancelled) and free the arena. */
 int wd_server_destroy(wd_server *srv);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libwd.so")
 WD_OK, WD_NOT_CONVERGED, WD_STAGNATED, WD_PENDING = 0, 1, 2, 3
 WD_ERR_INVALID_ARG, WD_ERR_UNSUPPORTED, WD_ERR_DIVERGED = -1, -2, -3
 WD_ERR_NO_MEMORY, WD_ERR_HIP, WD_ERR_CANCELLED, WD_ERR_NOT_FOUND = -4, -5, -6, -7
+WD_ERR_WARM_RUNAWAY = -8
 
 WD_BC_WALL, WD_BC_NEUMANN, WD_BC_OUTFLOW, WD_BC_PERIODIC = 0, 1, 2, 3
 WD_METRIC_UNIFORM, WD_METRIC_FIELDS = 0, 1
@@ -41,7 +42,7 @@ class wd_method(C.Structure):
                 ("eps0", C.c_double), ("scheme", C.c_int), ("filter", C.c_int),
                 ("alpha_f", C.c_double), ("rk", C.c_int), ("sigma", C.c_double),
                 ("tol", C.c_double), ("max_iter", C.c_int), ("stall_window", C.c_int),
-                ("precision", C.c_int), ("warm_start", C.c_int)]
+                ("precision", C.c_int), ("warm_start", C.c_int), ("warm_probe", C.c_int)]
 
 
 class wd_kernel_stat(C.Structure):
@@ -107,7 +108,8 @@ def lib():
         "wd_server_wait": ([vp, C.c_longlong, C.c_double], C.c_int),
         "wd_server_history": ([vp, C.c_longlong, dp, C.c_int, ip], C.c_int),
         "wd_server_cancel": ([vp, C.c_longlong], C.c_int),
-        "wd_server_stats": ([vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong), szp, ip],
+        "wd_server_stats": ([vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong), szp, ip,
+                             C.POINTER(C.c_longlong)],
                             C.c_int),
         "wd_server_destroy": ([vp], C.c_int),
     }
@@ -361,12 +363,13 @@ def wd_server_cancel(srv, req_id) -> int:
 
 
 def wd_server_stats(srv):
-    d, it, act = C.c_longlong(0), C.c_longlong(0), C.c_int(0)
+    d, it, act, rs = C.c_longlong(0), C.c_longlong(0), C.c_int(0), C.c_longlong(0)
     pk = C.c_size_t(0)
-    _check(lib().wd_server_stats(srv, C.byref(d), C.byref(it), C.byref(pk), C.byref(act)),
+    _check(lib().wd_server_stats(srv, C.byref(d), C.byref(it), C.byref(pk), C.byref(act),
+                                 C.byref(rs)),
            "wd_server_stats", ok=(WD_OK,))
     return {"done": d.value, "iterations": it.value, "peak_bytes": pk.value,
-            "peak_active": act.value}
+            "peak_active": act.value, "restarts": rs.value}
 
 
 def wd_server_destroy(srv) -> None:

@@ -29,7 +29,7 @@ def _torch():
 def make_method(equation="HJ", gamma="LAD", curvature=False, eps=0.2, c_lad=0.1,
                 nu0=1e-3, eps0=1e-6, scheme="C6", filter=True, alpha_f=0.48, rk="RK4",
                 sigma=1.0, tol=1e-10, max_iter=100000, stall_window=0, precision="fp64",
-                warm_start=False) -> L.wd_method:
+                warm_start=False, warm_probe=300) -> L.wd_method:
     m = L.wd_method()
     m.equation = EQUATIONS[equation] if isinstance(equation, str) else equation
     m.gamma = GAMMAS[gamma] if isinstance(gamma, str) else gamma
@@ -42,6 +42,7 @@ def make_method(equation="HJ", gamma="LAD", curvature=False, eps=0.2, c_lad=0.1,
     m.sigma, m.tol, m.max_iter, m.stall_window = sigma, tol, max_iter, stall_window
     m.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
     m.warm_start = int(bool(warm_start))
+    m.warm_probe = int(warm_probe)
     return m
 
 
@@ -154,7 +155,7 @@ class Solver:
         return L.wd_tune_get(self.ctx, prep.desc, PRECISIONS["fp64" if prep.dtype == self.torch.float64
                                                              else "fp32"])
 
-    # -- moving walls (the unsteady cases of Sec. 6) --------------------
+    # -- moving walls (the unsteady cases of Sec. 5.5) ------------------
     def solve_sequence(self, specs, method: L.wd_method, scheme="E4", precision="fp64",
                        warm=True, on_step=None, probe=300):
         """Wall distance while the walls move: one pseudo-time solve per
@@ -167,41 +168,29 @@ class Solver:
         result's field is overwritten by the next step).
 
         A warm estimate far from the new walls (a wall that moved many
-        cells in one step) can start a runaway: the central scheme
-        undershoots below zero beside a new wall, where Gamma = 0 leaves
-        only 1 - |grad phi|^2, which drives the point further down.  So a
-        warm step first runs `probe` pseudo-steps; a field that has gone
-        below -0.1 of its maximum there (a transient undershoot beside a
-        new wall is a small fraction of that and recovers), or a warm solve
-        that does not end converged or stagnated, is solved again from
-        zero.  Returns the list of (status, iterations, restarted) --
-        iterations include a failed warm attempt -- and the last step's
-        result."""
+        cells in one step) can start a runaway below zero beside a new
+        wall; the library's runaway check (wd_method.warm_probe = probe
+        iterations) then stops the solve with WD_ERR_WARM_RUNAWAY, and a
+        warm solve that ends so, or that does not end converged or
+        stagnated, is solved again from zero.  Returns the list of
+        (status, iterations, restarted) -- iterations include a failed
+        warm attempt -- and the last step's result."""
         torch = self.torch
         phi, out, steps = None, None, []
         for k, spec in enumerate(specs):
             prep = self.prepare(spec, scheme, precision)
             m = L.wd_method.from_buffer_copy(method)
             m.warm_start = int(bool(warm) and phi is not None)
+            m.warm_probe = int(probe)
             if phi is None or tuple(phi.shape) != tuple(spec.shape):
                 if m.warm_start:
                     raise ValueError("solve_sequence: grid dimensions changed between steps")
                 phi = torch.zeros(spec.shape, dtype=prep.dtype, device=self.device)
             restarted, spent = False, 0
             if m.warm_start:
-                first = L.wd_method.from_buffer_copy(m)
-                first.max_iter = min(probe, m.max_iter)
-                out = self.solve(prep, first, phi=phi, hist_cap=1, check=False)
+                out = self.solve(prep, m, phi=phi, hist_cap=1, check=False)
                 spent = out["iters"]
-                bad = out["status"] == L.WD_ERR_DIVERGED or bool(
-                    phi.min() < -0.1 * phi.abs().max())
-                if not bad and out["status"] == L.WD_NOT_CONVERGED and spent < m.max_iter:
-                    rest = L.wd_method.from_buffer_copy(m)
-                    rest.max_iter = m.max_iter - spent
-                    out = self.solve(prep, rest, phi=phi, hist_cap=1, check=False)
-                    out["iters"] += spent
-                    spent = out["iters"]
-                if bad or out["status"] not in (0, L.WD_STAGNATED):
+                if out["status"] not in (L.WD_OK, L.WD_STAGNATED):
                     restarted = True
                     m.warm_start = 0
             if not m.warm_start:

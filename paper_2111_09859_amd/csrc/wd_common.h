@@ -113,6 +113,7 @@ struct GridDev {
     double kp, kp2;           // largest modified wavenumbers: advective, diffusive
     int max_iter, stall;
     int warm;                 // initial field given by the caller
+    int warm_probe;           // > 0: the runaway check after this iteration
     double fcoef[6];          // filter correction factor for N = 1..5
     double da, db, dc;        // interior derivative coefficients
     int dradius, compact;
@@ -123,7 +124,8 @@ struct GridDev {
     void *P[3];               // partial sums carried between passes
     void *uw2;                // upwind baseline: |U|^2 of the stage (its
                               // advective term is carried in P[1])
-    double *rpart;            // [nparts][2] residual partials
+    double *rpart;            // [nparts][4] FP64 partials: max change, sum of
+                              // squared changes, max -phi, max |phi|
     double *hist;             // [hist_cap][2]
     int hist_cap;
     int nparts;

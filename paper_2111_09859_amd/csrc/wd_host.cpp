@@ -582,6 +582,7 @@ int check_method(const wd_method *m)
         return fail(WD_ERR_INVALID_ARG, "alpha_f must be in [0, 0.5) when the filter is on");
     if (!(m->sigma > 0.0)) return fail(WD_ERR_INVALID_ARG, "sigma must be > 0");
     if (m->max_iter < 1) return fail(WD_ERR_INVALID_ARG, "max_iter must be >= 1");
+    if (m->warm_probe < 0) return fail(WD_ERR_INVALID_ARG, "warm_probe must be >= 0");
     if (!(m->tol >= 0.0)) return fail(WD_ERR_INVALID_ARG, "tol must be >= 0");
     if (m->stall_window < 0) return fail(WD_ERR_INVALID_ARG, "stall_window must be >= 0");
     if (m->equation == WD_EQ_HJ && m->curvature && !(m->eps0 > 0.0))
@@ -627,7 +628,7 @@ size_t grid_region_bytes(const wd_grid_desc &d, const wd_method &m)
         b += (size_t)(d.ndim + 1) * al256((size_t)N * 8);  // FP64 conversion
     long long parts = N / d.n[d.ndim - 1];
     parts = std::max(parts, (N + kChunk - 1) / kChunk);
-    b += al256((size_t)parts * 16);
+    b += al256((size_t)parts * 32);
     b += al256((size_t)hist_dev_cap(m) * 16);
     b += al256(sizeof(GridState));
     return b;
@@ -778,6 +779,7 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     g.max_iter = m.max_iter;
     g.stall = m.stall_window;
     g.warm = m.warm_start;
+    g.warm_probe = m.warm_start ? std::max(0, m.warm_probe) : 0;
     // filter correction factor -(1 - 2 af)(-1)^N / 4^N
     for (int N5 = 1; N5 <= 5; ++N5)
         g.fcoef[N5] = -(1.0 - 2.0 * m.alpha_f) * ((N5 & 1) ? -1.0 : 1.0) / std::ldexp(1.0, 2 * N5);
@@ -804,7 +806,7 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     }
     long long parts = N / d.n[d.ndim - 1];
     parts = std::max(parts, (N + kChunk - 1) / kChunk);
-    g.rpart = static_cast<double *>(take((size_t)parts * 16));
+    g.rpart = static_cast<double *>(take((size_t)parts * 32));
     g.hist_cap = hist_dev_cap(m);
     g.hist = static_cast<double *>(take((size_t)g.hist_cap * 16));
     g.state = static_cast<GridState *>(take(sizeof(GridState)));
@@ -1584,6 +1586,7 @@ int solve_plan(wd_ctx *ctx, Plan &P, void *const *aux, double *const *hists, int
     }
     if (hipStreamSynchronize(s) != hipSuccess) return fail(WD_ERR_HIP, "final sync failed");
     if (worst == WD_ERR_DIVERGED) fail(WD_ERR_DIVERGED, "a pseudo-step change was not finite");
+    if (worst == WD_ERR_WARM_RUNAWAY) fail(WD_ERR_WARM_RUNAWAY, "warm start stopped by the runaway check");
     return worst;
 }
 
@@ -1635,6 +1638,7 @@ int wd_method_default(wd_method *m)
     m->stall_window = 0;
     m->precision = WD_FP64;
     m->warm_start = 0;
+    m->warm_probe = 300;
     return WD_OK;
 }
 

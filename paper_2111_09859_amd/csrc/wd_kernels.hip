@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(kThreads)
 k_resid(const GridDev *__restrict__ grids, const Item *__restrict__ items,
         int nitems)
 {
-    __shared__ double sh[2 * kThreads / 64];
+    __shared__ double sh[4 * kThreads / 64];
     int step, end;
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
@@ -162,7 +162,7 @@ k_resid(const GridDev *__restrict__ grids, const Item *__restrict__ items,
         gptr<T> phi = gcast<T>(g.phi);
         gptr<const T> ps = gcast<const T>(g.ps);
         const long long q0 = (long long)item.tile * kChunk;
-        double mx = 0.0, sm = 0.0;
+        double mx = 0.0, sm = 0.0, ng = 0.0, mg = 0.0;
         for (int i = threadIdx.x; i < kChunk; i += kThreads) {
             const long long q = q0 + i;
             if (q >= g.N) break;
@@ -170,13 +170,12 @@ k_resid(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             const double e = fabs((double)nv - (double)phi[q]);
             mx = nanmax(mx, e);
             sm += e * e;
+            ng = nanmax(ng, -(double)nv);
+            mg = nanmax(mg, fabs((double)nv));
             phi[q] = nv;
         }
-        block_reduce(mx, sm, sh);
-        if (threadIdx.x == 0) {
-            gmem(g.rpart)[2 * item.tile] = mx;
-            gmem(g.rpart)[2 * item.tile + 1] = sm;
-        }
+        block_reduce(mx, sm, ng, mg, sh);
+        if (threadIdx.x == 0) put_rpart(g, item.tile, mx, sm, ng, mg);
         __syncthreads();
     }
 }
@@ -282,15 +281,18 @@ k_init(const GridDev *__restrict__ grids, const Item *__restrict__ items,
 __global__ void __launch_bounds__(kThreads)
 k_finalize(const GridDev *__restrict__ grids, int ngrids)
 {
-    __shared__ double sh[2 * kThreads / 64];
+    __shared__ double sh[4 * kThreads / 64];
     const GridDev &g = grids[blockIdx.x];
     if (gmem(g.state)->done) return;
-    double mx = 0.0, sm = 0.0;
+    double mx = 0.0, sm = 0.0, ng = 0.0, mg = 0.0;
     for (int i = threadIdx.x; i < g.nparts; i += kThreads) {
-        mx = nanmax(mx, gmem(g.rpart)[2 * i]);
-        sm += gmem(g.rpart)[2 * i + 1];
+        gptr<const double> r = gmem(g.rpart) + 4 * (long long)i;
+        mx = nanmax(mx, r[0]);
+        sm += r[1];
+        ng = nanmax(ng, r[2]);
+        mg = nanmax(mg, r[3]);
     }
-    block_reduce(mx, sm, sh);
+    block_reduce(mx, sm, ng, mg, sh);
     if (threadIdx.x != 0) return;
     GridState st = *g.state;
     const int it = st.iter;
@@ -304,6 +306,12 @@ k_finalize(const GridDev *__restrict__ grids, int ngrids)
     st.last = mx;
     if (!(fabs(mx) <= 1.0e300) || !(fabs(l2) <= 1.0e300)) {
         st.status = -3;
+        st.done = 1;
+    } else if (g.warm_probe > 0 && nit == g.warm_probe && ng > 0.1 * mg) {
+        // warm-start guard: after the probe window the field lies below
+        // -0.1 of its largest magnitude somewhere -- an undershoot beside a
+        // wall that Gamma = 0 cannot damp, which only grows (WD_ERR_WARM_RUNAWAY)
+        st.status = -8;
         st.done = 1;
     } else if (mx <= g.tol) {
         st.status = 0;

@@ -1537,25 +1537,46 @@ __device__ inline double nanmax(double a, double b)
     return (a > b || a != a) ? a : b;
 }
 
-__device__ inline void block_reduce(double &mx, double &sm, double *sh)
+// The FP64 partials of one tile or chunk, reduced over the workgroup into
+// thread 0: largest change mx, sum of squared changes sm, and of the new
+// field the largest -phi (ng) and the largest |phi| (mg).  sh holds
+// 4 * kThreads / 64 doubles.
+__device__ inline void block_reduce(double &mx, double &sm, double &ng, double &mg, double *sh)
 {
     for (int o = 32; o > 0; o >>= 1) {
         mx = nanmax(mx, __shfl_xor(mx, o));
         sm += __shfl_xor(sm, o);
+        ng = nanmax(ng, __shfl_xor(ng, o));
+        mg = nanmax(mg, __shfl_xor(mg, o));
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) {
-        sh[2 * wv] = mx;
-        sh[2 * wv + 1] = sm;
+        sh[4 * wv] = mx;
+        sh[4 * wv + 1] = sm;
+        sh[4 * wv + 2] = ng;
+        sh[4 * wv + 3] = mg;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < kThreads / 64; ++w) {
-            mx = nanmax(mx, sh[2 * w]);
-            sm += sh[2 * w + 1];
+            mx = nanmax(mx, sh[4 * w]);
+            sm += sh[4 * w + 1];
+            ng = nanmax(ng, sh[4 * w + 2]);
+            mg = nanmax(mg, sh[4 * w + 3]);
         }
     }
+}
+
+// a tile's or chunk's partials into rpart (thread 0)
+__device__ inline void put_rpart(const GridDev &g, int part, double mx, double sm, double ng,
+                                 double mg)
+{
+    gptr<double> r = gmem(g.rpart) + 4 * (long long)part;
+    r[0] = mx;
+    r[1] = sm;
+    r[2] = ng;
+    r[3] = mg;
 }
 
 // Filter pass along direction l (Sec. 3.4), in correction form:
@@ -1613,7 +1634,7 @@ k_filter(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                 if (pvalid(tl, k)) ps[pt.Q[k]] = v0[k] + r[k];
             continue;
         }
-        double mx = 0.0, sm = 0.0;
+        double mx = 0.0, sm = 0.0, ng = 0.0, mg = 0.0;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             if (!pvalid(tl, k)) continue;
@@ -1642,17 +1663,16 @@ k_filter(const GridDev *__restrict__ grids, const Item *__restrict__ items,
                 const double e = fabs((double)nv - (double)pold[k]);
                 mx = nanmax(mx, e);
                 sm += e * e;
+                ng = nanmax(ng, -(double)nv);
+                mg = nanmax(mg, fabs((double)nv));
                 phi[q] = nv;
             } else {
                 ps[q] = nv;
             }
         }
         if (resid) {
-            block_reduce(mx, sm, reinterpret_cast<double *>(B));
-            if (threadIdx.x == 0) {
-                gmem(g.rpart)[2 * item.tile] = mx;
-                gmem(g.rpart)[2 * item.tile + 1] = sm;
-            }
+            block_reduce(mx, sm, ng, mg, reinterpret_cast<double *>(B));
+            if (threadIdx.x == 0) put_rpart(g, item.tile, mx, sm, ng, mg);
             __syncthreads();
         }
     }

@@ -819,7 +819,7 @@ k_seg_filter(const GridDev *__restrict__ grids, const Item *__restrict__ items, 
             seg_write<T, M>(ps, L, P, x);
             continue;
         }
-        double mx = 0.0, sm = 0.0;
+        double mx = 0.0, sm = 0.0, ng = 0.0, mg = 0.0;
         {
             T po[M];
             seg_read<T, M>(phi, L, P, po);
@@ -829,17 +829,18 @@ k_seg_filter(const GridDev *__restrict__ grids, const Item *__restrict__ items, 
                 const double d = fabs((double)x[i] - (double)po[i]);
                 mx = nanmax(mx, d);
                 sm += d * d;
+                ng = nanmax(ng, -(double)x[i]);
+                mg = nanmax(mg, fabs((double)x[i]));
             }
         }
         seg_write<T, M>(phi, L, P, x);
         for (int o = 32; o > 0; o >>= 1) {
             mx = nanmax(mx, __shfl_xor(mx, o, kSegThreads));
             sm += __shfl_xor(sm, o, kSegThreads);
+            ng = nanmax(ng, __shfl_xor(ng, o, kSegThreads));
+            mg = nanmax(mg, __shfl_xor(mg, o, kSegThreads));
         }
-        if (threadIdx.x == 0) {
-            gmem(g.rpart)[2 * item.tile] = mx;
-            gmem(g.rpart)[2 * item.tile + 1] = sm;
-        }
+        if (threadIdx.x == 0) put_rpart(g, item.tile, mx, sm, ng, mg);
     }
 }
 

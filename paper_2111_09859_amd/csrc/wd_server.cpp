@@ -91,6 +91,7 @@ struct Req {
     int status = WD_PENDING;
     double t_submit = 0, t_admit = 0, t_done = 0;
     int iters = 0;
+    int spent = 0;                     // iterations of an abandoned warm attempt
     std::vector<double> hist;
     size_t bytes = 0, off = 0;
     bool running = false, cancel = false, finished = false, fresh = false;
@@ -118,7 +119,7 @@ struct wd_server {
     bool stop = false;
     int error = 0;
     std::thread th;
-    long long n_done = 0, n_iters = 0;
+    long long n_done = 0, n_iters = 0, n_restarts = 0;
     int peak_active = 0;
     int round_iters = 16;
     long long point_budget = 8LL << 20;   // grid points iterated together
@@ -295,9 +296,20 @@ static int run_group(wd_server *srv, const std::vector<long long> &ids, bool sam
             std::lock_guard<std::mutex> lk(srv->mu);
             Req &r = srv->reqs[ids[i]];
             r.fresh = false;
-            r.iters = st[i].iter;
+            r.iters = r.spent + st[i].iter;
             cancel = r.cancel;
             hist_cap = r.hist_cap;
+            if (st[i].done && !cancel && st[i].status == WD_ERR_WARM_RUNAWAY) {
+                // the runaway check stopped a warm start: solve it again
+                // from zero in the same slot (the next round initialises it)
+                r.spent += st[i].iter;
+                r.g.warm = 0;
+                r.g.warm_probe = 0;
+                r.meth.warm_start = 0;
+                r.fresh = true;
+                ++srv->n_restarts;
+                continue;
+            }
         }
         if (!st[i].done && !cancel) continue;
         int status = cancel && !st[i].done ? WD_ERR_CANCELLED : st[i].status;
@@ -499,10 +511,11 @@ int wd_server_cancel(wd_server *srv, long long req_id)
 }
 
 int wd_server_stats(wd_server *srv, long long *done, long long *iterations, size_t *peak_bytes,
-                    int *peak_active)
+                    int *peak_active, long long *restarts)
 {
     if (!srv) return fail(WD_ERR_INVALID_ARG, "null server");
     std::lock_guard<std::mutex> lk(srv->mu);
+    if (restarts) *restarts = srv->n_restarts;
     if (done) *done = srv->n_done;
     if (iterations) *iterations = srv->n_iters;
     if (peak_bytes) *peak_bytes = srv->arena.peak;

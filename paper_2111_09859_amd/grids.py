@@ -245,7 +245,7 @@ def star_grain(n: int = 512, step: int = 0, **kw) -> GridSpec:
 
 
 # ---------------------------------------------------------------------------
-# Moving walls (the unsteady canonical cases of Sec. 6): one grid per
+# Moving walls (the unsteady canonical cases of Sec. 5.5): one grid per
 # physical time step, the same index dimensions at every step.
 def piston(ntheta: int = 64, nr: int = 25, nz: int = 33, h: float = 1.0,
            R: float = 0.25, Rb: float = 1.0) -> GridSpec:

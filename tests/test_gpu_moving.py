@@ -1,4 +1,4 @@
-"""Moving walls on the GPU (the unsteady cases of Sec. 6): a piston in an
+"""Moving walls on the GPU (the unsteady cases of Sec. 5.5): a piston in an
 annular bore (3D curvilinear grid, the piston face moving along z) and a
 cube bouncing between a floor and a ceiling (3D Cartesian grid, the cube
 a moving solid mask).  Each physical time step is a pseudo-time solve that
@@ -135,9 +135,10 @@ def test_cube_sequence_fp32(solver):
 def test_warm_start_runaway_restarts_cold(solver):
     """The cube dropped 70 cells in one step (129^3): the warm estimate
     leaves about 0.3 two cells from the cube's new face, the march
-    undershoots below zero there and runs away.  The sequence sees the
-    field go negative within the first pseudo-steps and solves that step
-    again from zero: the result is the cold step's field, bit for bit."""
+    undershoots below zero there and runs away.  The library's runaway
+    check stops the warm solve after its probe window and the sequence
+    solves that step again from zero: the result is the cold step's field,
+    bit for bit."""
     zs = G.bounce_heights(2, 6.0)[:2]
     specs = [G.bouncing_cube(129, z) for z in zs]
     fields = {}
@@ -235,3 +236,68 @@ def test_full_size_piston_theta_invariance(solver):
     assert out["status"] in (0, 2)
     assert s_early <= SYM_EARLY and s_conv <= SYM_STOPPED
     assert err < 1.5 * cell
+
+
+@pytest.mark.parametrize("level,probe,want", [(0.3, 300, "runaway"), (0.1, 300, "runs on"),
+                                              (0.3, 0, "runs on")])
+def test_runaway_check(solver, oracle, level, probe, want):
+    """The device's runaway check of a warm start (wd_method.warm_probe) on
+    the steep estimates of the oracle's runaway pin: box 129^2, the field
+    `level` everywhere but on the walls, E4 LAD pseudo-HJ, FP64.  A jump of
+    0.3 over one cell runs away: the solve stops at the end of the probe
+    window with WD_ERR_WARM_RUNAWAY, the GPU field then lies below -0.1 of
+    its largest magnitude, and so does the oracle's after as many
+    iterations from the same start.  A jump of 0.1 recovers and runs on to
+    max_iter, as does any start with the check off."""
+    import torch
+    from paper_2111_09859_amd import _lib as L
+    from test_moving_oracle import lad
+    spec = G.box2d(129)
+    prep = solver.prepare(spec, "E4", "fp64")
+    m = gm("fp64", tol=0.0, max_iter=400, warm=True)
+    m.warm_probe = probe
+    phi = torch.full(spec.shape, level, dtype=torch.float64, device=solver.device)
+    out = solver.solve(prep, m, phi=phi, check=False)
+    f = phi.cpu().numpy()
+    say(f"[runaway check] level {level} probe {probe}: status {out['status']} "
+        f"iters {out['iters']} min {f.min():.3g} max|phi| {np.abs(f).max():.3g}")
+    if want == "runaway":
+        assert out["status"] == L.WD_ERR_WARM_RUNAWAY and out["iters"] == probe
+        assert f.min() < -0.1 * np.abs(f).max()
+        ref, _, it, _ = oracle.solve(spec, lad(oracle, fixed=probe),
+                                     phi0=np.full(spec.shape, level))
+        assert it == probe and ref.min() < -0.1 * np.abs(ref).max()
+    else:
+        assert out["status"] in (L.WD_NOT_CONVERGED, L.WD_ERR_DIVERGED)
+        assert out["status"] == L.WD_ERR_DIVERGED or out["iters"] == 400
+
+
+def test_server_restarts_runaway_warm_request(solver):
+    """A warm request that the runaway check stops is solved again from
+    zero inside the server: its field is the plain cold solve's, bit for
+    bit, its iteration count adds the abandoned probe window, and the
+    server counts one restart."""
+    import torch
+    from paper_2111_09859_amd import api, _lib as L
+    spec = G.box2d(129)
+    prep = solver.prepare(spec, "E4", "fp32")
+    warm = gm("fp32", tol=1e-5, max_iter=20000, warm=True, stall=1000)
+    warm.warm_probe = 300
+    cold = gm("fp32", tol=1e-5, max_iter=20000, warm=False, stall=1000)
+    ref_phi = torch.zeros(spec.shape, dtype=torch.float32, device=solver.device)
+    ref = solver.solve(prep, cold, phi=ref_phi, check=False)
+    srv = api.Server(solver, budget_bytes=256 << 20, max_slots=4)
+    try:
+        phi = torch.full(spec.shape, 0.3, dtype=torch.float32, device=solver.device)
+        rid = srv.submit(prep, warm, phi=phi, session=3)
+        st = srv.wait(rid, 120.0)
+        info = srv.poll(rid)
+        stats = srv.stats()
+        say(f"[server restart] status {st} iters {info['iters']} (cold {ref['iters']}) "
+            f"restarts {stats['restarts']}")
+        assert st == ref["status"] and st in (L.WD_OK, L.WD_STAGNATED)
+        assert info["iters"] == 300 + ref["iters"]
+        assert stats["restarts"] == 1
+        assert torch.equal(phi, ref_phi)
+    finally:
+        srv.close()

@@ -1,4 +1,4 @@
-"""Moving walls (the unsteady cases of Sec. 6), CPU side: the closed-form
+"""Moving walls (the unsteady cases of Sec. 5.5), CPU side: the closed-form
 distances of the two moving-wall geometries against a brute-force search
 over sampled wall surfaces, and the oracle's warm-started march (a
 physical time step starts from the previous step's field) against what
