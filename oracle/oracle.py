@@ -44,7 +44,7 @@ class _Grid(C.Structure):
                 ("bc", (C.c_int * 2) * 3), ("uniform", C.c_int),
                 ("h", C.c_double * 3), ("coords", C.POINTER(C.c_double)),
                 ("period", (C.c_double * 3) * 3),
-                ("mask", C.POINTER(C.c_ubyte))]
+                ("mask", C.POINTER(C.c_ubyte)), ("metric_form", C.c_int)]
 
 
 class _Method(C.Structure):
@@ -115,6 +115,7 @@ class OracleGrid:
                 for m in range(spec.ndim):
                     g.period[l][m] = float(spec.period[l][m])
         g.uniform = 1 if spec.coords is None else 0
+        g.metric_form = int(getattr(spec, "metric_form", 0))
         self._coords = None
         if spec.coords is not None:
             self._coords = np.ascontiguousarray(spec.coords, dtype=np.float64)

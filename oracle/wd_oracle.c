@@ -429,7 +429,67 @@ static int filter_dir(const wdo_grid *g, int l, double af, double *f)
 /* ------------------------------------------------------------------ */
 /* Metrics (Sec. 3.1 with the solve's own scheme, Sec. 3.2): the Jacobian
  * J[m][l] = d x_m / d xi_l from the derivative operator, then its inverse
- * M[l][m] = d xi_l / d x_m at every point. */
+ * M[l][m] = d xi_l / d x_m at every point.
+ *
+ * metric_form 1 (3D, an option beside the paper's recipe): the
+ * conservative form of the metric terms.  The cofactor of d x_m / d xi_l
+ * is written as a divergence, J xi_{l,m} = sum over the Levi-Civita
+ * symbols of D_q (x_b D_p x_a) / 2, which for (m, a, b) and (l, p, q)
+ * cyclic is
+ *   Q_{p,m} = x_b J[a][p] - x_a J[b][p],
+ *   J xi_{l,m} = (D_q Q_{p,m} - D_p Q_{q,m}) / 2,
+ * and xi_{l,m} = (J xi_{l,m}) / det J.  Because derivatives along
+ * different directions commute, sum_l D_l (J xi_{l,m}) = 0 holds to
+ * rounding (the discrete metric identity); on an affine grid the two forms
+ * agree.  Coordinates that jump across a periodic seam are not supported
+ * in this form (the products would jump by a varying amount). */
+static int metrics_conservative(const wdo_grid *g, int scheme, const double *J, double *met)
+{
+    long N = npoints(g);
+    for (int l = 0; l < 3; ++l)
+        for (int m = 0; m < 3; ++m)
+            if (g->period[l][m] != 0.0) return -2;
+    double *Q = malloc(sizeof(double) * N * 9);
+    double *Dq = malloc(sizeof(double) * N);
+    double *Dp = malloc(sizeof(double) * N);
+    double *T = malloc(sizeof(double) * N * 9);
+    int rc = 0;
+    /* Q[p][m] */
+    for (int p = 0; p < 3; ++p)
+        for (int m = 0; m < 3; ++m) {
+            int a = (m + 1) % 3, b = (m + 2) % 3;
+            const double *xa = g->coords + a * N, *xb = g->coords + b * N;
+            const double *Jap = J + (a * 3 + p) * N, *Jbp = J + (b * 3 + p) * N;
+            double *q = Q + (p * 3 + m) * N;
+            for (long k = 0; k < N; ++k) q[k] = xb[k] * Jap[k] - xa[k] * Jbp[k];
+        }
+    /* J xi_{l,m} */
+    for (int l = 0; l < 3 && !rc; ++l) {
+        int p = (l + 1) % 3, q = (l + 2) % 3;
+        for (int m = 0; m < 3 && !rc; ++m) {
+            rc = deriv_dir(g, q, scheme, 0.0, Q + (p * 3 + m) * N, Dq);
+            if (!rc) rc = deriv_dir(g, p, scheme, 0.0, Q + (q * 3 + m) * N, Dp);
+            double *t = T + (l * 3 + m) * N;
+            for (long k = 0; k < N; ++k) t[k] = 0.5 * (Dq[k] - Dp[k]);
+        }
+    }
+    if (!rc)
+        for (long k = 0; k < N; ++k) {
+            double A[3][3];
+            for (int m = 0; m < 3; ++m)
+                for (int l = 0; l < 3; ++l)
+                    A[m][l] = J[(m * 3 + l) * N + k];
+            double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1])
+                       - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0])
+                       + A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+            for (int l = 0; l < 3; ++l)
+                for (int m = 0; m < 3; ++m)
+                    met[(l * 3 + m) * N + k] = T[(l * 3 + m) * N + k] / det;
+        }
+    free(Q); free(Dq); free(Dp); free(T);
+    return rc;
+}
+
 int wdo_metrics(const wdo_grid *g, int scheme, double *met)
 {
     int d = g->ndim;
@@ -448,6 +508,11 @@ int wdo_metrics(const wdo_grid *g, int scheme, double *met)
                                g->coords + m * N, J + (m * d + l) * N);
             if (rc) { free(J); return rc; }
         }
+    if (d == 3 && g->metric_form == 1) {
+        int rc = metrics_conservative(g, scheme, J, met);
+        free(J);
+        return rc;
+    }
 #pragma omp parallel for schedule(static)
     for (long q = 0; q < N; ++q) {
         double A[3][3], Inv[3][3];

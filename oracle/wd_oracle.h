@@ -37,6 +37,9 @@ typedef struct {
     const double *coords;      /* ndim SoA components (uniform == 0)     */
     double period[3][3];       /* x_m(i_l + n_l) = x_m(i_l) + period[l][m] */
     const unsigned char *mask; /* optional, 1 = solid point              */
+    int metric_form;           /* 0: inverse of the coordinate Jacobian;
+                                  1: conservative form (3D; see
+                                  wdo_metrics)                          */
 } wdo_grid;
 
 typedef struct {

@@ -37,6 +37,8 @@ class GridSpec:
     mask: Optional[np.ndarray] = None
     exact: Optional[np.ndarray] = None
     meta: dict = field(default_factory=dict)
+    metric_form: int = 0                 # 0 inverse of the coordinate Jacobian,
+                                         # 1 conservative form (3D)
 
     @property
     def shape(self):
@@ -182,6 +184,32 @@ def duct(n: int = 256, nx: Optional[int] = None) -> GridSpec:
     return GridSpec("duct", 3, (nx, n, n),
                     ((PERIODIC, PERIODIC), (WALL, WALL), (WALL, WALL)),
                     h=(dx, dy, dy), exact=exact)
+
+
+def warped_box(n: int = 33, amp: float = 0.05, nx: Optional[int] = None,
+               ny: Optional[int] = None, metric_form: int = 0) -> GridSpec:
+    """Curvilinear 3D grid of the unit cube [0,1]^3 with walls on all six
+    faces, its interior nodes displaced smoothly so that every coordinate
+    depends on every index (a full, varying 3x3 Jacobian, not an
+    extrusion): with s = (i, j, k) / (n - 1),
+      x = s_x + amp sin(pi s_x) sin(2 pi s_y) cos(pi s_z),
+      y = s_y + amp sin(pi s_y) sin(2 pi s_z) cos(pi s_x),
+      z = s_z + amp sin(pi s_z) sin(2 pi s_x) cos(pi s_y).
+    Each face keeps its plane (x = 0 on s_x = 0, ...), so the exact
+    distance is min(x, 1-x, y, 1-y, z, 1-z) at every node."""
+    nx = n if nx is None else nx
+    ny = n if ny is None else ny
+    nz = n
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    sx, sy, sz = i / (nx - 1.0), j / (ny - 1.0), k / (nz - 1.0)
+    pi = np.pi
+    x = sx + amp * np.sin(pi * sx) * np.sin(2 * pi * sy) * np.cos(pi * sz)
+    y = sy + amp * np.sin(pi * sy) * np.sin(2 * pi * sz) * np.cos(pi * sx)
+    z = sz + amp * np.sin(pi * sz) * np.sin(2 * pi * sx) * np.cos(pi * sy)
+    exact = np.minimum.reduce([x, 1 - x, y, 1 - y, z, 1 - z])
+    return GridSpec("warped_box", 3, (nx, ny, nz),
+                    ((WALL, WALL), (WALL, WALL), (WALL, WALL)),
+                    coords=np.stack([x, y, z]), exact=exact, metric_form=metric_form)
 
 
 def box2d(n: int = 65) -> GridSpec:

@@ -711,3 +711,104 @@ def test_thread_count_does_not_change_results(oracle, case):
     assert (st1, it1) == (st4, it4)
     assert np.array_equal(ref, par)
     assert np.array_equal(h1, h4)
+
+
+def _warped_jacobian(spec, amp=0.05):
+    """Analytic d x_m / d xi_l (index space) of grids.warped_box."""
+    nx, ny, nz = spec.n
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    s = [i / (nx - 1.0), j / (ny - 1.0), k / (nz - 1.0)]
+    h = [1.0 / (nx - 1.0), 1.0 / (ny - 1.0), 1.0 / (nz - 1.0)]
+    pi = np.pi
+    A = np.zeros((3, 3) + spec.shape)
+    for m in range(3):
+        a, b = (m + 1) % 3, (m + 2) % 3
+        # x_m = s_m + amp sin(pi s_m) sin(2 pi s_a) cos(pi s_b)
+        f1, f2, f3 = np.sin(pi * s[m]), np.sin(2 * pi * s[a]), np.cos(pi * s[b])
+        A[m, m] = (1 + amp * pi * np.cos(pi * s[m]) * f2 * f3) * h[m]
+        A[m, a] = amp * f1 * 2 * pi * np.cos(2 * pi * s[a]) * f3 * h[a]
+        A[m, b] = -amp * f1 * f2 * pi * np.sin(pi * s[b]) * h[b]
+    return A
+
+
+def _inverse_metrics(A):
+    Am = np.moveaxis(A, (0, 1), (-2, -1))
+    inv = np.linalg.inv(Am)                  # inv[..., l, m] = d xi_l / d x_m
+    return np.moveaxis(inv, (-2, -1), (0, 1))
+
+
+def _dline(oracle, f, axis, scheme):
+    """Derivative along one array axis (no periodic directions)."""
+    g = np.moveaxis(f, axis, -1)
+    out = np.empty_like(g)
+    for idx in np.ndindex(g.shape[:-1]):
+        out[idx] = oracle.deriv_line(np.ascontiguousarray(g[idx]), scheme)
+    return np.moveaxis(out, -1, axis)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_metrics_3d_conservative_form_affine(oracle, scheme):
+    """The conservative metric form (J xi_{l,m} written as a divergence of
+    coordinate products) equals M^-1 on an affine grid, as the inverse form
+    does: the products are linear there and every scheme is exact."""
+    spec, M = _affine3d()
+    spec.metric_form = 1
+    met = oracle.metrics(spec, scheme)
+    inv = np.linalg.inv(M)
+    for l in range(3):
+        for mm in range(3):
+            assert np.abs(met[3 * l + mm] - inv[l, mm]).max() < 1e-11 * np.abs(inv).max()
+
+
+def test_metric_identity_of_the_conservative_form(oracle):
+    """On the warped box (a full, varying Jacobian) the conservative form
+    satisfies the discrete metric identities sum_l D_l (J xi_{l,m}) = 0 to
+    rounding, with J the determinant of the coordinate derivatives; the
+    inverse form leaves a truncation-size residual."""
+    spec = G.warped_box(13)
+    res = {}
+    # array axes of a (z, y, x) field: direction l runs along axis 2 - l
+    D = [[_dline(oracle, spec.coords[m], 2 - l, "E4") for l in range(3)] for m in range(3)]
+    Am = np.moveaxis(np.array(D), (0, 1), (-2, -1))
+    det = np.linalg.det(Am)
+    for form in (0, 1):
+        spec.metric_form = form
+        met = oracle.metrics(spec, "E4").reshape((3, 3) + spec.shape)
+        worst = 0.0
+        for mm in range(3):
+            s = sum(_dline(oracle, det * met[l, mm], 2 - l, "E4") for l in range(3))
+            worst = max(worst, float(np.abs(s).max()))
+        res[form] = worst
+    scale = float(np.abs(det).max())
+    assert res[1] < 1e-13 * scale * 13
+    assert res[0] > 1e3 * res[1]
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_warped_metrics_converge_at_the_scheme_order(oracle, form):
+    """Both metric forms approach the analytic metrics of the warped box at
+    the scheme's order under refinement (E4: about 16x per halving of the
+    spacing; a sign or index slip in either form would not converge)."""
+    errs = []
+    for n in (17, 33):
+        spec = G.warped_box(n, metric_form=form)
+        met = oracle.metrics(spec, "E4").reshape((3, 3) + spec.shape)
+        ex = _inverse_metrics(_warped_jacobian(spec))
+        errs.append(float(np.abs(met - ex).max() / np.abs(ex).max()))
+    assert errs[1] < errs[0] / 10.0
+    assert errs[1] < 1e-3
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("scheme,sigma", [("C6", 1.0), ("E4", 0.5)])
+def test_warped_box_distance(oracle, form, scheme, sigma):
+    """The LAD pseudo-HJ march on the 17^3 warped box (both metric forms)
+    converges to within about a cell of min(x, 1-x, y, 1-y, z, 1-z) (the
+    kinks where the nearest wall changes); E4 needs the halved pseudo-step
+    here (with sigma = 1 it settles to 5e-8 and then grows)."""
+    spec = G.warped_box(17, metric_form=form)
+    m = oracle.make_method(equation=oracle.HJ, gamma=oracle.GAMMA_LAD, eps=0.2, scheme=scheme,
+                           alpha_f=0.48, sigma=sigma, tol=1e-8, max_iter=3000)
+    phi, st, it, _ = oracle.solve(spec, m)
+    assert st == 0
+    assert np.abs(phi - spec.exact).max() < 1.0 / 16
