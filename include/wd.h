@@ -163,6 +163,25 @@ int wd_compute_metrics(wd_ctx *ctx, const wd_grid_desc *desc, int scheme,
                        const double *coords, const double *period, void *out,
                        int out_precision, void *stream);
 
+/* Metric forms.  INVERSE: the per-point inverse of the coordinate
+ * derivatives (wd_compute_metrics, the recipe of Sec. 3.1 with the solve's
+ * scheme).  CONSERVATIVE (an option beside it, 3D): each J xi_{l,m} written
+ * as a divergence of coordinate products, J xi_{l,m} = (D_q Q_{p,m} -
+ * D_p Q_{q,m}) / 2 with Q_{p,m} = x_b D_p x_a - x_a D_p x_b ((l, p, q) and
+ * (m, a, b) cyclic), then divided by the determinant of the coordinate
+ * derivatives; derivatives along different directions commute, so the
+ * discrete metric identities sum_l D_l (J xi_{l,m}) = 0 hold to rounding.
+ * On affine grids, and in 2D, the two forms agree. */
+enum wd_metric_form { WD_METRICS_INVERSE = 0, WD_METRICS_CONSERVATIVE = 1 };
+
+/* wd_compute_metrics with the form chosen (wd_metric_form).  The
+ * conservative form needs FP64 scratch of 36 doubles per point (the inverse
+ * form 9) and returns WD_ERR_UNSUPPORTED for coordinates that jump across
+ * a periodic seam (any non-zero period entry). */
+int wd_compute_metrics_form(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, int form,
+                            const double *coords, const double *period, void *out,
+                            int out_precision, void *stream);
+
 /* Workspace bytes a wd_solve / wd_solve_batched of these grids needs.  The
  * caller allocates it on the device (any allocator) and passes it in. */
 int wd_workspace_bytes(wd_ctx *ctx, int n_grids, const wd_grid_desc *descs,

@@ -78,6 +78,7 @@ def lib():
         "wd_ctx_create": ([C.c_int, C.POINTER(vp)], C.c_int),
         "wd_ctx_destroy": ([vp], C.c_int),
         "wd_compute_metrics": ([vp, gd, C.c_int, vp, dp, vp, C.c_int, vp], C.c_int),
+        "wd_compute_metrics_form": ([vp, gd, C.c_int, C.c_int, vp, dp, vp, C.c_int, vp], C.c_int),
         "wd_workspace_bytes": ([vp, C.c_int, gd, me, szp], C.c_int),
         "wd_solve": ([vp, gd, me, vp, vp, dp, C.c_int, ip, vp, C.c_size_t, vp], C.c_int),
         "wd_solve_batched": ([vp, C.c_int, gd, me, C.POINTER(vp), C.POINTER(vp),
@@ -154,16 +155,30 @@ def wd_ctx_destroy(ctx) -> None:
     lib().wd_ctx_destroy(ctx)
 
 
+WD_METRICS_INVERSE, WD_METRICS_CONSERVATIVE = 0, 1
+
+
+def _period_arg(period):
+    if period is None:
+        return None
+    arr = (C.c_double * 9)(*[float(period[l][m]) if l < len(period) and m < len(period[l])
+                              else 0.0 for l in range(3) for m in range(3)])
+    return C.cast(arr, C.POINTER(C.c_double))
+
+
 def wd_compute_metrics(ctx, desc, scheme, coords_ptr, period, out_ptr, out_precision,
                        stream=None):
-    per = None
-    if period is not None:
-        arr = (C.c_double * 9)(*[float(period[l][m]) if l < len(period) and m < len(period[l])
-                                  else 0.0 for l in range(3) for m in range(3)])
-        per = C.cast(arr, C.POINTER(C.c_double))
-    return _check(lib().wd_compute_metrics(ctx, C.byref(desc), scheme, coords_ptr, per,
-                                           out_ptr, out_precision, stream),
+    return _check(lib().wd_compute_metrics(ctx, C.byref(desc), scheme, coords_ptr,
+                                           _period_arg(period), out_ptr, out_precision, stream),
                   "wd_compute_metrics")
+
+
+def wd_compute_metrics_form(ctx, desc, scheme, form, coords_ptr, period, out_ptr, out_precision,
+                            stream=None):
+    return _check(lib().wd_compute_metrics_form(ctx, C.byref(desc), scheme, form, coords_ptr,
+                                                _period_arg(period), out_ptr, out_precision,
+                                                stream),
+                  "wd_compute_metrics_form")
 
 
 def wd_workspace_bytes(ctx, descs, methods) -> int:

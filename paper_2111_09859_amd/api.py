@@ -101,10 +101,11 @@ class Solver:
                                      device=self.device)
             met = torch.empty((spec.ndim * spec.ndim,) + spec.shape, dtype=dt,
                               device=self.device)
-            L.wd_compute_metrics(self.ctx, d, L.SCHEMES[scheme] if isinstance(scheme, str)
-                                 else scheme, C.c_void_p(coords.data_ptr()), spec.period,
-                                 C.c_void_p(met.data_ptr()), PRECISIONS[precision],
-                                 self.stream())
+            L.wd_compute_metrics_form(self.ctx, d, L.SCHEMES[scheme] if isinstance(scheme, str)
+                                      else scheme, int(getattr(spec, "metric_form", 0)),
+                                      C.c_void_p(coords.data_ptr()), spec.period,
+                                      C.c_void_p(met.data_ptr()), PRECISIONS[precision],
+                                      self.stream())
             d.metrics = met.data_ptr()
         mask = None
         if spec.mask is not None:

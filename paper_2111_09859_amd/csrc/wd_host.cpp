@@ -1802,10 +1802,13 @@ int wd_solve_noalloc(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *met
     return rc;
 }
 
-int wd_compute_metrics(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, const double *coords,
-                       const double *period, void *out, int out_precision, void *stream)
+int wd_compute_metrics_form(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, int form,
+                            const double *coords, const double *period, void *out,
+                            int out_precision, void *stream)
 {
     if (!ctx || !desc || !coords || !out) return fail(WD_ERR_INVALID_ARG, "bad arguments");
+    if (form != WD_METRICS_INVERSE && form != WD_METRICS_CONSERVATIVE)
+        return fail(WD_ERR_INVALID_ARG, "bad metric form");
     wd_grid_desc d = *desc;
     d.metric_mode = WD_METRIC_UNIFORM;
     for (int l = 0; l < 3; ++l) d.h[l] = 1.0;
@@ -1814,22 +1817,34 @@ int wd_compute_metrics(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, const 
     if (rc) return rc;
     if (scheme < WD_E2 || scheme > WD_UW) return fail(WD_ERR_INVALID_ARG, "bad scheme");
     if (scheme == WD_UW) scheme = WD_E2;   // the upwind baseline's metrics are central E2
+    const int dim = d.ndim;
+    // the conservative form differs from the inverse in 3D only (in 2D both
+    // are the adjugate of the coordinate derivatives)
+    const bool gcl = form == WD_METRICS_CONSERVATIVE && dim == 3;
+    if (gcl && period)
+        for (int k = 0; k < 9; ++k)
+            if (period[k] != 0.0)
+                return fail(WD_ERR_UNSUPPORTED, "conservative metrics: coordinates jump across a seam");
     std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     (void)hipSetDevice(ctx->device);
     StreamJoin join(ctx, stream);
     hipStream_t s = ctx->stream;
-    const int dim = d.ndim;
     const long long N = npoints(d);
-    // scratch: J (dim*dim*N doubles), one grid view, items, state
+    // scratch: J (dim*dim*N doubles), for the conservative form the products
+    // Q (9N) and their derivatives (18N), one grid view, items, state
     void *scratch = nullptr;
     long long maxt = 0;
     for (int l = 0; l < dim; ++l) maxt = std::max(maxt, N / d.n[l]);
-    const size_t bytes = al256((size_t)dim * dim * N * 8) + al256(sizeof(GridDev)) +
+    const size_t jb = al256((size_t)dim * dim * N * 8);
+    const size_t qb = gcl ? al256((size_t)9 * N * 8) : 0, db = gcl ? al256((size_t)18 * N * 8) : 0;
+    const size_t bytes = jb + qb + db + al256(sizeof(GridDev)) +
                          al256((size_t)maxt * sizeof(Item)) + al256(sizeof(GridState));
     if (hipMalloc(&scratch, bytes) != hipSuccess) return fail(WD_ERR_NO_MEMORY, "metric scratch allocation failed");
     unsigned char *b = static_cast<unsigned char *>(scratch);
     double *J = reinterpret_cast<double *>(b);
-    GridDev *dg = reinterpret_cast<GridDev *>(b + al256((size_t)dim * dim * N * 8));
+    double *Q = reinterpret_cast<double *>(b + jb);
+    double *D = reinterpret_cast<double *>(b + jb + qb);
+    GridDev *dg = reinterpret_cast<GridDev *>(b + jb + qb + db);
     Item *ditems = reinterpret_cast<Item *>(reinterpret_cast<unsigned char *>(dg) + al256(sizeof(GridDev)));
     GridState *dst = reinterpret_cast<GridState *>(reinterpret_cast<unsigned char *>(ditems) +
                                                    al256((size_t)maxt * sizeof(Item)));
@@ -1867,30 +1882,54 @@ int wd_compute_metrics(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, const 
         g.ntiles[l] = l == 0 ? (int)((N / d.n[0] + g.tw[0] - 1) / g.tw[0])
                              : (int)((N / ((long long)d.n[0] * d.n[l])) * ((d.n[0] + g.tw[l] - 1) / g.tw[l]));
     }
-    for (int m = 0; m < dim && !rc; ++m) {
-        for (int l = 0; l < dim && !rc; ++l) {
-            GridDev v = g;
-            v.phi = const_cast<double *>(coords + (size_t)m * N);
-            v.F[l] = J + (size_t)(m * dim + l) * N;
-            v.jump[l] = period ? period[l * 3 + m] : 0.0;
-            std::vector<Item> it(g.ntiles[l]);
-            for (int t = 0; t < g.ntiles[l]; ++t) it[t] = Item{0, t};
-            if (hipMemcpyAsync(dg, &v, sizeof v, hipMemcpyHostToDevice, s) != hipSuccess ||
-                hipMemcpyAsync(ditems, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice, s) != hipSuccess) {
-                rc = fail(WD_ERR_HIP, "metric view upload failed");
-                break;
+    // dst = D_l src (FP64, index space), `jump` added across a periodic seam
+    auto deriv = [&](const double *src, int l, double *out_l, double jump) {
+        GridDev v = g;
+        v.phi = const_cast<double *>(src);
+        v.F[l] = out_l;
+        v.jump[l] = jump;
+        std::vector<Item> it(g.ntiles[l]);
+        for (int t = 0; t < g.ntiles[l]; ++t) it[t] = Item{0, t};
+        if (hipMemcpyAsync(dg, &v, sizeof v, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(ditems, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(WD_ERR_HIP, "metric view upload failed");
+        launch_pass(PASS_D1, 1, tile_np(g, l), dg, ditems, g.ntiles[l], l, 0,
+                    nwg_for(ctx, 1, PASS_D1, tile_np(g, l), g.ntiles[l]), s);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(WD_ERR_HIP, "metric pass failed");
+        return (int)WD_OK;
+    };
+    for (int m = 0; m < dim && !rc; ++m)
+        for (int l = 0; l < dim && !rc; ++l)
+            rc = deriv(coords + (size_t)m * N, l, J + (size_t)(m * dim + l) * N,
+                       period ? period[l * 3 + m] : 0.0);
+    if (!rc && gcl) {
+        // J xi_{l,m} = (D_q Q[p][m] - D_p Q[q][m]) / 2, (l, p, q) cyclic
+        launch_gcl_products(coords, J, Q, N, s);
+        for (int l = 0; l < 3 && !rc; ++l) {
+            const int p = (l + 1) % 3, q = (l + 2) % 3;
+            for (int m = 0; m < 3 && !rc; ++m) {
+                rc = deriv(Q + (size_t)(p * 3 + m) * N, q, D + (size_t)((l * 3 + m) * 2) * N, 0.0);
+                if (!rc)
+                    rc = deriv(Q + (size_t)(q * 3 + m) * N, p, D + (size_t)((l * 3 + m) * 2 + 1) * N, 0.0);
             }
-            launch_pass(PASS_D1, 1, tile_np(g, l), dg, ditems, g.ntiles[l], l, 0,
-                        nwg_for(ctx, 1, PASS_D1, tile_np(g, l), g.ntiles[l]), s);
-            if (hipStreamSynchronize(s) != hipSuccess) rc = fail(WD_ERR_HIP, "metric pass failed");
         }
-    }
-    if (!rc) {
+        if (!rc) {
+            launch_gcl_combine(J, D, out, out_precision == WD_FP64, N, s);
+            if (hipStreamSynchronize(s) != hipSuccess) rc = fail(WD_ERR_HIP, "metric combination failed");
+        }
+    } else if (!rc) {
         launch_invert(J, out, out_precision == WD_FP64, dim, N, s);
         if (hipStreamSynchronize(s) != hipSuccess) rc = fail(WD_ERR_HIP, "metric inversion failed");
     }
     (void)hipFree(scratch);
     return rc;
+}
+
+int wd_compute_metrics(wd_ctx *ctx, const wd_grid_desc *desc, int scheme, const double *coords,
+                       const double *period, void *out, int out_precision, void *stream)
+{
+    return wd_compute_metrics_form(ctx, desc, scheme, WD_METRICS_INVERSE, coords, period, out,
+                                   out_precision, stream);
 }
 
 int wd_autotune(wd_ctx *ctx, const wd_grid_desc *desc, const wd_method *method, void *phi,

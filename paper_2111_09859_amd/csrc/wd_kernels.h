@@ -89,6 +89,11 @@ void launch_convert(int src_fp64, int dst_fp64, const void *src, void *dst,
                     long long n, hipStream_t s);
 void launch_invert(const double *J, void *out, int out_fp64, int d,
                    long long N, hipStream_t s);
+// conservative metric form (3D): coordinate products, then the metrics from
+// their derivatives (layouts as in wd_compute_metrics_form)
+void launch_gcl_products(const double *x, const double *J, double *Q, long long N, hipStream_t s);
+void launch_gcl_combine(const double *J, const double *D, void *out, int out_fp64, long long N,
+                        hipStream_t s);
 void launch_poisson_dist(const GridDev *g, int fp64, long long N,
                          const double *phip, void *out, hipStream_t s);
 

@@ -838,6 +838,48 @@ __global__ void k_invert(const double *__restrict__ J, T *__restrict__ out, int 
     }
 }
 
+// Conservative metric form (3D): the coordinate products
+//   Q[p][m] = x_b J[a][p] - x_a J[b][p]   ((m, a, b) cyclic; J[a][p] = D_p x_a)
+// whose derivatives give J xi_{l,m} in curl form.
+__global__ void k_gcl_products(const double *__restrict__ x, const double *__restrict__ J,
+                               double *__restrict__ Q, long long N)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < N;
+         q += (long long)gridDim.x * blockDim.x) {
+        double xv[3], a[3][3];
+        for (int m = 0; m < 3; ++m) xv[m] = x[m * N + q];
+        for (int m = 0; m < 3; ++m)
+            for (int l = 0; l < 3; ++l) a[m][l] = J[(m * 3 + l) * N + q];
+        for (int p = 0; p < 3; ++p)
+            for (int m = 0; m < 3; ++m) {
+                const int ia = (m + 1) % 3, ib = (m + 2) % 3;
+                Q[(p * 3 + m) * N + q] = xv[ib] * a[ia][p] - xv[ia] * a[ib][p];
+            }
+    }
+}
+
+// xi_{l,m} = (D_q Q[p][m] - D_p Q[q][m]) / (2 det J)  ((l, p, q) cyclic);
+// D[(l * 3 + m) * 2] holds D_q Q[p][m], D[(l * 3 + m) * 2 + 1] D_p Q[q][m]
+template <typename T>
+__global__ void k_gcl_combine(const double *__restrict__ J, const double *__restrict__ D,
+                              T *__restrict__ out, long long N)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < N;
+         q += (long long)gridDim.x * blockDim.x) {
+        double a[3][3];
+        for (int m = 0; m < 3; ++m)
+            for (int l = 0; l < 3; ++l) a[m][l] = J[(m * 3 + l) * N + q];
+        const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1])
+                         - a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0])
+                         + a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+        for (int l = 0; l < 3; ++l)
+            for (int m = 0; m < 3; ++m) {
+                const int k = (l * 3 + m) * 2;
+                out[(l * 3 + m) * N + q] = (T)(0.5 * (D[k * N + q] - D[(k + 1) * N + q]) / det);
+            }
+    }
+}
+
 // distance = 2 phi' / (|grad phi'| + sqrt(|grad phi'|^2 + 2 phi')), the
 // cancellation-free form of Eq. Poiss2 with the minus sign, in FP64 from
 // g.F[l] (FP64, index space) and the metrics of grid g (T).
@@ -1011,6 +1053,22 @@ void launch_invert(const double *J, void *out, int out_fp64, int d, long long N,
         hipLaunchKernelGGL(k_invert<double>, grid, block, 0, s, J, (double *)out, d, N);
     else
         hipLaunchKernelGGL(k_invert<float>, grid, block, 0, s, J, (float *)out, d, N);
+}
+
+void launch_gcl_products(const double *x, const double *J, double *Q, long long N, hipStream_t s)
+{
+    dim3 grid(blocks_for(N)), block(kThreads);
+    hipLaunchKernelGGL(k_gcl_products, grid, block, 0, s, x, J, Q, N);
+}
+
+void launch_gcl_combine(const double *J, const double *D, void *out, int out_fp64, long long N,
+                        hipStream_t s)
+{
+    dim3 grid(blocks_for(N)), block(kThreads);
+    if (out_fp64)
+        hipLaunchKernelGGL(k_gcl_combine<double>, grid, block, 0, s, J, D, (double *)out, N);
+    else
+        hipLaunchKernelGGL(k_gcl_combine<float>, grid, block, 0, s, J, D, (float *)out, N);
 }
 
 void launch_poisson_dist(const GridDev *g, int fp64, long long N, const double *phip,
