@@ -1107,10 +1107,10 @@ static double point_accesses(const GridDev &g, int kind, int l, int stage)
     auto finish = [&](int src_counted) {
         double r = src_counted ? 0 : 1;            // stage value
         if (stage > 0) r += 1;                     // phi^n
-        if (rk4 && stage > 0) r += 1;              // acc read
+        if (rk4) r += 1;                           // acc read (stage 0: the carried remainder)
         if (stage > 0) r += 1;                     // dt read
         double w = 1;                              // new stage value
-        if (rk4 && stage < 3) w += 1;              // acc write
+        if (rk4) w += 1;                           // acc write (stage 3: the remainder)
         if (stage == 0) w += 1;                    // dt write
         if (g.lad) r += 1;                         // LAD field
         return r + w;

@@ -259,6 +259,7 @@ k_init(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             index_of(g, q, idx);
             const bool zero = !g.warm || wall_point(g, idx) || (g.mask && gmem(g.mask)[q]);
             if (zero) phi[q] = (T)0;
+            if (g.rk == 1) gcast<T>(g.acc)[q] = (T)0;   // no carried remainder yet
         }
         if (!g.uniform) {
             // element e of this chunk's point-major block: point e / dd,

@@ -612,7 +612,8 @@ template <typename T>
 struct FinIn {
     T pn;     // phi^n
     T dt;     // local step (stages > 0)
-    T acc;    // RK4 accumulator (stages > 0)
+    T acc;    // RK4 accumulator: the increment so far (stage 0: the
+              // remainder the previous iteration's rounding dropped)
 };
 
 template <typename T>
@@ -621,7 +622,7 @@ __device__ inline FinIn<T> fin_load(const GridDev &g, int stage, int q, T phis)
     FinIn<T> r;
     r.pn = stage == 0 ? phis : gcast<const T>(g.phi)[q];
     r.dt = stage == 0 ? (T)0 : gcast<const T>(g.dt)[q];
-    r.acc = (g.rk == 1 && stage > 0) ? gcast<const T>(g.acc)[q] : (T)0;
+    r.acc = g.rk == 1 ? gcast<const T>(g.acc)[q] : (T)0;
     return r;
 }
 
@@ -670,9 +671,16 @@ __device__ __forceinline__ T finish_point(const GridDev &g, int stage, int q, bo
     const T pn = in.pn;
     T out;
     if (g.rk == 1) {
+        // RK4 with the accumulator holding the iteration's increment
+        // dt (R1/6 + R2/3 + R3/3 + R4/6), added to phi^n once.  The part of
+        // it that this one rounding drops (exactly inc - (out - pn) when
+        // |inc| <= |pn|) is kept in the accumulator and starts the next
+        // iteration's increment, so a near-converged field does not stall
+        // where increments fall below half an ulp of phi (which biases the
+        // FP32 fixed point by about ulp(phi) / (2 dt) per point).
         gptr<T> acc = gcast<T>(g.acc);
         if (stage == 0) {
-            acc[q] = pn + dt * (T)(1.0 / 6.0) * R;
+            acc[q] = in.acc + dt * (T)(1.0 / 6.0) * R;
             out = pn + dt * (T)0.5 * R;
         } else if (stage == 1) {
             acc[q] = in.acc + dt * (T)(1.0 / 3.0) * R;
@@ -681,7 +689,10 @@ __device__ __forceinline__ T finish_point(const GridDev &g, int stage, int q, bo
             acc[q] = in.acc + dt * (T)(1.0 / 3.0) * R;
             out = pn + dt * R;
         } else {
-            out = in.acc + dt * (T)(1.0 / 6.0) * R;
+            const T inc = in.acc + dt * (T)(1.0 / 6.0) * R;
+            out = pn + inc;
+            const T kept = out - pn;
+            acc[q] = zero ? (T)0 : inc - kept;
         }
     } else {
         if (stage == 0)
