@@ -389,6 +389,8 @@ def run_cpu_baseline(spec, kw, iters, threads):
 
 
 ALPHA_F = 0.48   # filter coefficient of the batch and serving workloads
+BATCH_TOL = 1e-6
+BATCH_STALL = 200
 
 
 def method_for(spec, scheme, prec, **over):
@@ -418,7 +420,11 @@ def run_batch(args):
     mix = G.batch_mix(args.batch_count)
     s = api.Solver(0)
     p32 = [s.prepare(spec, sch, "fp32") for spec, sch in mix]
-    m32 = [method_for(spec, sch, "fp32") for spec, sch in mix]
+    # the batch's stopping rule: max change <= 1e-6 in both precisions (FP32
+    # with the stall window at its rounding floor), tight enough that the
+    # two runs' distances from their fixed points stay below the 1e-5
+    # accuracy bar
+    m32 = [method_for(spec, sch, "fp32", tol=BATCH_TOL, stall_window=BATCH_STALL) for spec, sch in mix]
     # tiles of about 2048 points: a full batch is throughput bound, so each
     # shape gets fewer, larger tiles than its solo latency optimum
     for p in p32:
@@ -434,7 +440,7 @@ def run_batch(args):
     seen = set()
     for (spec, sch), ph32 in zip(mix, out["phi"]):
         p = s.prepare(spec, sch, "fp64")
-        m = method_for(spec, sch, "fp64")
+        m = method_for(spec, sch, "fp64", tol=BATCH_TOL)
         if spec.n not in seen:      # same tile tuning as the batched run
             seen.add(spec.n)
             s.autotune(p, m, iters=4)
@@ -455,11 +461,12 @@ def run_batch(args):
     pts = sum(sp.npoints for sp, _ in mix)
     # "same stated accuracy": both runs finished (no divergence) and their
     # L-inf errors against the exact distance agree within 5 % or within the
-    # stopping tolerance; beside it, the FP32 field within 1e-5 relative of
-    # the FP64 one
+    # FP32 accuracy bar, 1e-5 of the field's largest value (the relative
+    # L-inf of every parity statement); beside it, the FP32 field within
+    # 1e-5 relative of the FP64 one
     ok = [i for i in range(len(mix)) if out["status"][i] >= 0 and st64[i] >= 0
-          and abs(e32[i] - e64[i]) <= 0.05 * e64[i] + 1e-5]
-    close = [i for i in range(len(mix)) if d3264[i] <= 1e-5 * max(1.0, max_abs64[i])]
+          and abs(e32[i] - e64[i]) <= 0.05 * e64[i] + 1e-5 * max_abs64[i]]
+    close = [i for i in range(len(mix)) if d3264[i] <= 1e-5 * max_abs64[i]]
     return {
         "metric": "solves/s (FP32 batched)", "value": len(mix) / t32, "unit": "solves/s",
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * t32,
@@ -719,16 +726,19 @@ def run_moving(args):
 
 
 def run_serve(args):
-    """Config 5 (bounded sample): open-loop Poisson arrivals (200 req/s) of
-    2D grids 129^2..2049^2 and 3D ducts 64^3..192^3 into the continuous-
-    batching server, beside 4 closed-loop warm-started star-grain sessions.
-    FP32, LAD pseudo-HJ, stop at max change <= 1e-5 (the paper's criterion)."""
+    """Config 5: open-loop Poisson arrivals (--serve-rate, default the
+    config's 200 req/s; a rate at or below the server's measured capacity
+    gives latencies of the server rather than of an overloaded queue) of
+    --serve-count 2D grids 129^2..2049^2 and 3D ducts 64^3..192^3 into the
+    continuous-batching server, beside 4 closed-loop warm-started
+    star-grain sessions of --serve-steps steps.  FP32, LAD pseudo-HJ, stop
+    at max change <= 1e-5 (the paper's criterion)."""
     import threading
     import torch
     from paper_2111_09859_amd import api, grids as G
     s = api.Solver(0)
     srv = api.Server(s, budget_bytes=args.serve_budget << 20, max_slots=64)
-    stream = G.serving_stream(count=args.serve_count)
+    stream = G.serving_stream(count=args.serve_count, rate=args.serve_rate)
     over = dict(tol=1e-5, stall_window=500, max_iter=20000)
     ids = []
     sess_lat = []
@@ -793,8 +803,11 @@ def run_serve(args):
         "metric": "served solves/s", "value": n / wall, "unit": "solves/s", "n_gpus": 1,
         "steps": 1, "warmup": 0, "ms_per_step": 1e3 * wall, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{len(ids)} Poisson-arrival requests (200/s) + 4 warm-started "
-                               f"star-grain sessions x {args.serve_steps} steps",
+        "config": {"workload": f"{len(ids)} Poisson-arrival requests ({args.serve_rate:g}/s) "
+                               f"+ 4 warm-started star-grain sessions x {args.serve_steps} steps",
+                   "arrival_rate_per_s": args.serve_rate, "requests": len(ids),
+                   "session_steps": args.serve_steps,
+                   "warm_restarts": st.get("restarts"),
                    "p50_latency_s": float(np.percentile(lat, 50)),
                    "p99_latency_s": float(np.percentile(lat, 99)),
                    "p50_queue_wait_s": float(np.percentile(qwait, 50)),
@@ -849,6 +862,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--serve-count", type=int, default=200)
     ap.add_argument("--serve-steps", type=int, default=10)
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="arrivals per second")
     ap.add_argument("--serve-budget", type=int, default=4096, help="arena MiB")
     ap.add_argument("--burn-n", type=int, default=1024)
     ap.add_argument("--burn-steps", type=int, default=500)
