@@ -1,6 +1,8 @@
 """Writes the stored expected values under tests/golden/ from the FP64
 oracle alone (plus the seeded grid generator).  Run from the repository
-root:  python tests/golden/make_golden.py  (about 15 minutes, one core).
+root:  python tests/golden/make_golden.py  (about 15 minutes on one core,
+a few on eight: the oracle shares its line and point loops among threads,
+with results independent of the thread count).
 
 cyl512x256_lad_curv_fp64.json: the 2D cylinder O-grid 512 x 256 (wall
 R = 0.5, far field r = 20, outflow faces, radial spacing 1e-3 * 1.03^j
@@ -10,7 +12,10 @@ phi = 0 until the max change is <= 1e-10 (Sec. 3.3-3.5): iteration count,
 L-inf error against r - R, the field on 8 theta-lines at every 4th radial
 node, and how far that field still is from the discrete fixed point
 (2000 further iterations).
+cyl512x256_lad_curv_fp64.f64.gz: that converged field at all 131,072
+points, float64 little-endian, r-major (index j * 512 + i), gzip.
 """
+import gzip
 import json
 import os
 import sys
@@ -50,6 +55,8 @@ def cylinder_config():
         "samples_i_j_phi": samples,
         "oracle_seconds": round(t1 - t0, 1),
     }
+    with gzip.GzipFile(os.path.join(HERE, "cyl512x256_lad_curv_fp64.f64.gz"), "wb", mtime=0) as f:
+        f.write(np.ascontiguousarray(phi, dtype="<f8").tobytes())
     with open(os.path.join(HERE, "cyl512x256_lad_curv_fp64.json"), "w") as f:
         json.dump(rec, f, indent=0)
         f.write("\n")
