@@ -773,6 +773,9 @@ def run_serve(args):
         spec = G.build_request(req)
         p = s.prepare(spec, req["scheme"], "fp32")
         ids.append((srv.submit(p, method_for(spec, req["scheme"], "fp32", **over)), spec))
+        if len(ids) % 10 == 0:
+            print(f"[serve] {len(ids)}/{len(stream)} requests submitted at "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     # requests finish out of order (smallest first): report the count done
     pending = [rid for rid, _ in ids]
     while pending:
