@@ -187,6 +187,7 @@ struct wd_ctx {
     size_t noalloc_bytes = 0;
     int use_seg = 1;                     // segmented passes on Cartesian grids
                                          // (16, 24, 32: segment length tried first)
+    int seg_split_finish = 1;            // 1: a pointwise pass finishes their stages
     std::map<wd::TuneKey, int> tune;
     std::vector<wd::CachedGraph> graphs;
     int profile = 0;

@@ -525,11 +525,28 @@ __device__ inline void seg_emit(gptr<T> f, int l, const SegGeo &sg, const Tile &
 }
 
 // ---------------------------------------------------------------------
+// read this lane's segment values back from the line buffer (positions
+// past a short segment's end repeat its last one)
+template <typename T, int M>
+__device__ inline void seg_get(const SegGeo &sg, const SegLane &L, const T *X, T (&x)[M])
+{
+    if (L.len == M) {
+        const int base = seg_slot<M>(sg, L.w, L.b);
+#pragma unroll
+        for (int i = 0; i < M; ++i) x[i] = X[base + i];
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) x[i] = X[seg_slot<M>(sg, L.w, L.b + min(i, L.len - 1))];
+}
+
 // Cartesian pass along direction l (uniform spacing, no curvature): U_l =
 // D_l phi / h_l and D_l U_l / h_l from one tile; partial sums |grad phi|^2
-// and Laplacian carried in HBM between the directions; the last direction
-// (LAST) finishes the stage (Sec. 3.3), with the extrapolated faces normal
-// to it when the grid keeps them there.
+// and Laplacian carried in HBM between the directions.  The last direction
+// (LAST) finishes the stage (Sec. 3.3) in place: each lane ends its own
+// segment's points (residual, local step at stage 0, RK update, walls and
+// solids) and, when the grid keeps its extrapolated faces normal to this
+// direction, the lanes holding a line's ends set them from the new values.
 template <typename T, int M, bool LAST>
 __global__ void __launch_bounds__(kSegThreads)
 k_seg_cart(const GridDev *__restrict__ grids, const Item *__restrict__ items, int nitems,
@@ -567,19 +584,6 @@ k_seg_cart(const GridDev *__restrict__ grids, const Item *__restrict__ items, in
         seg_window<T, M>(sg, L, n, per, X, v);
         seg_deriv_all<T, M>(g, v, L.len, lo, hi, x);
         seg_solve<T, M>(sg, op, tb, L, ih, x);                 // U_l
-        // |U_l|^2: registers (passes that carry the sums on), or a second
-        // line buffer read back by the stage finish
-        T u2[LAST ? 1 : M];
-        T *Y = X + sg.xsize;
-        if constexpr (LAST) {
-            T q2[M];
-#pragma unroll
-            for (int i = 0; i < M; ++i) q2[i] = x[i] * x[i];
-            seg_put<T, M>(sg, L, Y, q2);
-        } else {
-#pragma unroll
-            for (int i = 0; i < M; ++i) u2[i] = x[i] * x[i];
-        }
         if (g.need_lap) {
             __syncthreads();
             seg_put<T, M>(sg, L, X, x);
@@ -588,102 +592,71 @@ k_seg_cart(const GridDev *__restrict__ grids, const Item *__restrict__ items, in
             seg_deriv_all<T, M>(g, v, L.len, lo, hi, x);
             seg_solve<T, M>(sg, op, tb, L, ih, x);             // D_l U_l
         }
+        // U_l^2: U_l from the line buffer when it holds it (then it is not
+        // kept through the second solve), else x itself
+        T a[M];
+        if (g.need_lap) {
+            seg_get<T, M>(sg, L, X, a);
+#pragma unroll
+            for (int i = 0; i < M; ++i) a[i] = a[i] * a[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < M; ++i) a[i] = x[i] * x[i];
+        }
         gptr<T> P0 = gcast<T>(g.P[0]);
         gptr<T> P1 = gcast<T>(g.P[1]);
         if constexpr (!LAST) {
+            // carried sums, one field at a time
             if (l > 0) {
-                T a[M];
-                seg_read<T, M>(P0, L, P, a);
+                T b[M];
+                seg_read<T, M>(P0, L, P, b);
 #pragma unroll
-                for (int i = 0; i < M; ++i) u2[i] += a[i];
-                if (g.need_lap) {
-                    seg_read<T, M>(P1, L, P, a);
-#pragma unroll
-                    for (int i = 0; i < M; ++i) x[i] += a[i];
-                }
+                for (int i = 0; i < M; ++i) a[i] += b[i];
             }
-            seg_emit<T, M>(P0, l, sg, tl, L, P, X, u2);
-            if (g.need_lap) seg_emit<T, M>(P1, l, sg, tl, L, P, X, x);
+            seg_emit<T, M>(P0, l, sg, tl, L, P, X, a);
+            if (g.need_lap) {
+                if (l > 0) {
+                    T b[M];
+                    seg_read<T, M>(P1, L, P, b);
+#pragma unroll
+                    for (int i = 0; i < M; ++i) x[i] += b[i];
+                }
+                seg_emit<T, M>(P1, l, sg, tl, L, P, X, x);
+            }
         } else {
-        // stage finish (Sec. 3.3) element by element in the cooperative
-        // order (lanes on consecutive elements of the tile), eight at a time,
-        // from the two line buffers (|U_l|^2, D_l U_l) and the fields
-        __syncthreads();
-        seg_put<T, M>(sg, L, X, x);
-        __syncthreads();
-        T S1 = (T)0, S2 = (T)0;
-        for (int d = 0; d < g.ndim; ++d) {
-            S1 += (T)g.invh[d];
-            S2 += (T)g.invh[d] * (T)g.invh[d];
-        }
-        gptr<const T> P2 = gcast<const T>(g.P[2]);
-        gptr<const unsigned char> mk = gmem(g.mask);
-        gptr<T> ps = gcast<T>(g.ps);
-        const int nel = sg.W * n;
-        const float rw = 1.0f / (float)sg.W;
-        constexpr int B = 8;
-#pragma unroll 1
-        for (int c0 = 0; c0 < M; c0 += B) {
-            int qq[B], sl[B];
-            T ph[B], pg2[B], plap[B], plad[B];
-            FinIn<T> fin[B];
-            unsigned char solid[B];
+            // stage finish of the lane's own points, eight at a time
+            T S1 = (T)0, S2 = (T)0;
+            for (int d = 0; d < g.ndim; ++d) {
+                S1 += (T)g.invh[d];
+                S2 += (T)g.invh[d] * (T)g.invh[d];
+            }
+            gptr<const T> P2 = gcast<const T>(g.P[2]);
+            gptr<const unsigned char> mk = gmem(g.mask);
+            const bool sw = seg_side_wall(g, l, P);
+            bool z0 = false, z1 = false;
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const int e = (c0 + u) * kSegThreads + (int)threadIdx.x;
-                qq[u] = -1;
-                sl[u] = 0;
-                if (e >= nel) continue;
-                int w, j;
-                if (l == 0) {
-                    w = sdiv(e, tl.rn);
-                    j = e - w * n;
-                } else {
-                    j = sdiv(e, rw);
-                    w = e - j * sg.W;
-                }
-                if (w >= tl.wa) continue;
-                const int q = (int)tl.base + w * (int)tl.gw + j * (int)tl.gj;
-                qq[u] = q;
-                sl[u] = seg_slot<M>(sg, w, j);
-                ph[u] = src[q];
-                pg2[u] = l > 0 ? P0[q] : (T)0;
-                plap[u] = (l > 0 && g.need_lap) ? P1[q] : (T)0;
-                plad[u] = g.lad ? P2[q] : (T)0;
-                fin[u] = fin_load<T>(g, stage, q, ph[u]);
-                solid[u] = g.mask ? mk[q] : 0;
-            }
+            for (int c0 = 0; c0 < M; c0 += 8) {
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                if (qq[u] < 0) continue;
-                int idx[3];
-                index_of(g, qq[u], idx);
-                const bool z = solid[u] || wall_point(g, idx);
-                const T g2 = pg2[u] + Y[sl[u]];
-                const T lap = g.need_lap ? plap[u] + X[sl[u]] : (T)0;
-                const T nv = finish_point<T>(g, stage, qq[u], z, ph[u], g2, g2, lap, (T)0,
-                                             plad[u], S1, S2, fin[u]);
-                if (g.fuse_faces) X[sl[u]] = nv;
-                else ps[qq[u]] = nv;
-            }
-        }
-        if (g.fuse_faces) {
-            seg_faces<T, M>(g, sg, tl, l, X);
-#pragma unroll 1
-            for (int c = 0; c < M; ++c) {
-                const int e = c * kSegThreads + (int)threadIdx.x;
-                if (e >= nel) continue;
-                int w, j;
-                if (l == 0) {
-                    w = sdiv(e, tl.rn);
-                    j = e - w * n;
-                } else {
-                    j = sdiv(e, rw);
-                    w = e - j * sg.W;
+                for (int u = 0; u < 8; ++u) {
+                    const int i = c0 + u;
+                    if (!P.ok || i >= L.len) {
+                        x[i] = (T)0;
+                        continue;
+                    }
+                    const int q = P.q0 + i * P.gj;
+                    const T ph = src[q];
+                    const T g2 = a[i] + (l > 0 ? P0[q] : (T)0);
+                    const T lap = g.need_lap ? x[i] + (l > 0 ? P1[q] : (T)0) : (T)0;
+                    const T lad = g.lad ? P2[q] : (T)0;
+                    const FinIn<T> fin = fin_load<T>(g, stage, q, ph);
+                    const bool z = seg_zero(g, l, L, i, sw, g.mask ? mk[q] : (unsigned char)0);
+                    if (i == 0) z0 = z;
+                    if (i == M - 1) z1 = z;
+                    x[i] = finish_point<T>(g, stage, q, z, ph, g2, g2, lap, (T)0, lad, S1, S2, fin);
                 }
-                if (w < tl.wa) ps[(int)tl.base + w * (int)tl.gw + j * (int)tl.gj] = X[seg_slot<M>(sg, w, j)];
             }
-        }
+            if (g.fuse_faces) seg_face_fix<T, M>(g, l, lo, hi, z0, z1, x);
+            seg_write<T, M>(gcast<T>(g.ps), L, P, x);
         }
     }
 }
