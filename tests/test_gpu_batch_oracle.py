@@ -119,3 +119,38 @@ def test_served_grids_vs_oracle(solver, oracle, prec):
         assert srv.stats()["peak_active"] > 1
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_served_warm_session_step_vs_oracle(solver, oracle, prec):
+    """A warm-started session step through the server (the receding star
+    grain of Sec. 5.5): the previous step's field is the oracle's converged
+    field of the grain at step 0; the server advances the grain at step 4
+    from it for a fixed number of iterations, the oracle does the same from
+    the same start, and the two fields agree element by element."""
+    import torch
+    from paper_2111_09859_amd import api
+    kw = dict(eq="HJ", gamma="LAD", scheme="E6", eps=0.15)
+    s0, s1 = G.star_grain(64, step=0), G.star_grain(64, step=4)
+    prev, st, _, _ = oracle.solve(s0, omethod(oracle, tol=1e-10, max_iter=20000, **kw))
+    assert st == 0
+    n = 12
+    ref, _, it, h = oracle.solve(s1, omethod(oracle, fixed=n, **kw), phi0=prev)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    phi = torch.as_tensor(prev, dtype=dt, device=solver.device).contiguous()
+    srv = api.Server(solver, budget_bytes=256 << 20, max_slots=4)
+    try:
+        p = solver.prepare(s1, "E6", prec)
+        m = gmethod(tol=0.0, max_iter=n, precision=prec, **kw)
+        m.warm_start = 1
+        rid = srv.submit(p, m, phi=phi, session=5, hist_cap=n)
+        srv.wait(rid, 120.0)
+        assert srv.poll(rid)["iters"] == n
+        e = rel(phi.double().cpu().numpy(), ref)
+        say(f"[served warm step {prec}] star64 step 4 from step 0: rel_linf={e:.2e}")
+        assert e <= (FP64_TOL if prec == "fp64" else FP32_TOL)
+        if prec == "fp64":
+            hist = np.array(srv.history(rid, n)).reshape(-1, 2)
+            assert np.allclose(hist[:, 0], h[:, 0], rtol=1e-8, atol=1e-14)
+    finally:
+        srv.close()
