@@ -964,6 +964,19 @@ def main():
             "iters_per_solve": rc["iters"] / ca.steps, "status": rc["statuses"][-1],
             "linf_err_vs_exact": rc["err"], "stop": stop_rule("fp32", 0)}
         print("[bench] cylinder leg done", file=sys.stderr, flush=True)
+        # the same duct with the explicit E6 scheme (one pointwise pass per
+        # RK stage), FP32, 200 iterations per step
+        ea = argparse.Namespace(**vars(args))
+        ea.steps, ea.warmup = max(1, min(args.steps, 3)), 1
+        ekw = dict(kw, scheme="E6")
+        re6 = run_gpu(ea, spec, ekw, "fp32")
+        line["config"]["duct_e6"] = {
+            "workload": "the same duct and method with E6 explicit derivatives "
+                        "(one pointwise pass per RK stage)",
+            "value": spec.npoints * re6["iters"] / re6["time"], "unit": "point-updates/s",
+            "ms_per_iter": 1e3 * re6["time"] / re6["iters"], "steps": ea.steps,
+            "iters_per_step": re6["iters"] / ea.steps}
+        print("[bench] duct E6 leg done", file=sys.stderr, flush=True)
     line["roofline"] = roofline(r, spec, args.precision, f"{args.workload}-{args.precision}")
     if not args.no_cpu:
         model, ncpu, avail = cpu_info()

@@ -337,6 +337,15 @@ int wd_ctx_profile_read(wd_ctx *ctx, wd_kernel_stat *out, int cap, int *n);
  * Affects plans made after the call. */
 int wd_ctx_set_segmented(wd_ctx *ctx, int enable);
 
+/* enable != 0 (the default 1): uniform Cartesian grids with an explicit
+ * scheme (E2/E4/E6, Sec. 3.2) and no extrapolated face advance each RK
+ * stage in one pointwise pass: every point forms D_l phi and D_l D_l phi
+ * along each direction straight from its neighbours (the Laplacian's
+ * stencil is the first derivative's applied twice, closures included)
+ * and finishes the stage; 0: the directional line passes.  The results
+ * agree to rounding.  Affects plans made after the call. */
+int wd_ctx_set_explicit_onepass(wd_ctx *ctx, int enable);
+
 /* ---- host-side diagnostics ------------------------------------------ */
 /* Applies, on the host and in FP64 arithmetic, the parallel-cyclic-reduction
  * multipliers the kernels use for a line system (Sec. 3.2 compact first

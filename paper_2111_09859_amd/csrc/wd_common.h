@@ -135,6 +135,8 @@ struct GridDev {
     int seg;                  // 1: the segmented passes serve this grid
     int seg_split;            // 1: its last direction carries the sums on and
                               // a pointwise pass finishes the stage
+    int xstage;               // 1: explicit scheme, each stage one pointwise
+                              // pass (stage values alternate ps / P[0])
     SegGeo sgeo[3];
     SegOpDev sdop[3];         // segmented first-derivative operator
     SegOpDev sfop[3];         // segmented filter-correction operator

@@ -790,6 +790,13 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     case WD_C4: g.da = 1.5; g.dradius = 1; g.compact = 1; break;
     default: g.da = 14.0 / 9.0; g.db = 1.0 / 9.0; g.dradius = 2; g.compact = 1; break;
     }
+    // uniform Cartesian grid, explicit central scheme, no extrapolated
+    // face: each RK stage in one pointwise pass (lines of at least 4R + 2
+    // points, so that the two ends' closure rows never meet in a stencil)
+    g.xstage = ctx->use_xstage && g.mode == MODE_CART && !g.compact && !g.uw && !has_x;
+    for (int l = 0; l < d.ndim; ++l)
+        if (d.n[l] < 4 * g.dradius + 2) g.xstage = 0;
+    if ((double)N * (fp64 ? 8 : 4) >= 2147483648.0) g.xstage = 0;   // 32-bit buffer offsets
     const size_t f = (size_t)N * (fp64 ? 8 : 4);
     g.phi = phi;
     g.ps = take(f);
@@ -973,7 +980,7 @@ void build_items(Plan &P)
         }
         return li;
     };
-    auto cart = [](const GridDev &g) { return g.mode == MODE_CART && !g.seg; };
+    auto cart = [](const GridDev &g) { return g.mode == MODE_CART && !g.seg && !g.xstage; };
     // segmented pass: one list of the tiles of every segmented grid
     // segmented pass: one list per segment length M (16, 24, 32) present
     // among the segmented grids (the list's np field holds M)
@@ -994,15 +1001,21 @@ void build_items(Plan &P)
     };
     for (int l = 0; l < 3; ++l)
         seg_list(P.scart[l], PASS_SCART, l, 0, [l](const GridDev &g) {
-            return l < g.ndim - 1 || g.seg_split;
+            return !g.xstage && (l < g.ndim - 1 || g.seg_split);
         });
     for (int l = 0; l < 3; ++l)
         seg_list(P.scartl[l], PASS_SCART_LAST, l, 0, [l](const GridDev &g) {
-            return l == g.ndim - 1 && !g.seg_split;
+            return !g.xstage && l == g.ndim - 1 && !g.seg_split;
         });
     P.cfin = point_list(PASS_CFIN, 0, 0, [&](int i) {
-        return P.grids[i].seg_split ? P.grids[i].nchunks : 0;
+        return P.grids[i].seg_split && !P.grids[i].xstage ? P.grids[i].nchunks : 0;
     });
+    // one-pass explicit stages, one list per scheme radius (the list's l)
+    for (int r = 1; r <= 3; ++r)
+        P.xstage[r - 1] = point_list(PASS_XSTAGE, r, 0, [&](int i) {
+            const GridDev &g = P.grids[i];
+            return g.xstage && g.dradius == r ? g.nchunks : 0;
+        });
     for (int l = 0; l < 3; ++l)
         seg_list(P.slad0[l], PASS_SLAD, l, 0, [](const GridDev &g) { return g.lad != 0; });
     for (int l = 0; l < 3; ++l)
@@ -1092,6 +1105,7 @@ static const char *kind_name(int kind)
     case PASS_SCART: return "k_seg_cart";
     case PASS_SCART_LAST: return "k_seg_cart_fin";
     case PASS_CFIN: return "k_cart_finish";
+    case PASS_XSTAGE: return "k_xstage";
     case PASS_SFILTER: return "k_seg_filter";
     case PASS_SLAD: return "k_seg_lad";
     default: return "k_finalize";
@@ -1132,6 +1146,8 @@ static double point_accesses(const GridDev &g, int kind, int l, int stage)
     }
     case PASS_CFIN:
         return (1 + g.need_lap) + finish(0);       // the two sums + the finish's fields
+    case PASS_XSTAGE:
+        return finish(0);                          // the stage value (and its neighbours) + the finish's fields
     case PASS_D1:
         // phi in, F_l out; at stage 0 of an LAD grid the sensor part:
         // metrics in, sensor sum in (after the first direction) and out
@@ -1335,6 +1351,7 @@ void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s)
             issue_seg(ctx, P, P.scart[l], st, s);
             issue_seg(ctx, P, P.scartl[l], st, s);
         }
+        for (int r = 0; r < 3; ++r) issue_list(ctx, P, P.xstage[r], st, s);
         issue_list(ctx, P, P.cfin, st, s);
         for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, st == 0 ? P.d1[l] : P.d1n[l], st, s);
         issue_slot(ctx, P, P.d12, st, s);
@@ -2170,6 +2187,14 @@ int wd_ctx_set_segmented(wd_ctx *ctx, int enable)
     if (!ctx) return fail(WD_ERR_INVALID_ARG, "null context");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     ctx->use_seg = enable;
+    return WD_OK;
+}
+
+int wd_ctx_set_explicit_onepass(wd_ctx *ctx, int enable)
+{
+    if (!ctx) return fail(WD_ERR_INVALID_ARG, "null context");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->use_xstage = enable ? 1 : 0;
     return WD_OK;
 }
 

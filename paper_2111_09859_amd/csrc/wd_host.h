@@ -117,6 +117,7 @@ struct Plan {
     Slot scart[3], scartl[3], sfilt[3], slad0[3], slad1[3];  // segmented passes, one list per M
     int face[6], face_init[6];
     int fin = 0, resid = 0, init = 0, uwadv = 0, cfin = 0;
+    int xstage[3] = {0, 0, 0};   // one-pass explicit stages per scheme radius
     TableArena *arena = nullptr;   // line-operator tables of a call that allocates nothing
     GridDev *d_grids = nullptr;
     GridDev *d_aux = nullptr, *d_aux2 = nullptr;
@@ -188,6 +189,8 @@ struct wd_ctx {
     int use_seg = 1;                     // segmented passes on Cartesian grids
                                          // (16, 24, 32: segment length tried first)
     int seg_split_finish = 1;            // 1: a pointwise pass finishes their stages
+    int use_xstage = 1;                  // explicit schemes on Cartesian grids: one
+                                         // pointwise pass per RK stage
     std::map<wd::TuneKey, int> tune;
     std::vector<wd::CachedGraph> graphs;
     int profile = 0;

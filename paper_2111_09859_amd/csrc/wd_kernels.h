@@ -23,6 +23,8 @@ enum PassKind {
     PASS_SLAD = 13,
     PASS_SCART_LAST = 14,   // segmented Cartesian pass that finishes the stage
     PASS_CFIN = 15,         // pointwise stage finish of a segmented Cartesian grid
+    PASS_XSTAGE = 16,       // one-pass stage of an explicit-scheme Cartesian grid
+                            // (l = the scheme's radius)
 };
 
 // Segmented passes (segment length M = 16, 24 or 32): workgroups of one

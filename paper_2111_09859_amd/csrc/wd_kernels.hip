@@ -114,6 +114,216 @@ k_cart_finish(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     }
 }
 
+// ---------------------------------------------------------------------
+// One-pass RK stage of a uniform Cartesian grid with an explicit scheme
+// (E2/E4/E6, radius R; Sec. 3.2): every point forms U_l = D_l phi / h_l
+// and D_l U_l / h_l along each direction straight from the stage value's
+// neighbours (no line solve: D_l U_l at i needs U_l at i-R..i+R, which
+// need phi at i-2R..i+2R), sums |grad phi|^2 and the Laplacian and finishes
+// the stage.  The stage value is read from one buffer and written to
+// another (the stencil reads neighbours the pass also writes).
+
+// first derivative at end position a (index space, counted from a
+// non-periodic end: a = 0 is the end point) from e[] (phi at end positions
+// 0, 1, ...); rows within R of the end are the one-sided closures.  At the
+// high end the end coordinate runs against the index, so the derivative
+// there is the negative of this one (the second derivative is unchanged).
+template <typename T, int R, int A>
+__device__ inline T xend_row(const GridDev &g, const T *e)
+{
+    if (A < R) {
+        if (R == 1) return ((T)-3 * e[0] + (T)4 * e[1] - e[2]) * (T)0.5;
+        if (A == 0)
+            return ((T)-25 * e[0] + (T)48 * e[1] - (T)36 * e[2] + (T)16 * e[3] - (T)3 * e[4]) *
+                   (T)(1.0 / 12.0);
+        if (A == 1)
+            return ((T)-3 * e[0] - (T)10 * e[1] + (T)18 * e[2] - (T)6 * e[3] + e[4]) *
+                   (T)(1.0 / 12.0);
+        return (e[0] - (T)8 * e[1] + (T)8 * e[3] - e[4]) * (T)(1.0 / 12.0);
+    }
+    const T a = (T)(0.5 * g.da), b = (T)(0.25 * g.db), c = (T)(g.dc / 6.0);
+    T sum = a * (e[A + 1] - e[A - 1]);
+    if (R >= 2) sum += b * (e[A + 2] - e[A - 2]);
+    if (R >= 3) sum += c * (e[A + 3] - e[A - 3]);
+    return sum;
+}
+
+template <typename T, int R, int A>
+struct XEnd {
+    // lap[A'] for A' = 0 .. A-1 (compile-time recursion)
+    __device__ static void run(const GridDev &g, const T *Ue, T *lap)
+    {
+        XEnd<T, R, A - 1>::run(g, Ue, lap);
+        lap[A - 1] = xend_row<T, R, A - 1>(g, Ue);
+    }
+};
+template <typename T, int R>
+struct XEnd<T, R, 0> {
+    __device__ static void run(const GridDev &, const T *, T *) {}
+};
+
+template <typename T, int R, int A>
+struct XEndU {
+    __device__ static void run(const GridDev &g, const T *e, T *Ue)
+    {
+        XEndU<T, R, A - 1>::run(g, e, Ue);
+        Ue[A - 1] = xend_row<T, R, A - 1>(g, e);
+    }
+};
+template <typename T, int R>
+struct XEndU<T, R, 0> {
+    __device__ static void run(const GridDev &, const T *, T *) {}
+};
+
+// A field as a buffer resource (wave-uniform): an access is a per-lane
+// 32-bit byte offset plus a wave-uniform one, so the neighbours of a point
+// along a direction share one offset register and their strides are scalar.
+// The grids served here hold fewer than 2^31 bytes per field.
+struct XBuf {
+    __amdgpu_buffer_rsrc_t r;
+};
+
+template <typename T>
+__device__ __forceinline__ XBuf xbuf(const void *p, long long n)
+{
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0,
+                                              (int)(n * (long long)sizeof(T)), 0x00020000)};
+}
+
+template <typename T>
+__device__ __forceinline__ T xload(XBuf b, unsigned vo, unsigned so);
+template <>
+__device__ __forceinline__ float xload<float>(XBuf b, unsigned vo, unsigned so)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, vo, so, 0));
+}
+template <>
+__device__ __forceinline__ double xload<double>(XBuf b, unsigned vo, unsigned so)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, vo, so, 0));
+}
+
+// U_l and D_l U_l at point q (position i along l)
+template <typename T, int R>
+__device__ inline void xaxis(const GridDev &g, int l, gptr<const T> f, XBuf fb, long long q, int i,
+                             T &u, T &lap)
+{
+    const int n = g.n[l];
+    const long long st = g.stride[l];
+    const bool per = g.periodic[l] != 0;
+    const T ih = (T)g.invh[l];
+    const T a = (T)(0.5 * g.da), b = (T)(0.25 * g.db), c = (T)(g.dc / 6.0);
+    const bool inner = i >= 2 * R && i <= n - 1 - 2 * R;
+    if (per || inner) {
+        // interior (or periodic): phi at i-2R..i+2R, U at i-R..i+R
+        T v[4 * R + 1];
+        if (inner) {
+            // buffer loads from the stencil's first point: one offset
+            // register, scalar steps of the stride
+            constexpr unsigned E = sizeof(T);
+            const unsigned vo = (unsigned)(q - 2 * R * st) * E;
+#pragma unroll
+            for (int k = 0; k <= 4 * R; ++k) v[k] = xload<T>(fb, vo, (unsigned)(k * st) * E);
+        } else {
+#pragma unroll
+            for (int k = -2 * R; k <= 2 * R; ++k) {
+                int j = i + k;
+                j = j < 0 ? j + n : (j >= n ? j - n : j);
+                v[k + 2 * R] = f[q + (long long)(j - i) * st];
+            }
+        }
+        T U[2 * R + 1];
+#pragma unroll
+        for (int m = -R; m <= R; ++m) {
+            const int cj = 2 * R + m;
+            T sum = a * (v[cj + 1] - v[cj - 1]);
+            if (R >= 2) sum += b * (v[cj + 2] - v[cj - 2]);
+            if (R >= 3) sum += c * (v[cj + 3] - v[cj - 3]);
+            U[m + R] = sum * ih;
+        }
+        u = U[R];
+        T sl = a * (U[R + 1] - U[R - 1]);
+        if (R >= 2) sl += b * (U[R + 2] - U[R - 2]);
+        if (R >= 3) sl += c * (U[R + 3] - U[R - 3]);
+        lap = sl * ih;
+        return;
+    }
+    // within 2R of a non-periodic end: in end coordinates (a = 0 at the
+    // end, growing inward), phi at 0..4R, U at 0..max(3R, 5)-1, and the
+    // point's own row picked among the first 2R
+    const bool low = i < 2 * R;
+    const int ai = low ? i : n - 1 - i;
+    const T sgn = low ? (T)1 : (T)-1;
+    constexpr int NE = 4 * R + 1;
+    constexpr int NU = 3 * R > 5 ? 3 * R : 5;
+    T e[NE > NU + R ? NE : NU + R];
+#pragma unroll
+    for (int k = 0; k < (NE > NU + R ? NE : NU + R); ++k) {
+        const int pos = low ? min(k, n - 1) : max(n - 1 - k, 0);
+        e[k] = f[q + (long long)(pos - i) * st];
+    }
+    T Ue[NU];
+    XEndU<T, R, NU>::run(g, e, Ue);
+    T lp[2 * R];
+    XEnd<T, R, 2 * R>::run(g, Ue, lp);
+    T uu = Ue[0], ll = lp[0];
+#pragma unroll
+    for (int k = 1; k < 2 * R; ++k) {
+        uu = ai == k ? Ue[k] : uu;
+        ll = ai == k ? lp[k] : ll;
+    }
+    // U in index space; the second derivative is the same in both senses
+    u = sgn * uu * ih;
+    lap = ll * ih * ih;
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kThreads)
+k_xstage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int nitems,
+         int stage)
+{
+    int step, end;
+    for (int it = item_begin(nitems, step, end); it < end; it += step) {
+        const Item item = items[it];
+        const GridDev &g = grids[item.grid];
+        if (gmem(g.state)->done) continue;
+        T S1 = (T)0, S2 = (T)0;
+        for (int d = 0; d < g.ndim; ++d) {
+            S1 += (T)g.invh[d];
+            S2 += (T)g.invh[d] * (T)g.invh[d];
+        }
+        // stage values alternate between ps and P[0] so that the last
+        // stage ends in ps
+        const bool to_ps = ((g.stages - 1 - stage) & 1) == 0;
+        const void *srcp = stage == 0 ? g.phi : (to_ps ? g.P[0] : g.ps);
+        gptr<const T> src = gcast<const T>(srcp);
+        const XBuf sb = xbuf<T>(srcp, g.N);
+        gptr<T> dst = gcast<T>(to_ps ? g.ps : g.P[0]);
+        gptr<const T> P2 = gcast<const T>(g.P[2]);
+        gptr<const unsigned char> mk = gmem(g.mask);
+        const long long q0 = (long long)item.tile * kChunk;
+        for (int k = threadIdx.x; k < kChunk; k += kThreads) {
+            const long long q = q0 + k;
+            if (q >= g.N) break;
+            int idx[3];
+            index_of(g, q, idx);
+            T g2 = (T)0, lap = (T)0;
+            for (int l = 0; l < g.ndim; ++l) {
+                T u, lp;
+                xaxis<T, R>(g, l, src, sb, q, idx[l], u, lp);
+                g2 += u * u;
+                lap += lp;
+            }
+            const T ph = src[q];
+            const T lad = g.lad ? P2[q] : (T)0;
+            const FinIn<T> fin = fin_load<T>(g, stage, (int)q, ph);
+            const bool zero = (g.mask && mk[q]) || wall_point(g, idx);
+            dst[q] = finish_point<T>(g, stage, (int)q, zero, ph, g2, g2, g.need_lap ? lap : (T)0,
+                                     (T)0, lad, S1, S2, fin);
+        }
+    }
+}
+
 // Advective term of the upwind baseline for grids whose stage finish is
 // pointwise (Eikonal): P[1] <- U.grad(phi) of Eqs. UW1-UW5, uw2 <- |U|^2,
 // from the stage value, before the finish overwrites it.
@@ -917,6 +1127,12 @@ static void point_launch(int kind, const GridDev *g, const Item *it, int nitems,
     switch (kind) {
     case PASS_FINAL: hipLaunchKernelGGL(k_final<T>, grid, block, 0, s, g, it, nitems, stage); break;
     case PASS_CFIN: hipLaunchKernelGGL(k_cart_finish<T>, grid, block, 0, s, g, it, nitems, stage); break;
+    // explicit one-pass stages: l carries the scheme radius
+    case PASS_XSTAGE:
+        if (l == 1) hipLaunchKernelGGL((k_xstage<T, 1>), grid, block, 0, s, g, it, nitems, stage);
+        else if (l == 2) hipLaunchKernelGGL((k_xstage<T, 2>), grid, block, 0, s, g, it, nitems, stage);
+        else hipLaunchKernelGGL((k_xstage<T, 3>), grid, block, 0, s, g, it, nitems, stage);
+        break;
     case PASS_UWADV: hipLaunchKernelGGL(k_uwadv<T>, grid, block, 0, s, g, it, nitems, stage); break;
     case PASS_RESID: hipLaunchKernelGGL(k_resid<T>, grid, block, 0, s, g, it, nitems); break;
     case PASS_FACE: hipLaunchKernelGGL(k_face<T>, grid, block, 0, s, g, it, nitems, l, stage); break;
@@ -933,6 +1149,7 @@ void launch_pass(int kind, int fp64, int np, const GridDev *g, const Item *it, i
     switch (kind) {
     case PASS_FINAL:
     case PASS_CFIN:
+    case PASS_XSTAGE:
     case PASS_UWADV:
     case PASS_RESID:
     case PASS_FACE:

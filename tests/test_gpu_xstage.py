@@ -1,0 +1,121 @@
+"""GPU parity of the one-pass explicit RK stages (uniform Cartesian grids,
+E2/E4/E6, Sec. 3.2): every point forms D_l phi and D_l D_l phi from its
+neighbours, closure rows included, and finishes the stage in one pass.
+
+Each case runs with the one-pass stages (the default for these grids) and
+with the directional line passes, and once on the FP64 oracle, at equal
+iterations: FP64 relative L-inf <= 1e-12 against the oracle (with the
+change history) and between the two GPU paths; FP32 <= 1e-5.  Lines of
+4R + 2 points are the shortest the one-pass stage takes (every point then
+sits within 2R of an end, where the closure rows enter the composed
+stencil); one point fewer falls back to the line passes.
+"""
+import numpy as np
+import pytest
+
+from paper_2111_09859_amd import grids as G
+
+from test_gpu_parity import FP32_TOL, FP64_TOL, gpu_fixed, oracle_fixed, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2111_09859_amd import api
+    s = api.Solver(0)
+    yield s
+    s.close()
+
+
+def run_both(solver, spec, n, precision, kw):
+    from paper_2111_09859_amd import _lib as L
+    L.wd_ctx_set_explicit_onepass(solver.ctx, True)
+    one, out = gpu_fixed(solver, spec, n, precision=precision, **kw)
+    L.wd_ctx_set_explicit_onepass(solver.ctx, False)
+    try:
+        lines, _ = gpu_fixed(solver, spec, n, precision=precision, **kw)
+    finally:
+        L.wd_ctx_set_explicit_onepass(solver.ctx, True)
+    return one, lines, out
+
+
+def oracle_ref(O, spec, n, kw):
+    ref, h = oracle_fixed(O, spec, n, **kw)
+    if kw.get("eq") == "POISSON":
+        ref = O.poisson_distance(spec, kw["scheme"], ref)
+    return ref, h
+
+
+CASES = [
+    ("duct40x33x33_E4_lad", lambda: G.duct(33, nx=40),
+     dict(eq="HJ", gamma="LAD", scheme="E4", alpha_f=0.48), 25),
+    ("duct40x33x33_E6_poisson", lambda: G.duct(33, nx=40),
+     dict(eq="POISSON", scheme="E6", alpha_f=0.48), 25),
+    ("duct40x33x33_E2_linear_rk3", lambda: G.duct(33, nx=40),
+     dict(eq="HJ", gamma="LINEAR", scheme="E2", rk="RK3", eps=0.1, alpha_f=0.48), 25),
+    ("duct16x256x256_E6_lad", lambda: G.duct(256, nx=16),
+     dict(eq="HJ", gamma="LAD", scheme="E6", alpha_f=0.48), 4),
+    ("box100_E6_lad", lambda: G.box2d(100), dict(eq="HJ", gamma="LAD", scheme="E6", alpha_f=0.48), 12),
+    ("box100_E4_eikonal", lambda: G.box2d(100), dict(eq="EIKONAL", scheme="E4", alpha_f=0.48), 40),
+    ("star96_E6_lad_mask", lambda: G.star_grain(96),
+     dict(eq="HJ", gamma="LAD", scheme="E6", eps=0.15, alpha_f=0.48), 12),
+    ("channel129x65_E4_linear_rk3", lambda: G.channel(129, 65),
+     dict(eq="HJ", gamma="LINEAR", scheme="E4", rk="RK3", eps=0.1, alpha_f=0.495), 60),
+    # the shortest lines the one-pass stage takes: 4R + 2 points
+    ("box14_E6_linear", lambda: G.box2d(14), dict(eq="HJ", gamma="LINEAR", scheme="E6"), 30),
+    ("box10_E4_lad", lambda: G.box2d(10), dict(eq="HJ", gamma="LAD", scheme="E4"), 12),
+    ("box8_E2_linear", lambda: G.box2d(8), dict(eq="HJ", gamma="LINEAR", scheme="E2"), 30),
+    # one point short: the line passes serve it
+    ("box13_E6_linear", lambda: G.box2d(13), dict(eq="HJ", gamma="LINEAR", scheme="E6"), 30),
+]
+
+
+@pytest.mark.parametrize("name,mk,kw,n", CASES, ids=[c[0] for c in CASES])
+def test_onepass_fp64_vs_oracle(solver, oracle, name, mk, kw, n):
+    spec = mk()
+    say(f"[onepass fp64] {name} {spec.n[:spec.ndim]} iters={n}")
+    one, lines, out = run_both(solver, spec, n, "fp64", kw)
+    ref, h = oracle_ref(oracle, spec, n, kw)
+    e1, e2, e12 = rel(one, ref), rel(lines, ref), rel(one, lines)
+    say(f"  one-pass vs oracle {e1:.2e}, line passes vs oracle {e2:.2e}, between {e12:.2e}")
+    assert e1 <= FP64_TOL
+    assert e12 <= FP64_TOL
+    assert np.allclose(out["hist"][:, 0], h[:, 0], rtol=1e-8, atol=1e-14)
+
+
+FP32_CASES = [c for c in CASES if c[0] in ("duct40x33x33_E4_lad", "duct16x256x256_E6_lad",
+                                           "box100_E6_lad", "star96_E6_lad_mask",
+                                           "duct40x33x33_E6_poisson")]
+
+
+@pytest.mark.parametrize("name,mk,kw,n", FP32_CASES, ids=[c[0] for c in FP32_CASES])
+def test_onepass_fp32_vs_oracle(solver, oracle, name, mk, kw, n):
+    spec = mk()
+    say(f"[onepass fp32] {name}")
+    one, lines, _ = run_both(solver, spec, n, "fp32", kw)
+    ref, _ = oracle_ref(oracle, spec, n, kw)
+    e1 = rel(one, ref)
+    say(f"  one-pass vs oracle {e1:.2e}, line passes vs oracle {rel(lines, ref):.2e}")
+    assert e1 <= FP32_TOL
+
+
+def test_onepass_channel_config1_converged(solver, oracle):
+    """The 129 x 65 channel (standard HJ eps 0.1, E4, RK3, FP64 to 1e-10)
+    through the one-pass stages stops at the oracle's iteration with its
+    field."""
+    from test_gpu_parity import gmethod, omethod
+    spec = G.channel(129, 65)
+    kw = dict(eq="HJ", gamma="LINEAR", scheme="E4", rk="RK3", eps=0.1, alpha_f=0.495)
+    prep = solver.prepare(spec, "E4", "fp64")
+    out = solver.solve(prep, gmethod(tol=1e-10, **kw))
+    phi = out["phi"].double().cpu().numpy()
+    ref, st, it, _ = oracle.solve(spec, omethod(oracle, tol=1e-10, **kw))
+    say(f"[onepass converged] channel 129x65: gpu {out['iters']} iters, oracle {it}, "
+        f"rel {rel(phi, ref):.2e}")
+    assert out["status"] == 0 and st == 0
+    assert out["iters"] == it
+    assert rel(phi, ref) <= FP64_TOL
