@@ -873,6 +873,8 @@ def main():
     ap.add_argument("--burn-big-steps", type=int, default=40)
     ap.add_argument("--burn-big3", type=int, default=256)
     ap.add_argument("--moving-steps", type=int, default=24)
+    ap.add_argument("--scheme", default=None,
+                    help="derivative scheme in place of the workload's (E2, E4, E6, C4, C6)")
     ap.add_argument("--seg", type=int, default=1,
                     help="segmented Cartesian passes: 0 off, 1 auto, 16/24/32 segment length")
     args = ap.parse_args()
@@ -913,6 +915,9 @@ def main():
     spec, kw, desc = workload(args.workload)
     if args.alpha_f is not None:
         kw["alpha_f"] = args.alpha_f
+    if args.scheme:
+        kw["scheme"] = args.scheme
+        desc += f", scheme {args.scheme} in place of the above"
     desc += f", alpha_f {kw['alpha_f']}"
     print(f"[bench] {args.workload} {args.precision}: {args.warmup} + {args.steps} steps",
           file=sys.stderr, flush=True)

@@ -11,6 +11,7 @@ constexpr int kThreads = 512;             // threads per workgroup (8 waves)
 constexpr int kPPT = 8;                   // max points per thread in a tile
 constexpr int kTileMax = kThreads * kPPT; // max points held by one tile
 constexpr int kMaxLev = 14;               // max PCR levels of a line system
+constexpr int kXTX = 64, kXTY = 16;    // one-pass explicit stage: x-y tile
 constexpr int kChunk = 1024;              // points per pointwise work item
 constexpr int kMaxLine = kTileMax;        // longest grid line supported
 
@@ -137,6 +138,8 @@ struct GridDev {
                               // a pointwise pass finishes the stage
     int xstage;               // 1: explicit scheme, each stage one pointwise
                               // pass (stage values alternate ps / P[0])
+    int xkz, xkz2;            // z planes per item (chunk of the march) of its
+                              // fast and of its general tiles
     SegGeo sgeo[3];
     SegOpDev sdop[3];         // segmented first-derivative operator
     SegOpDev sfop[3];         // segmented filter-correction operator
@@ -146,6 +149,26 @@ struct GridDev {
     int ntiles[3];
     int nchunks;              // pointwise work items
 };
+
+// One-pass explicit stage tiles (kXTX x kXTY points of an x-y plane).
+// Origin of tile t along a direction of n points, tiles of w points: the
+// last tile is moved back to end at point n - 1 (it then covers points of
+// the tile before it and finishes only its own ones), so that the closure
+// rows of either end read points inside the tile and its halo.
+__host__ __device__ inline int xtile_origin(int t, int w, int n)
+{
+    const int e = n - w > 0 ? n - w : 0;
+    return t * w < e ? t * w : e;
+}
+
+// Whether x-y tile (x0, y0) of a grid is full and every U position it
+// forms along x and y takes the interior row: such tiles go to the fast
+// variant, the rest to the general one.
+__host__ __device__ inline bool xtile_fast(int x0, int y0, int n0, int n1, bool px, bool py, int R)
+{
+    return n0 >= kXTX && n1 >= kXTY && (px || (x0 >= 2 * R && x0 + kXTX + 2 * R <= n0)) &&
+           (py || (y0 >= 2 * R && y0 + kXTY + 2 * R <= n1));
+}
 
 struct Item {
     int grid;

@@ -797,6 +797,28 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
     for (int l = 0; l < d.ndim; ++l)
         if (d.n[l] < 4 * g.dradius + 2) g.xstage = 0;
     if ((double)N * (fp64 ? 8 : 4) >= 2147483648.0) g.xstage = 0;   // 32-bit buffer offsets
+    if (g.xstage) {
+        // x-y tiles of kXTX x kXTY points, fast (interior) and general ones;
+        // each kind's z march cut into chunks of at least 8 planes, as many
+        // as fit its kernel's resident workgroups in one round
+        const int ntx = (d.n[0] + kXTX - 1) / kXTX, nty = (d.n[1] + kXTY - 1) / kXTY;
+        const int n2 = d.ndim == 3 ? d.n[2] : 1;
+        int nf = 0;
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx)
+                nf += xtile_fast(xtile_origin(tx, kXTX, d.n[0]), xtile_origin(ty, kXTY, d.n[1]),
+                                 d.n[0], d.n[1], g.periodic[0] != 0, g.periodic[1] != 0,
+                                 g.dradius);
+        const int ng = ntx * nty - nf;
+        auto chunk = [&](int tiles, int fast) {
+            if (tiles == 0) return n2;
+            const int slots = ctx->cus * xstage_blocks_per_cu(fp64, g.dradius, fast);
+            const int nzc = std::max(1, std::min(slots / tiles, n2 / 8));
+            return (n2 + nzc - 1) / nzc;
+        };
+        g.xkz = chunk(nf, 1);
+        g.xkz2 = chunk(ng, 0);
+    }
     const size_t f = (size_t)N * (fp64 ? 8 : 4);
     g.phi = phi;
     g.ps = take(f);
@@ -1010,12 +1032,33 @@ void build_items(Plan &P)
     P.cfin = point_list(PASS_CFIN, 0, 0, [&](int i) {
         return P.grids[i].seg_split && !P.grids[i].xstage ? P.grids[i].nchunks : 0;
     });
-    // one-pass explicit stages, one list per scheme radius (the list's l)
+    // one-pass explicit stages: per scheme radius (the list's l) one list of
+    // general tiles (np 1) and one of fast tiles (np 2), each item a tile
+    // and a chunk of its z march
     for (int r = 1; r <= 3; ++r)
-        P.xstage[r - 1] = point_list(PASS_XSTAGE, r, 0, [&](int i) {
-            const GridDev &g = P.grids[i];
-            return g.xstage && g.dradius == r ? g.nchunks : 0;
-        });
+        for (int fast = 0; fast < 2; ++fast) {
+            const int li = add_list(PASS_XSTAGE, r, 0, 1 + fast);
+            for (int i = 0; i < n; ++i) {
+                const GridDev &g = P.grids[i];
+                if (!g.xstage || g.dradius != r) continue;
+                const int ntx = (g.n[0] + kXTX - 1) / kXTX, nty = (g.n[1] + kXTY - 1) / kXTY;
+                const int n2 = g.ndim == 3 ? g.n[2] : 1;
+                const int kz = fast ? g.xkz : g.xkz2;
+                const int nzc = (n2 + kz - 1) / kz;
+                for (int zc = 0; zc < nzc; ++zc)
+                    for (int ty = 0; ty < nty; ++ty)
+                        for (int tx = 0; tx < ntx; ++tx) {
+                            const bool f = xtile_fast(xtile_origin(tx, kXTX, g.n[0]),
+                                                      xtile_origin(ty, kXTY, g.n[1]), g.n[0],
+                                                      g.n[1], g.periodic[0] != 0,
+                                                      g.periodic[1] != 0, r);
+                            if (f != (fast != 0)) continue;
+                            P.items.push_back(Item{i, (zc * nty + ty) * ntx + tx});
+                            ++P.lists[li].count;
+                        }
+            }
+            P.xstage[r - 1][fast] = li;
+        }
     for (int l = 0; l < 3; ++l)
         seg_list(P.slad0[l], PASS_SLAD, l, 0, [](const GridDev &g) { return g.lad != 0; });
     for (int l = 0; l < 3; ++l)
@@ -1188,6 +1231,20 @@ static double launch_bytes(const Plan &P, const ItemList &L, int stage)
     if (L.kind == PASS_FACE) return 0.0;
     const double S = P.fp64 ? 8.0 : 4.0;
     double b = 0.0;
+    if (L.kind == PASS_XSTAGE) {
+        // the points each item finishes (its tile's own part of its chunk)
+        for (int i = 0; i < L.count; ++i) {
+            const Item &it = P.items[L.first + i];
+            const GridDev &g = P.grids[it.grid];
+            const int ntx = (g.n[0] + kXTX - 1) / kXTX, nty = (g.n[1] + kXTY - 1) / kXTY;
+            const int n2 = g.ndim == 3 ? g.n[2] : 1, kz = L.np == 2 ? g.xkz : g.xkz2;
+            const int tx = it.tile % ntx, ty = (it.tile / ntx) % nty, zc = it.tile / (ntx * nty);
+            const double pts = (double)std::min(kXTX, g.n[0] - tx * kXTX) *
+                               std::min(kXTY, g.n[1] - ty * kXTY) * std::min(kz, n2 - zc * kz);
+            b += pts * point_accesses(g, L.kind, L.l, stage) * S;
+        }
+        return b;
+    }
     int last_grid = -1;
     for (int i = 0; i < L.count; ++i) {
         const int gi = P.items[L.first + i].grid;
@@ -1251,12 +1308,15 @@ void prof_collect(wd_ctx *ctx)
 // once (its kernel's occupancy times the compute units), so a persistent
 // loop over more items never leaves a partial second round of workgroups;
 // pointwise passes get up to 4 (FP32) or 2 (FP64) per compute unit.
-static int nwg_for(wd_ctx *ctx, int fp64, int kind, int np, int count)
+static int nwg_for(wd_ctx *ctx, int fp64, int kind, int np, int count, int l = 0)
 {
     int per = fp64 ? 2 : 4;
     switch (kind) {
     case PASS_CART: case PASS_D1: case PASS_D2: case PASS_D12: case PASS_FILTER: case PASS_LAD:
         per = std::min(4, line_blocks_per_cu(kind, fp64, np));
+        break;
+    case PASS_XSTAGE:
+        per = xstage_blocks_per_cu(fp64, l, np == 2);
         break;
     default:
         break;
@@ -1283,6 +1343,9 @@ void issue_list(wd_ctx *ctx, const Plan &P, int li, int stage, hipStream_t s)
         case PASS_SCART_LAST: case PASS_SFILTER:
             name += "/d" + std::to_string(L.l);
             break;
+        case PASS_XSTAGE:
+            name += L.np == 2 ? "/fast" : "/edge";
+            break;
         default:
             break;
         }
@@ -1307,7 +1370,7 @@ void issue_list(wd_ctx *ctx, const Plan &P, int li, int stage, hipStream_t s)
                    lds, s);
     } else {
         launch_pass(L.kind, P.fp64, L.np, P.d_grids, P.d_items + L.first, L.count, L.l, arg,
-                    nwg_for(ctx, P.fp64, L.kind, L.np, L.count), s);
+                    nwg_for(ctx, P.fp64, L.kind, L.np, L.count, L.l), s);
     }
     if (ctx->profile) prof_end(ctx, pl, s);
 }
@@ -1351,7 +1414,8 @@ void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s)
             issue_seg(ctx, P, P.scart[l], st, s);
             issue_seg(ctx, P, P.scartl[l], st, s);
         }
-        for (int r = 0; r < 3; ++r) issue_list(ctx, P, P.xstage[r], st, s);
+        for (int r = 0; r < 3; ++r)
+            for (int f = 1; f >= 0; --f) issue_list(ctx, P, P.xstage[r][f], st, s);
         issue_list(ctx, P, P.cfin, st, s);
         for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, st == 0 ? P.d1[l] : P.d1n[l], st, s);
         issue_slot(ctx, P, P.d12, st, s);

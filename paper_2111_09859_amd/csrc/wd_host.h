@@ -117,7 +117,8 @@ struct Plan {
     Slot scart[3], scartl[3], sfilt[3], slad0[3], slad1[3];  // segmented passes, one list per M
     int face[6], face_init[6];
     int fin = 0, resid = 0, init = 0, uwadv = 0, cfin = 0;
-    int xstage[3] = {0, 0, 0};   // one-pass explicit stages per scheme radius
+    int xstage[3][2] = {};       // one-pass explicit stages per scheme radius:
+                                 // general and fast tiles
     TableArena *arena = nullptr;   // line-operator tables of a call that allocates nothing
     GridDev *d_grids = nullptr;
     GridDev *d_aux = nullptr, *d_aux2 = nullptr;

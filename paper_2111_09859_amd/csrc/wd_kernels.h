@@ -55,6 +55,9 @@ WD_LINE_LAUNCHER(line_launch_f64_4)
 WD_LINE_LAUNCHER(line_launch_f64_8)
 #undef WD_LINE_LAUNCHER
 // workgroups of a line pass's kernel that one compute unit holds at once
+// workgroups of the one-pass explicit stage (scheme radius r, general or
+// fast tiles) that one compute unit holds at once
+int xstage_blocks_per_cu(int fp64, int r, int fast);
 int line_blocks_per_cu(int kind, int fp64, int np);
 // level-set burnback (uniform grids)
 constexpr int kMaxLevels = 8;   // iso-values per length call

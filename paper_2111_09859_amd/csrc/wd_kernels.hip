@@ -9,6 +9,8 @@
 #include "wd_kernels.h"
 
 #include <algorithm>
+#include <climits>
+#include <atomic>
 #include <mutex>
 
 namespace wd {
@@ -190,6 +192,17 @@ __device__ __forceinline__ XBuf xbuf(const void *p, long long n)
                                               (int)(n * (long long)sizeof(T)), 0x00020000)};
 }
 
+// A resource over `bytes` bytes: an access at a per-lane offset at or
+// beyond that (kXOut, or any offset when bytes = 0) is out of range, which
+// the buffer unit answers with 0 for a load and drops for a store (no
+// memory is touched), so lanes without a point and fields a grid does not
+// use need no branch around their accesses.
+constexpr unsigned kXOut = 0x80000000u;
+__device__ __forceinline__ XBuf xbuf_bytes(const void *p, long long bytes)
+{
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000)};
+}
+
 template <typename T>
 __device__ __forceinline__ T xload(XBuf b, unsigned vo, unsigned so);
 template <>
@@ -201,6 +214,25 @@ template <>
 __device__ __forceinline__ double xload<double>(XBuf b, unsigned vo, unsigned so)
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, vo, so, 0));
+}
+
+__device__ __forceinline__ unsigned char xload_u8(XBuf b, unsigned vo, unsigned so)
+{
+    return __builtin_amdgcn_raw_buffer_load_b8(b.r, vo, so, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ void xstore(XBuf b, T v, unsigned vo, unsigned so);
+template <>
+__device__ __forceinline__ void xstore<float>(XBuf b, float v, unsigned vo, unsigned so)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.r, vo, so, 0);
+}
+template <>
+__device__ __forceinline__ void xstore<double>(XBuf b, double v, unsigned vo, unsigned so)
+{
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b.r, vo, so, 0);
 }
 
 // U_l and D_l U_l at point q (position i along l)
@@ -277,49 +309,441 @@ __device__ inline void xaxis(const GridDev &g, int l, gptr<const T> f, XBuf fb, 
     lap = ll * ih * ih;
 }
 
+// Tiles of the one-pass stage: kXTX x kXTY points of an x-y plane per
+// workgroup, marched along z over a chunk of planes.  The tile's stage
+// values and a halo of 2R points sit in LDS; U_x and U_y are formed there
+// once per position (the tile and a halo of R), so each point's D_l U_l
+// reads R neighbours of U on each side.  Along z every thread keeps a
+// queue of its columns' stage values (4R + 1 planes) and U_z (2R + 1
+// planes) in registers: a plane costs one new load and one new U_z per
+// point.  Planes within 2R of a non-periodic z end take their z terms from
+// the end-coordinate rows above instead.
+constexpr int kXRow = kThreads / kXTX;   // rows the threads cover at once
+constexpr int kXPY = kXTY / kXRow;       // points per thread and plane
+
 template <typename T, int R>
+struct XTile {
+    static constexpr int PW = kXTX + 4 * R, PH = kXTY + 4 * R;
+    static constexpr int UW = kXTX + 2 * R, UH = kXTY + 2 * R;
+    T ph[2][PH * PW];    // stage value at x0-2R .. x0+TX+2R-1, y0-2R .. y0+TY+2R-1
+                         // (this plane's and the next one's)
+    T ux[kXTY * UW];     // U_x at x0-R .. x0+TX+R-1 of rows y0 .. y0+TY-1
+    T uy[UH * kXTX];     // U_y at rows y0-R .. y0+TY+R-1 of columns x0 .. x0+TX-1
+};
+
+
+// D f at position j of a line of n points (index space, not scaled by
+// 1/h), f(m) the value at index m: the interior central row, or within R
+// of a non-periodic end that end's closure row over the points counted
+// from the end (negated at the high end, where that count runs against the
+// index).  The periodic rows read f at j - R .. j + R unwrapped: the
+// caller's f holds the wrapped values there.
+template <typename T>
+struct XCo {
+    T a, b, c;   // interior first-derivative weights of f(j +- 1, 2, 3)
+};
+
+template <typename T, int R, typename F>
+__device__ __forceinline__ T xrow(const GridDev &g, const XCo<T> &co, int j, int n, bool per,
+                                  const F &f)
+{
+    if (per || (j >= R && j <= n - 1 - R)) {
+        const T a = co.a, b = co.b, c = co.c;
+        T s = a * (f(j + 1) - f(j - 1));
+        if (R >= 2) s += b * (f(j + 2) - f(j - 2));
+        if (R >= 3) s += c * (f(j + 3) - f(j - 3));
+        return s;
+    }
+    const bool low = j < R;
+    const int A = low ? j : n - 1 - j;
+    T e[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) e[m] = (R == 1 && m > 2) ? (T)0 : f(low ? m : n - 1 - m);
+    T d;
+    if (R >= 3 && A == 2) d = xend_row<T, R, (R >= 3 ? 2 : 0)>(g, e);
+    else if (R >= 2 && A == 1) d = xend_row<T, R, (R >= 2 ? 1 : 0)>(g, e);
+    else d = xend_row<T, R, 0>(g, e);
+    return low ? d : -d;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ T xcentral(const XCo<T> &co, const T *v)
+{
+    // the interior row on v[0 .. 2R] (centre v[R])
+    const T a = co.a, b = co.b, c = co.c;
+    T s = a * (v[R + 1] - v[R - 1]);
+    if (R >= 2) s += b * (v[R + 2] - v[R - 2]);
+    if (R >= 3) s += c * (v[R + 3] - v[R - 3]);
+    return s;
+}
+
+// Workgroup barrier ordering LDS accesses only: global loads in flight
+// (the next plane's prefetch) stay in flight across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// U_z queue (3D grids): U_z of planes jb .. jb + 2R (index space, scaled
+// by 1/h_z) and the stage values of planes jb + R + 1 .. jb + 3R, from which
+// the next U_z follows with one more plane.  Filled from the stage values
+// around plane jb with each position's own row (closure rows of either
+// end from the end's five points); moved on one plane at a time while the
+// new position takes the interior row.
+template <typename T, int R>
+struct XZq {
+    T u[2 * R + 1];
+    T p[2 * R];
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void xz_fill(const GridDev &g, const XCo<T> &co, XBuf sb, unsigned vo,
+                                        int jb, int n2, int s2, bool pz, T ih2, XZq<T, R> &z)
+{
+    constexpr unsigned E = sizeof(T);
+    T v[4 * R + 1];
+#pragma unroll
+    for (int m = 0; m <= 4 * R; ++m) {
+        int kk = jb - R + m;
+        if (pz) kk = kk < 0 ? kk + n2 : (kk >= n2 ? kk - n2 : kk);
+        else kk = kk < 0 ? 0 : (kk >= n2 ? n2 - 1 : kk);
+        v[m] = xload<T>(sb, vo, (unsigned)(kk * s2) * E);
+    }
+#pragma unroll
+    for (int i = 0; i <= 2 * R; ++i) z.u[i] = xcentral<T, R>(co, &v[i]);
+    if (!pz && (jb < R || jb + 2 * R > n2 - 1 - R)) {
+        // closure rows: the five points of each end
+        T lo[5], hi[5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            const int a = min(m, n2 - 1), b = max(n2 - 1 - m, 0);
+            lo[m] = xload<T>(sb, vo, (unsigned)(a * s2) * E);
+            hi[m] = xload<T>(sb, vo, (unsigned)(b * s2) * E);
+        }
+        T cl[3], ch[3];
+        cl[0] = xend_row<T, R, 0>(g, lo);
+        ch[0] = -xend_row<T, R, 0>(g, hi);
+        cl[1] = cl[2] = ch[1] = ch[2] = (T)0;
+        if (R >= 2) {
+            cl[1] = xend_row<T, R, (R >= 2 ? 1 : 0)>(g, lo);
+            ch[1] = -xend_row<T, R, (R >= 2 ? 1 : 0)>(g, hi);
+        }
+        if (R >= 3) {
+            cl[2] = xend_row<T, R, (R >= 3 ? 2 : 0)>(g, lo);
+            ch[2] = -xend_row<T, R, (R >= 3 ? 2 : 0)>(g, hi);
+        }
+#pragma unroll
+        for (int i = 0; i <= 2 * R; ++i) {
+            const int j = jb + i, A = n2 - 1 - j;
+#pragma unroll
+            for (int a = 0; a < R; ++a) {
+                z.u[i] = j == a ? cl[a] : z.u[i];
+                z.u[i] = A == a ? ch[a] : z.u[i];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i <= 2 * R; ++i) z.u[i] *= ih2;
+#pragma unroll
+    for (int m = 0; m < 2 * R; ++m) z.p[m] = v[2 * R + 1 + m];
+}
+
+// u_z and D_z u_z at plane k from the queue (base jb: k - R inside,
+// 0 or n2 - 1 - 2R within R of a non-periodic end)
+template <typename T, int R>
+__device__ __forceinline__ void xz_terms(const GridDev &g, const XCo<T> &co, const XZq<T, R> &z,
+                                         int k, int jb, int n2, bool pz, T ih2, T &u2, T &l2)
+{
+    if (pz || (k >= R && k <= n2 - 1 - R)) {
+        u2 = z.u[R];
+        l2 = xcentral<T, R>(co, z.u) * ih2;
+        return;
+    }
+    const int d = k - jb;
+    T e[5];
+    const bool low = k < R;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) e[m] = low ? z.u[m < 2 * R + 1 ? m : 0] : z.u[2 * R - m >= 0 ? 2 * R - m : 0];
+    u2 = z.u[0];
+#pragma unroll
+    for (int i = 1; i <= 2 * R; ++i) u2 = d == i ? z.u[i] : u2;
+    const int A = low ? k : n2 - 1 - k;
+    T l = xend_row<T, R, 0>(g, e);
+    if (R >= 2 && A == 1) l = xend_row<T, R, (R >= 2 ? 1 : 0)>(g, e);
+    if (R >= 3 && A == 2) l = xend_row<T, R, (R >= 3 ? 2 : 0)>(g, e);
+    l2 = (low ? l : -l) * ih2;
+}
+
+// The interior row on values S apart around c[0].
+template <typename T, int R, int S>
+__device__ __forceinline__ T xcentral_at(const XCo<T> &co, const T *c)
+{
+    T v = co.a * (c[S] - c[-S]);
+    if (R >= 2) v += co.b * (c[2 * S] - c[-2 * S]);
+    if (R >= 3) v += co.c * (c[3 * S] - c[-3 * S]);
+    return v;
+}
+
+template <typename T, int R, bool FAST>
 __global__ void __launch_bounds__(kThreads)
 k_xstage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int nitems,
          int stage)
 {
+    using Tile = XTile<T, R>;
+    constexpr int PW = Tile::PW, PH = Tile::PH, UW = Tile::UW, UH = Tile::UH;
+    constexpr int NT = (PH * PW + kThreads - 1) / kThreads;       // tile loads per thread
+    constexpr int NUX = (kXTY * UW + kThreads - 1) / kThreads;    // U_x positions per thread
+    constexpr int NUY = (UH * kXTX + kThreads - 1) / kThreads;    // U_y positions per thread
+    constexpr unsigned E = sizeof(T);
+    __shared__ Tile sm;
+    const int tid = threadIdx.x, cx = tid % kXTX, r0 = tid / kXTX;
     int step, end;
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
         const GridDev &g = grids[item.grid];
         if (gmem(g.state)->done) continue;
+        const int n0 = g.n[0], n1 = g.n[1];
+        const bool d3 = g.ndim == 3;
+        const int n2 = d3 ? g.n[2] : 1;
+        const int ntx = (n0 + kXTX - 1) / kXTX, nty = (n1 + kXTY - 1) / kXTY;
+        const int tx = item.tile % ntx, ty = (item.tile / ntx) % nty;
+        const int zc = item.tile / (ntx * nty);
+        const int x0 = xtile_origin(tx, kXTX, n0), y0 = xtile_origin(ty, kXTY, n1);
+        const int wx = min(kXTX, n0), wy = min(kXTY, n1);
+        const int kz = FAST ? g.xkz : g.xkz2;
+        const int z0 = zc * kz, z1 = min(z0 + kz, n2);
+        const bool px = g.periodic[0] != 0, py = g.periodic[1] != 0;
+        const bool pz = d3 && g.periodic[2] != 0;
+        const int s1 = (int)g.stride[1], s2 = d3 ? (int)g.stride[2] : 0;
+        const T ih0 = (T)g.invh[0], ih1 = (T)g.invh[1], ih2 = (T)g.invh[2];
         T S1 = (T)0, S2 = (T)0;
         for (int d = 0; d < g.ndim; ++d) {
             S1 += (T)g.invh[d];
             S2 += (T)g.invh[d] * (T)g.invh[d];
         }
+        XCo<T> co;
+        co.a = (T)(0.5 * g.da);
+        co.b = (T)(0.25 * g.db);
+        co.c = (T)(g.dc / 6.0);
         // stage values alternate between ps and P[0] so that the last
         // stage ends in ps
         const bool to_ps = ((g.stages - 1 - stage) & 1) == 0;
         const void *srcp = stage == 0 ? g.phi : (to_ps ? g.P[0] : g.ps);
-        gptr<const T> src = gcast<const T>(srcp);
-        const XBuf sb = xbuf<T>(srcp, g.N);
-        gptr<T> dst = gcast<T>(to_ps ? g.ps : g.P[0]);
-        gptr<const T> P2 = gcast<const T>(g.P[2]);
-        gptr<const unsigned char> mk = gmem(g.mask);
-        const long long q0 = (long long)item.tile * kChunk;
-        for (int k = threadIdx.x; k < kChunk; k += kThreads) {
-            const long long q = q0 + k;
-            if (q >= g.N) break;
-            int idx[3];
-            index_of(g, q, idx);
-            T g2 = (T)0, lap = (T)0;
-            for (int l = 0; l < g.ndim; ++l) {
-                T u, lp;
-                xaxis<T, R>(g, l, src, sb, q, idx[l], u, lp);
-                g2 += u * u;
-                lap += lp;
+        const long long fb = g.N * (long long)E;
+        const XBuf sb = xbuf_bytes(srcp, fb);
+        const XBuf db = xbuf_bytes(to_ps ? g.ps : g.P[0], fb);
+        // the finish's other fields (zero-sized where the method does not
+        // use them); phi^n and the local step are read after stage 0, the
+        // local step written at stage 0 (offsets or-ed with kXOut select)
+        const XBuf pnb = xbuf_bytes(g.phi, stage > 0 ? fb : 0);
+        const XBuf dtb = xbuf_bytes(g.dt, fb);
+        const XBuf acb = xbuf_bytes(g.acc, g.rk == 1 ? fb : 0);
+        const XBuf ldb = xbuf_bytes(g.P[2], g.lad ? fb : 0);
+        const XBuf mkb = xbuf_bytes(g.mask, g.mask ? g.N : 0);
+        const unsigned dtl = stage > 0 ? 0u : kXOut, dts = stage == 0 ? 0u : kXOut;
+
+        // the tile's stage values: element tid + m kThreads of the LDS tile
+        // is read at byte offset toff[m] of each plane (kXOut: none)
+        unsigned toff[NT];
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+            const int e = tid + m * kThreads;
+            const int ey = e / PW, ex = e - ey * PW;
+            int jx = x0 - 2 * R + ex, jy = y0 - 2 * R + ey;
+            bool ok = e < PH * PW && ex < wx + 4 * R && ey < wy + 4 * R;
+            if (px) jx = jx < 0 ? jx + n0 : (jx >= n0 ? jx - n0 : jx);
+            else ok = ok && jx >= 0 && jx < n0;
+            if (py) jy = jy < 0 ? jy + n1 : (jy >= n1 ? jy - n1 : jy);
+            else ok = ok && jy >= 0 && jy < n1;
+            toff[m] = ok ? (unsigned)(jy * s1 + jx) * E : kXOut;
+        }
+        // this thread's points: column x0 + cx, rows y0 + r0 + kXRow p;
+        // byte offsets within a plane for loads (kXOut outside the grid)
+        // and for stores (kXOut unless the point is this tile's own)
+        const int gx = x0 + cx;
+        unsigned vin[kXPY], vown[kXPY];
+#pragma unroll
+        for (int p = 0; p < kXPY; ++p) {
+            const int ry = r0 + kXRow * p;
+            const bool in = cx < wx && ry < wy;
+            const bool own = in && gx >= tx * kXTX && y0 + ry >= ty * kXTY;
+            const unsigned off = (unsigned)((y0 + ry) * s1 + gx);
+            vin[p] = in ? off * E : kXOut;
+            vown[p] = own ? off * E : kXOut;
+        }
+        XZq<T, R> zq[kXPY];
+        int jb = INT_MIN;   // the queue's base plane (none yet)
+        T tv[NT];
+        auto tile_put = [&](T *ph) {
+#pragma unroll
+            for (int m = 0; m < NT; ++m)
+                if (m < NT - 1 || tid + m * kThreads < PH * PW) ph[tid + m * kThreads] = tv[m];
+        };
+        auto zbase = [&](int k) {
+            return pz ? k - R : min(max(k - R, 0), n2 - 1 - 2 * R);
+        };
+#pragma unroll
+        for (int m = 0; m < NT; ++m) tv[m] = xload<T>(sb, toff[m], (unsigned)(z0 * s2) * E);
+        lds_barrier();   // the previous item's reads of the tiles are done
+        tile_put(sm.ph[0]);
+        int cur = 0;
+        for (int k = z0; k < z1; ++k) {
+            const unsigned so = (unsigned)(k * s2) * E;
+            if (d3 && zbase(k) != jb) {
+                jb = zbase(k);
+#pragma unroll
+                for (int p = 0; p < kXPY; ++p)
+                    xz_fill<T, R>(g, co, sb, vin[p], jb, n2, s2, pz, ih2, zq[p]);
             }
-            const T ph = src[q];
-            const T lad = g.lad ? P2[q] : (T)0;
-            const FinIn<T> fin = fin_load<T>(g, stage, (int)q, ph);
-            const bool zero = (g.mask && mk[q]) || wall_point(g, idx);
-            dst[q] = finish_point<T>(g, stage, (int)q, zero, ph, g2, g2, g.need_lap ? lap : (T)0,
-                                     (T)0, lad, S1, S2, fin);
+            // the queue moves on after this plane when the next plane's base
+            // is one further and its new position takes the interior row
+            const bool adv = d3 && k + 1 < z1 && zbase(k + 1) == jb + 1 &&
+                             (pz || jb + 2 * R + 1 <= n2 - 1 - R);
+            // this plane's tile is in sm.ph[cur]; the previous plane's
+            // reads of U and of the other tile buffer are done
+            lds_barrier();
+            const T *ph = sm.ph[cur];
+            // issued now, used later in the plane: the finish inputs, the
+            // stage value the z queue takes in next, and the next plane's
+            // tile (every access unconditional: offsets and sizes select)
+            T fpn[kXPY], fdt[kXPY], fac[kXPY], fld[kXPY], znx[kXPY];
+            unsigned char fmk[kXPY];
+            int kn = adv ? jb + 3 * R + 1 : k;
+            kn = kn >= n2 ? kn - n2 : kn;
+#pragma unroll
+            for (int p = 0; p < kXPY; ++p) {
+                fpn[p] = xload<T>(pnb, vown[p], so);
+                fdt[p] = xload<T>(dtb, vown[p] | dtl, so);
+                fac[p] = xload<T>(acb, vown[p], so);
+                fld[p] = xload<T>(ldb, vown[p], so);
+                fmk[p] = xload_u8(mkb, vown[p] == kXOut ? kXOut : vown[p] / E, (unsigned)(k * s2));
+                znx[p] = xload<T>(sb, vin[p], (unsigned)(kn * s2) * E);
+            }
+            {
+                const unsigned sn = (unsigned)(min(k + 1, z1 - 1) * s2) * E;
+#pragma unroll
+                for (int m = 0; m < NT; ++m) tv[m] = xload<T>(sb, toff[m], sn);
+            }
+            if constexpr (FAST) {
+#pragma unroll
+                for (int i = 0; i < NUX; ++i) {
+                    const int e = tid + i * kThreads;
+                    if (i < NUX - 1 || e < kXTY * UW) {
+                        const int ry = e / UW, ex = e - ry * UW;
+                        sm.ux[e] = xcentral_at<T, R, 1>(co, ph + (ry + 2 * R) * PW + ex + R) * ih0;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < NUY; ++i) {
+                    const int e = tid + i * kThreads;
+                    if (i < NUY - 1 || e < UH * kXTX) {
+                        const int ey = e / kXTX, c = e - ey * kXTX;
+                        sm.uy[e] = xcentral_at<T, R, PW>(co, ph + (ey + R) * PW + c + 2 * R) * ih1;
+                    }
+                }
+            } else {
+                for (int e = tid; e < kXTY * UW; e += kThreads) {
+                    const int ry = e / UW, ex = e - ry * UW;
+                    const int jx = x0 - R + ex;
+                    T v = (T)0;
+                    if (ry < wy && ex < wx + 2 * R && (px || (jx >= 0 && jx < n0))) {
+                        const int base = (ry + 2 * R) * PW - (x0 - 2 * R);
+                        v = xrow<T, R>(g, co, jx, n0, px, [&](int m) { return ph[base + m]; }) *
+                            ih0;
+                    }
+                    sm.ux[e] = v;
+                }
+                for (int e = tid; e < UH * kXTX; e += kThreads) {
+                    const int ey = e / kXTX, c = e - ey * kXTX;
+                    const int jy = y0 - R + ey;
+                    T v = (T)0;
+                    if (c < wx && ey < wy + 2 * R && (py || (jy >= 0 && jy < n1))) {
+                        const int base = 2 * R + c - (y0 - 2 * R) * PW;
+                        v = xrow<T, R>(g, co, jy, n1, py,
+                                       [&](int m) { return ph[base + m * PW]; }) *
+                            ih1;
+                    }
+                    sm.uy[e] = v;
+                }
+            }
+            lds_barrier();
+            T out[kXPY], dto[kXPY], aco[kXPY];
+#pragma unroll
+            for (int p = 0; p < kXPY; ++p) {
+                const int ry = r0 + kXRow * p, gy = y0 + ry;
+                out[p] = dto[p] = aco[p] = (T)0;
+                if (FAST || vin[p] != kXOut) {
+                    // U and D U along x and y from the tile's U fields
+                    const T *ucx = sm.ux + ry * UW + cx + R;
+                    const T *ucy = sm.uy + (ry + R) * kXTX + cx;
+                    const T u0 = *ucx, u1 = *ucy;
+                    T l0, l1;
+                    if constexpr (FAST) {
+                        l0 = xcentral_at<T, R, 1>(co, ucx) * ih0;
+                        l1 = xcentral_at<T, R, kXTX>(co, ucy) * ih1;
+                    } else {
+                        const int ub = ry * UW - (x0 - R);
+                        l0 = xrow<T, R>(g, co, gx, n0, px, [&](int m) { return sm.ux[ub + m]; }) *
+                             ih0;
+                        const int vb = cx - (y0 - R) * kXTX;
+                        l1 = xrow<T, R>(g, co, gy, n1, py,
+                                        [&](int m) { return sm.uy[vb + m * kXTX]; }) *
+                             ih1;
+                    }
+                    T g2 = (T)0, lap = (T)0;
+                    g2 += u0 * u0;
+                    lap += l0;
+                    g2 += u1 * u1;
+                    lap += l1;
+                    if (d3) {
+                        T u2, l2;
+                        xz_terms<T, R>(g, co, zq[p], k, jb, n2, pz, ih2, u2, l2);
+                        g2 += u2 * u2;
+                        lap += l2;
+                    }
+                    const T phs = ph[(ry + 2 * R) * PW + cx + 2 * R];
+                    FinIn<T> fin;
+                    fin.pn = stage == 0 ? phs : fpn[p];
+                    fin.dt = fdt[p];
+                    fin.acc = fac[p];
+                    const int idx[3] = {gx, gy, k};
+                    const bool zero = fmk[p] != 0 || wall_point(g, idx);
+                    out[p] = finish_core<T>(g, stage, zero, phs, g2, g2,
+                                            g.need_lap ? lap : (T)0, (T)0, fld[p], S1, S2, fin,
+                                            dto[p], aco[p]);
+                }
+            }
+            // the next plane's tile into the other buffer (before this
+            // plane's stores, so that waiting for its loads waits for no
+            // store), then this plane's results
+            if (k + 1 < z1) tile_put(sm.ph[cur ^ 1]);
+            cur ^= 1;
+#pragma unroll
+            for (int p = 0; p < kXPY; ++p) {
+                xstore<T>(db, out[p], vown[p], so);
+                xstore<T>(dtb, dto[p], vown[p] | dts, so);
+                xstore<T>(acb, aco[p], vown[p], so);
+            }
+            // the z queue moves on by one plane
+            if (adv) {
+                ++jb;
+#pragma unroll
+                for (int p = 0; p < kXPY; ++p) {
+                    XZq<T, R> &z = zq[p];
+                    T v[2 * R + 1];
+#pragma unroll
+                    for (int m = 0; m < 2 * R; ++m) v[m] = z.p[m];
+                    v[2 * R] = znx[p];
+#pragma unroll
+                    for (int m = 0; m < 2 * R; ++m) z.u[m] = z.u[m + 1];
+                    z.u[2 * R] = xcentral<T, R>(co, v) * ih2;
+#pragma unroll
+                    for (int m = 0; m < 2 * R - 1; ++m) z.p[m] = z.p[m + 1];
+                    z.p[2 * R - 1] = znx[p];
+                }
+            }
         }
     }
 }
@@ -1121,7 +1545,7 @@ __global__ void k_poisson_dist(const GridDev *__restrict__ gp, const double *__r
 // launchers
 template <typename T>
 static void point_launch(int kind, const GridDev *g, const Item *it, int nitems,
-                         int l, int stage, int nwg, hipStream_t s)
+                         int l, int stage, int nwg, hipStream_t s, int np = 1)
 {
     dim3 grid(nwg), block(kThreads);
     switch (kind) {
@@ -1129,9 +1553,15 @@ static void point_launch(int kind, const GridDev *g, const Item *it, int nitems,
     case PASS_CFIN: hipLaunchKernelGGL(k_cart_finish<T>, grid, block, 0, s, g, it, nitems, stage); break;
     // explicit one-pass stages: l carries the scheme radius
     case PASS_XSTAGE:
-        if (l == 1) hipLaunchKernelGGL((k_xstage<T, 1>), grid, block, 0, s, g, it, nitems, stage);
-        else if (l == 2) hipLaunchKernelGGL((k_xstage<T, 2>), grid, block, 0, s, g, it, nitems, stage);
-        else hipLaunchKernelGGL((k_xstage<T, 3>), grid, block, 0, s, g, it, nitems, stage);
+        if (np == 2) {
+            if (l == 1) hipLaunchKernelGGL((k_xstage<T, 1, true>), grid, block, 0, s, g, it, nitems, stage);
+            else if (l == 2) hipLaunchKernelGGL((k_xstage<T, 2, true>), grid, block, 0, s, g, it, nitems, stage);
+            else hipLaunchKernelGGL((k_xstage<T, 3, true>), grid, block, 0, s, g, it, nitems, stage);
+        } else {
+            if (l == 1) hipLaunchKernelGGL((k_xstage<T, 1, false>), grid, block, 0, s, g, it, nitems, stage);
+            else if (l == 2) hipLaunchKernelGGL((k_xstage<T, 2, false>), grid, block, 0, s, g, it, nitems, stage);
+            else hipLaunchKernelGGL((k_xstage<T, 3, false>), grid, block, 0, s, g, it, nitems, stage);
+        }
         break;
     case PASS_UWADV: hipLaunchKernelGGL(k_uwadv<T>, grid, block, 0, s, g, it, nitems, stage); break;
     case PASS_RESID: hipLaunchKernelGGL(k_resid<T>, grid, block, 0, s, g, it, nitems); break;
@@ -1154,8 +1584,8 @@ void launch_pass(int kind, int fp64, int np, const GridDev *g, const Item *it, i
     case PASS_RESID:
     case PASS_FACE:
     case PASS_INIT:
-        if (fp64) point_launch<double>(kind, g, it, nitems, l, stage, nwg, s);
-        else point_launch<float>(kind, g, it, nitems, l, stage, nwg, s);
+        if (fp64) point_launch<double>(kind, g, it, nitems, l, stage, nwg, s, np);
+        else point_launch<float>(kind, g, it, nitems, l, stage, nwg, s, np);
         return;
     default:
         break;
@@ -1175,6 +1605,33 @@ void launch_pass(int kind, int fp64, int np, const GridDev *g, const Item *it, i
         default: line_launch_f32_8(kind, g, it, nitems, l, stage, nwg, s); break;
         }
     }
+}
+
+template <typename T>
+static const void *xstage_fn(int r, bool fast)
+{
+    if (fast)
+        return r == 1 ? reinterpret_cast<const void *>(&k_xstage<T, 1, true>)
+             : r == 2 ? reinterpret_cast<const void *>(&k_xstage<T, 2, true>)
+                      : reinterpret_cast<const void *>(&k_xstage<T, 3, true>);
+    return r == 1 ? reinterpret_cast<const void *>(&k_xstage<T, 1, false>)
+         : r == 2 ? reinterpret_cast<const void *>(&k_xstage<T, 2, false>)
+                  : reinterpret_cast<const void *>(&k_xstage<T, 3, false>);
+}
+
+int xstage_blocks_per_cu(int fp64, int r, int fast)
+{
+    static std::atomic<int> cache[2][3][2];
+    if (r < 1 || r > 3) return 1;
+    std::atomic<int> &c = cache[fp64 ? 1 : 0][r - 1][fast ? 1 : 0];
+    int v = c.load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    const void *f = fp64 ? xstage_fn<double>(r, fast != 0) : xstage_fn<float>(r, fast != 0);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kThreads, 0) != hipSuccess) n = 0;
+    v = std::max(1, n);
+    c.store(v, std::memory_order_relaxed);
+    return v;
 }
 
 int line_blocks_per_cu(int kind, int fp64, int np)

@@ -626,13 +626,15 @@ __device__ inline FinIn<T> fin_load(const GridDev &g, int stage, int q, T phis)
     return r;
 }
 
-// Residual of the chosen equation, local time step at stage 0 (stored),
-// RK stage combination (accumulator stored), walls/solids; returns the new
-// stage value (the caller stores it).  g2 = |U|^2, adv = U.grad(phi)
-// (= g2 for the central schemes; the upwind product for the baseline).
+// Residual of the chosen equation, local time step at stage 0, RK stage
+// combination, walls/solids; returns the new stage value and gives the
+// local step to store (stage 0) and the accumulator to store (RK4); the
+// caller stores all three.  g2 = |U|^2, adv = U.grad(phi) (= g2 for the
+// central schemes; the upwind product for the baseline).
 template <typename T>
-__device__ __forceinline__ T finish_point(const GridDev &g, int stage, int q, bool zero, T phis,
-                          T g2, T adv, T lap, T kap, T lads, T S1, T S2, const FinIn<T> &in)
+__device__ __forceinline__ T finish_core(const GridDev &g, int stage, bool zero, T phis, T g2,
+                                         T adv, T lap, T kap, T lads, T S1, T S2,
+                                         const FinIn<T> &in, T &dt_out, T &acc_out)
 {
     const T gm = sqrt(g2);
     T gam = (T)0, nu = (T)0, R;
@@ -664,7 +666,7 @@ __device__ __forceinline__ T finish_point(const GridDev &g, int stage, int q, bo
         else
             den = (T)2 * kp * S1 * gmx + kp2 * kp2 * (gam + nu) * S2;
         dt = (T)g.sigma / den;
-        gcast<T>(g.dt)[q] = dt;
+        dt_out = dt;
     } else {
         dt = in.dt;
     }
@@ -678,21 +680,20 @@ __device__ __forceinline__ T finish_point(const GridDev &g, int stage, int q, bo
         // iteration's increment, so a near-converged field does not stall
         // where increments fall below half an ulp of phi (which biases the
         // FP32 fixed point by about ulp(phi) / (2 dt) per point).
-        gptr<T> acc = gcast<T>(g.acc);
         if (stage == 0) {
-            acc[q] = in.acc + dt * (T)(1.0 / 6.0) * R;
+            acc_out = in.acc + dt * (T)(1.0 / 6.0) * R;
             out = pn + dt * (T)0.5 * R;
         } else if (stage == 1) {
-            acc[q] = in.acc + dt * (T)(1.0 / 3.0) * R;
+            acc_out = in.acc + dt * (T)(1.0 / 3.0) * R;
             out = pn + dt * (T)0.5 * R;
         } else if (stage == 2) {
-            acc[q] = in.acc + dt * (T)(1.0 / 3.0) * R;
+            acc_out = in.acc + dt * (T)(1.0 / 3.0) * R;
             out = pn + dt * R;
         } else {
             const T inc = in.acc + dt * (T)(1.0 / 6.0) * R;
             out = pn + inc;
             const T kept = out - pn;
-            acc[q] = zero ? (T)0 : inc - kept;
+            acc_out = zero ? (T)0 : inc - kept;
         }
     } else {
         if (stage == 0)
@@ -703,6 +704,20 @@ __device__ __forceinline__ T finish_point(const GridDev &g, int stage, int q, bo
             out = pn * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * (phis + dt * R);
     }
     return zero ? (T)0 : out;
+}
+
+// finish_core with the local step (stage 0) and the RK4 accumulator stored
+// at point q; returns the new stage value (the caller stores it).
+template <typename T>
+__device__ __forceinline__ T finish_point(const GridDev &g, int stage, int q, bool zero, T phis,
+                                          T g2, T adv, T lap, T kap, T lads, T S1, T S2,
+                                          const FinIn<T> &in)
+{
+    T dt = (T)0, acc = (T)0;
+    const T out = finish_core<T>(g, stage, zero, phis, g2, adv, lap, kap, lads, S1, S2, in, dt, acc);
+    if (stage == 0) gcast<T>(g.dt)[q] = dt;
+    if (g.rk == 1) gcast<T>(g.acc)[q] = acc;
+    return out;
 }
 
 // Per-point metric values are kept as m[3*l + c] = d xi_l / d x_c (fixed

@@ -9,6 +9,13 @@ change history) and between the two GPU paths; FP32 <= 1e-5.  Lines of
 4R + 2 points are the shortest the one-pass stage takes (every point then
 sits within 2R of an end, where the closure rows enter the composed
 stencil); one point fewer falls back to the line passes.
+
+The stage works on 64 x 16 tiles of x-y planes marched along z in chunks:
+tiles whose U positions all take the interior row go to the fast variant,
+the rest to the general one, and the z queue is refilled with closure rows
+near non-periodic z ends.  The 64 x 40 x 40 duct has both kinds of tile
+and five z chunks (refills at both ends); the slab is periodic in x and z
+(the queue wraps); the 200^2 box has fast tiles with non-periodic x.
 """
 import numpy as np
 import pytest
@@ -50,7 +57,30 @@ def oracle_ref(O, spec, n, kw):
     return ref, h
 
 
+def slab(nx=64, ny=40, nz=24):
+    """Uniform box periodic in x and z, walls y = 0, 1 (exact min(y, 1-y))."""
+    dy = 1.0 / (ny - 1)
+    y = np.arange(ny) * dy
+    ex = np.broadcast_to(np.minimum(y, 1.0 - y)[None, :, None], (nz, ny, nx)).copy()
+    return G.GridSpec("slab", 3, (nx, ny, nz),
+                      ((G.PERIODIC, G.PERIODIC), (G.WALL, G.WALL), (G.PERIODIC, G.PERIODIC)),
+                      h=(1.0 / nx, dy, 1.0 / nz), exact=ex)
+
+
 CASES = [
+    ("duct64x40x40_E6_lad", lambda: G.duct(40, nx=64),
+     dict(eq="HJ", gamma="LAD", scheme="E6", alpha_f=0.48), 12),
+    ("duct64x40x40_E4_linear_rk3", lambda: G.duct(40, nx=64),
+     dict(eq="HJ", gamma="LINEAR", scheme="E4", rk="RK3", eps=0.1, alpha_f=0.48), 25),
+    ("duct64x40x40_E2_poisson", lambda: G.duct(40, nx=64),
+     dict(eq="POISSON", scheme="E2", alpha_f=0.48), 25),
+    ("slab64x40x24_E6_lad", slab, dict(eq="HJ", gamma="LAD", scheme="E6", alpha_f=0.48), 12),
+    ("slab64x40x24_E4_eikonal", slab, dict(eq="EIKONAL", scheme="E4", alpha_f=0.48), 30),
+    ("box200_E6_linear", lambda: G.box2d(200),
+     dict(eq="HJ", gamma="LINEAR", scheme="E6", eps=0.1, alpha_f=0.48), 20),
+    # LAD on this grid: a few iterations (the sensor amplifies rounding-order
+    # differences between any two summation orders while the front moves)
+    ("box200_E6_lad", lambda: G.box2d(200), dict(eq="HJ", gamma="LAD", scheme="E6", alpha_f=0.48), 4),
     ("duct40x33x33_E4_lad", lambda: G.duct(33, nx=40),
      dict(eq="HJ", gamma="LAD", scheme="E4", alpha_f=0.48), 25),
     ("duct40x33x33_E6_poisson", lambda: G.duct(33, nx=40),
@@ -89,7 +119,8 @@ def test_onepass_fp64_vs_oracle(solver, oracle, name, mk, kw, n):
 
 FP32_CASES = [c for c in CASES if c[0] in ("duct40x33x33_E4_lad", "duct16x256x256_E6_lad",
                                            "box100_E6_lad", "star96_E6_lad_mask",
-                                           "duct40x33x33_E6_poisson")]
+                                           "duct40x33x33_E6_poisson", "duct64x40x40_E6_lad",
+                                           "slab64x40x24_E6_lad", "box200_E6_lad")]
 
 
 @pytest.mark.parametrize("name,mk,kw,n", FP32_CASES, ids=[c[0] for c in FP32_CASES])
