@@ -486,6 +486,15 @@ __device__ __forceinline__ T xcentral_at(const XCo<T> &co, const T *c)
     return v;
 }
 
+// The method's fields the stage finish reads, held by the one-pass stage
+// for the item it works on (already in T: the same values the finish
+// forms from the grid record).
+template <typename T>
+struct XFin {
+    int eq, lad, curv, rk;
+    T eps, nu0, kp, kp2, sigma;
+};
+
 template <typename T, int R, bool FAST>
 __global__ void __launch_bounds__(kThreads)
 k_xstage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int nitems,
@@ -527,6 +536,19 @@ k_xstage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int 
         co.a = (T)(0.5 * g.da);
         co.b = (T)(0.25 * g.db);
         co.c = (T)(g.dc / 6.0);
+        XFin<T> fp;
+        fp.eq = g.eq;
+        fp.lad = g.lad;
+        fp.curv = g.curv;
+        fp.rk = g.rk;
+        fp.eps = (T)g.eps;
+        fp.nu0 = (T)g.nu0;
+        fp.kp = (T)g.kp;
+        fp.kp2 = (T)g.kp2;
+        fp.sigma = (T)g.sigma;
+        const bool need_lap = g.need_lap != 0;
+        // walls on the faces normal to z (the x and y ones are per point)
+        const bool wz_lo = d3 && g.wall_lo[2], wz_hi = d3 && g.wall_hi[2];
         // stage values alternate between ps and P[0] so that the last
         // stage ends in ps
         const bool to_ps = ((g.stages - 1 - stage) & 1) == 0;
@@ -564,14 +586,17 @@ k_xstage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int 
         // and for stores (kXOut unless the point is this tile's own)
         const int gx = x0 + cx;
         unsigned vin[kXPY], vown[kXPY];
+        bool wxy[kXPY];   // the point lies on a wall normal to x or y
 #pragma unroll
         for (int p = 0; p < kXPY; ++p) {
-            const int ry = r0 + kXRow * p;
+            const int ry = r0 + kXRow * p, gy = y0 + ry;
             const bool in = cx < wx && ry < wy;
-            const bool own = in && gx >= tx * kXTX && y0 + ry >= ty * kXTY;
-            const unsigned off = (unsigned)((y0 + ry) * s1 + gx);
+            const bool own = in && gx >= tx * kXTX && gy >= ty * kXTY;
+            const unsigned off = (unsigned)(gy * s1 + gx);
             vin[p] = in ? off * E : kXOut;
             vown[p] = own ? off * E : kXOut;
+            wxy[p] = (gx == 0 && g.wall_lo[0]) || (gx == n0 - 1 && g.wall_hi[0]) ||
+                     (gy == 0 && g.wall_lo[1]) || (gy == n1 - 1 && g.wall_hi[1]);
         }
         XZq<T, R> zq[kXPY];
         int jb = INT_MIN;   // the queue's base plane (none yet)
@@ -708,11 +733,10 @@ k_xstage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int 
                     fin.pn = stage == 0 ? phs : fpn[p];
                     fin.dt = fdt[p];
                     fin.acc = fac[p];
-                    const int idx[3] = {gx, gy, k};
-                    const bool zero = fmk[p] != 0 || wall_point(g, idx);
-                    out[p] = finish_core<T>(g, stage, zero, phs, g2, g2,
-                                            g.need_lap ? lap : (T)0, (T)0, fld[p], S1, S2, fin,
-                                            dto[p], aco[p]);
+                    const bool zero = fmk[p] != 0 || wxy[p] || (k == 0 && wz_lo) ||
+                                      (k == n2 - 1 && wz_hi);
+                    out[p] = finish_core<T>(fp, stage, zero, phs, g2, g2, need_lap ? lap : (T)0,
+                                            (T)0, fld[p], S1, S2, fin, dto[p], aco[p]);
                 }
             }
             // the next plane's tile into the other buffer (before this

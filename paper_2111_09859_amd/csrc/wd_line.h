@@ -630,9 +630,11 @@ __device__ inline FinIn<T> fin_load(const GridDev &g, int stage, int q, T phis)
 // combination, walls/solids; returns the new stage value and gives the
 // local step to store (stage 0) and the accumulator to store (RK4); the
 // caller stores all three.  g2 = |U|^2, adv = U.grad(phi) (= g2 for the
-// central schemes; the upwind product for the baseline).
-template <typename T>
-__device__ __forceinline__ T finish_core(const GridDev &g, int stage, bool zero, T phis, T g2,
+// central schemes; the upwind product for the baseline).  G holds the
+// method's fields (eq, lad, curv, rk, eps, nu0, kp, kp2, sigma): the grid
+// record itself or a copy of them.
+template <typename T, typename G>
+__device__ __forceinline__ T finish_core(const G &g, int stage, bool zero, T phis, T g2,
                                          T adv, T lap, T kap, T lads, T S1, T S2,
                                          const FinIn<T> &in, T &dt_out, T &acc_out)
 {
