@@ -868,8 +868,11 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
         // sums on and a pointwise pass finishes the stage (coalesced: on the
         // 256^3 duct 111 us against 320 us when each lane of the z pass
         // finishes its own strided points); otherwise the last direction's
-        // pass finishes the stage and sets the faces normal to it
-        g.seg_split = g.seg && !has_x && ctx->seg_split_finish;
+        // pass finishes the stage and sets the faces normal to it (and for
+        // fields of 2^31 bytes or more, which the pointwise pass's 32-bit
+        // buffer offsets do not reach)
+        g.seg_split = g.seg && !has_x && ctx->seg_split_finish &&
+                      (double)N * (fp64 ? 8 : 4) < 2147483648.0;
     }
     for (int l = 0; l < d.ndim; ++l) {
         const LineOpDev *dop = ctx_lineop(ctx, OP_DERIV, d.n[l], g.periodic[l], dscheme, 0.0, fp64, ar);

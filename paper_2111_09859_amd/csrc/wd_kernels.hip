@@ -15,6 +15,64 @@
 
 namespace wd {
 
+// A field as a buffer resource (wave-uniform): an access is a per-lane
+// 32-bit byte offset plus a wave-uniform one, so the neighbours of a point
+// along a direction share one offset register and their strides are scalar.
+// The grids served here hold fewer than 2^31 bytes per field.
+struct XBuf {
+    __amdgpu_buffer_rsrc_t r;
+};
+
+template <typename T>
+__device__ __forceinline__ XBuf xbuf(const void *p, long long n)
+{
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0,
+                                              (int)(n * (long long)sizeof(T)), 0x00020000)};
+}
+
+// A resource over `bytes` bytes: an access at a per-lane offset at or
+// beyond that (kXOut, or any offset when bytes = 0) is out of range, which
+// the buffer unit answers with 0 for a load and drops for a store (no
+// memory is touched), so lanes without a point and fields a grid does not
+// use need no branch around their accesses.
+constexpr unsigned kXOut = 0x80000000u;
+__device__ __forceinline__ XBuf xbuf_bytes(const void *p, long long bytes)
+{
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000)};
+}
+
+template <typename T>
+__device__ __forceinline__ T xload(XBuf b, unsigned vo, unsigned so);
+template <>
+__device__ __forceinline__ float xload<float>(XBuf b, unsigned vo, unsigned so)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, vo, so, 0));
+}
+template <>
+__device__ __forceinline__ double xload<double>(XBuf b, unsigned vo, unsigned so)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, vo, so, 0));
+}
+
+__device__ __forceinline__ unsigned char xload_u8(XBuf b, unsigned vo, unsigned so)
+{
+    return __builtin_amdgcn_raw_buffer_load_b8(b.r, vo, so, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ void xstore(XBuf b, T v, unsigned vo, unsigned so);
+template <>
+__device__ __forceinline__ void xstore<float>(XBuf b, float v, unsigned vo, unsigned so)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.r, vo, so, 0);
+}
+template <>
+__device__ __forceinline__ void xstore<double>(XBuf b, double v, unsigned vo, unsigned so)
+{
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b.r, vo, so, 0);
+}
+
 // Pointwise stage finish for general grids without a second derivative
 // level (Eikonal; for the upwind baseline also its advective term).
 template <typename T>
@@ -61,16 +119,28 @@ k_final(const GridDev *__restrict__ grids, const Item *__restrict__ items,
     }
 }
 
+// The method's fields the stage finish reads, held by a pointwise pass for
+// the item it works on (already in T: the same values the finish forms
+// from the grid record).
+template <typename T>
+struct XFin {
+    int eq, lad, curv, rk;
+    T eps, nu0, kp, kp2, sigma;
+};
+
 // Pointwise stage finish (Sec. 3.3) of a uniform Cartesian grid whose
 // directional passes carried the whole |grad phi|^2 and Laplacian on
 // (segmented passes, no extrapolated faces): every operand a plain field,
-// the loads of a thread's points issued before any use.
+// the loads of a thread's points issued before any use, every access
+// unconditional (buffer resources: out-of-range offsets and zero-sized
+// fields select), the method's fields held per item.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_cart_finish(const GridDev *__restrict__ grids, const Item *__restrict__ items,
               int nitems, int stage)
 {
     constexpr int K = kChunk / kThreads;
+    constexpr unsigned E = sizeof(T);
     int step, end;
     for (int it = item_begin(nitems, step, end); it < end; it += step) {
         const Item item = items[it];
@@ -81,37 +151,61 @@ k_cart_finish(const GridDev *__restrict__ grids, const Item *__restrict__ items,
             S1 += (T)g.invh[d];
             S2 += (T)g.invh[d] * (T)g.invh[d];
         }
-        gptr<const T> src = gcast<const T>(stage == 0 ? g.phi : g.ps);
-        gptr<const T> P0 = gcast<const T>(g.P[0]);
-        gptr<const T> P1 = gcast<const T>(g.P[1]);
-        gptr<const T> P2 = gcast<const T>(g.P[2]);
-        gptr<const unsigned char> mk = gmem(g.mask);
+        XFin<T> fp;
+        fp.eq = g.eq;
+        fp.lad = g.lad;
+        fp.curv = g.curv;
+        fp.rk = g.rk;
+        fp.eps = (T)g.eps;
+        fp.nu0 = (T)g.nu0;
+        fp.kp = (T)g.kp;
+        fp.kp2 = (T)g.kp2;
+        fp.sigma = (T)g.sigma;
+        const long long fb = g.N * (long long)E;
+        const XBuf srb = xbuf_bytes(stage == 0 ? g.phi : g.ps, fb);
+        const XBuf psb = xbuf_bytes(g.ps, fb);
+        const XBuf p0b = xbuf_bytes(g.P[0], fb);
+        const XBuf p1b = xbuf_bytes(g.P[1], g.need_lap ? fb : 0);
+        const XBuf p2b = xbuf_bytes(g.P[2], g.lad ? fb : 0);
+        const XBuf pnb = xbuf_bytes(g.phi, stage > 0 ? fb : 0);
+        const XBuf dtb = xbuf_bytes(g.dt, fb);
+        const XBuf acb = xbuf_bytes(g.acc, g.rk == 1 ? fb : 0);
+        const XBuf mkb = xbuf_bytes(g.mask, g.mask ? g.N : 0);
+        const unsigned dtl = stage > 0 ? 0u : kXOut, dts = stage == 0 ? 0u : kXOut;
         const long long q0 = (long long)item.tile * kChunk;
         int qv[K];
-        T ph[K], g2[K], lap[K], lad[K];
-        FinIn<T> fin[K];
+        unsigned vo[K];
+        T ph[K], g2[K], lap[K], lad[K], pn[K], dt[K], ac[K];
         unsigned char solid[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const long long qq = q0 + threadIdx.x + k * kThreads;
-            qv[k] = qq < g.N ? (int)qq : -1;
-            if (qv[k] < 0) continue;
-            const int q = qv[k];
-            ph[k] = src[q];
-            g2[k] = P0[q];
-            lap[k] = g.need_lap ? P1[q] : (T)0;
-            lad[k] = g.lad ? P2[q] : (T)0;
-            fin[k] = fin_load<T>(g, stage, q, ph[k]);
-            solid[k] = g.mask ? mk[q] : 0;
+            qv[k] = qq < g.N ? (int)qq : 0;
+            vo[k] = qq < g.N ? (unsigned)qq * E : kXOut;
+            ph[k] = xload<T>(srb, vo[k], 0);
+            g2[k] = xload<T>(p0b, vo[k], 0);
+            lap[k] = xload<T>(p1b, vo[k], 0);
+            lad[k] = xload<T>(p2b, vo[k], 0);
+            pn[k] = xload<T>(pnb, vo[k], 0);
+            dt[k] = xload<T>(dtb, vo[k] | dtl, 0);
+            ac[k] = xload<T>(acb, vo[k], 0);
+            solid[k] = xload_u8(mkb, vo[k] == kXOut ? kXOut : vo[k] / E, 0);
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            if (qv[k] < 0) continue;
             int idx[3];
             index_of(g, qv[k], idx);
             const bool zero = solid[k] || wall_point(g, idx);
-            gcast<T>(g.ps)[qv[k]] = finish_point<T>(g, stage, qv[k], zero, ph[k], g2[k], g2[k],
-                                                    lap[k], (T)0, lad[k], S1, S2, fin[k]);
+            FinIn<T> fin;
+            fin.pn = stage == 0 ? ph[k] : pn[k];
+            fin.dt = dt[k];
+            fin.acc = ac[k];
+            T dto = (T)0, aco = (T)0;
+            const T out = finish_core<T>(fp, stage, zero, ph[k], g2[k], g2[k], lap[k], (T)0,
+                                         lad[k], S1, S2, fin, dto, aco);
+            xstore<T>(psb, out, vo[k], 0);
+            xstore<T>(dtb, dto, vo[k] | dts, 0);
+            xstore<T>(acb, aco, vo[k], 0);
         }
     }
 }
@@ -177,63 +271,6 @@ struct XEndU<T, R, 0> {
     __device__ static void run(const GridDev &, const T *, T *) {}
 };
 
-// A field as a buffer resource (wave-uniform): an access is a per-lane
-// 32-bit byte offset plus a wave-uniform one, so the neighbours of a point
-// along a direction share one offset register and their strides are scalar.
-// The grids served here hold fewer than 2^31 bytes per field.
-struct XBuf {
-    __amdgpu_buffer_rsrc_t r;
-};
-
-template <typename T>
-__device__ __forceinline__ XBuf xbuf(const void *p, long long n)
-{
-    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0,
-                                              (int)(n * (long long)sizeof(T)), 0x00020000)};
-}
-
-// A resource over `bytes` bytes: an access at a per-lane offset at or
-// beyond that (kXOut, or any offset when bytes = 0) is out of range, which
-// the buffer unit answers with 0 for a load and drops for a store (no
-// memory is touched), so lanes without a point and fields a grid does not
-// use need no branch around their accesses.
-constexpr unsigned kXOut = 0x80000000u;
-__device__ __forceinline__ XBuf xbuf_bytes(const void *p, long long bytes)
-{
-    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000)};
-}
-
-template <typename T>
-__device__ __forceinline__ T xload(XBuf b, unsigned vo, unsigned so);
-template <>
-__device__ __forceinline__ float xload<float>(XBuf b, unsigned vo, unsigned so)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, vo, so, 0));
-}
-template <>
-__device__ __forceinline__ double xload<double>(XBuf b, unsigned vo, unsigned so)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, vo, so, 0));
-}
-
-__device__ __forceinline__ unsigned char xload_u8(XBuf b, unsigned vo, unsigned so)
-{
-    return __builtin_amdgcn_raw_buffer_load_b8(b.r, vo, so, 0);
-}
-
-template <typename T>
-__device__ __forceinline__ void xstore(XBuf b, T v, unsigned vo, unsigned so);
-template <>
-__device__ __forceinline__ void xstore<float>(XBuf b, float v, unsigned vo, unsigned so)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.r, vo, so, 0);
-}
-template <>
-__device__ __forceinline__ void xstore<double>(XBuf b, double v, unsigned vo, unsigned so)
-{
-    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b.r, vo, so, 0);
-}
 
 // U_l and D_l U_l at point q (position i along l)
 template <typename T, int R>
@@ -485,15 +522,6 @@ __device__ __forceinline__ T xcentral_at(const XCo<T> &co, const T *c)
     if (R >= 3) v += co.c * (c[3 * S] - c[-3 * S]);
     return v;
 }
-
-// The method's fields the stage finish reads, held by the one-pass stage
-// for the item it works on (already in T: the same values the finish
-// forms from the grid record).
-template <typename T>
-struct XFin {
-    int eq, lad, curv, rk;
-    T eps, nu0, kp, kp2, sigma;
-};
 
 template <typename T, int R, bool FAST>
 __global__ void __launch_bounds__(kThreads)
