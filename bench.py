@@ -236,8 +236,8 @@ def _per_kernel(rows, counter):
 
 # kernels of one RK stage, and of the rest of a pseudo iteration
 STAGE_KERNELS = ("k_seg_cart<", "k_seg_cart_fin<", "k_cart_finish<", "k_cart<", "k_d1<",
-                 "k_d12<", "k_d2<", "k_uwadv<", "k_final<", "k_face<")
-ITER_KERNELS = STAGE_KERNELS + ("k_seg_lad<", "k_lad<", "k_seg_filter<", "k_filter<",
+                 "k_d12<", "k_d2<", "k_uwadv<", "k_final<", "k_face<", "k_xstage<")
+ITER_KERNELS = STAGE_KERNELS + ("k_seg_lad<", "k_lad<", "k_xlad", "k_seg_filter<", "k_filter<",
                                 "k_resid<", "k_finalize")
 
 
@@ -974,13 +974,14 @@ def main():
         ea = argparse.Namespace(**vars(args))
         ea.steps, ea.warmup = max(1, min(args.steps, 3)), 1
         ekw = dict(kw, scheme="E6")
-        re6 = run_gpu(ea, spec, ekw, "fp32")
+        re6 = run_gpu(ea, spec, ekw, "fp32", profile=not args.no_profile)
         line["config"]["duct_e6"] = {
             "workload": "the same duct and method with E6 explicit derivatives "
-                        "(one pointwise pass per RK stage)",
+                        "(one pass per RK stage: k_xstage, fast and edge tiles)",
             "value": spec.npoints * re6["iters"] / re6["time"], "unit": "point-updates/s",
             "ms_per_iter": 1e3 * re6["time"] / re6["iters"], "steps": ea.steps,
-            "iters_per_step": re6["iters"] / ea.steps}
+            "iters_per_step": re6["iters"] / ea.steps,
+            "roofline": roofline(re6, spec, "fp32", "duct-e6-fp32")}
         print("[bench] duct E6 leg done", file=sys.stderr, flush=True)
     line["roofline"] = roofline(r, spec, args.precision, f"{args.workload}-{args.precision}")
     if not args.no_cpu:

@@ -346,6 +346,15 @@ int wd_ctx_set_segmented(wd_ctx *ctx, int enable);
  * agree to rounding.  Affects plans made after the call. */
 int wd_ctx_set_explicit_onepass(wd_ctx *ctx, int enable);
 
+/* enable != 0 (the default 1): the LAD diffusivity of a uniform Cartesian
+ * grid (Eq. Gamma_form2: the sensor C |sum_l d4_l phi^n / h_l| smoothed by
+ * the nine-point truncated Gaussian along each direction) is formed by two
+ * passes over x-y tiles marched along z, the sensor and then the smoothing
+ * along x, y and z; 0: a sensor pass per direction and a smoothing pass per
+ * direction along lines.  The results agree to rounding.  Affects plans
+ * made after the call. */
+int wd_ctx_set_lad_tiles(wd_ctx *ctx, int enable);
+
 /* ---- host-side diagnostics ------------------------------------------ */
 /* Applies, on the host and in FP64 arithmetic, the parallel-cyclic-reduction
  * multipliers the kernels use for a line system (Sec. 3.2 compact first

@@ -97,6 +97,7 @@ def lib():
         "wd_ctx_profile_read": ([vp, C.POINTER(wd_kernel_stat), C.c_int, ip], C.c_int),
         "wd_ctx_set_segmented": ([vp, C.c_int], C.c_int),
         "wd_ctx_set_explicit_onepass": ([vp, C.c_int], C.c_int),
+        "wd_ctx_set_lad_tiles": ([vp, C.c_int], C.c_int),
         "wd_solve_noalloc": ([vp, C.POINTER(wd_grid_desc), C.POINTER(wd_method), vp, vp, dp,
                               C.c_int, ip, vp], C.c_int),
         "wd_seg_solve_host": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int,
@@ -333,6 +334,13 @@ def wd_ctx_set_segmented(ctx, enable) -> None:
     (segmented, that segment length tried first)."""
     v = int(enable) if not isinstance(enable, bool) else int(enable)
     _check(lib().wd_ctx_set_segmented(ctx, v), "wd_ctx_set_segmented", ok=(WD_OK,))
+
+
+def wd_ctx_set_lad_tiles(ctx, enable) -> None:
+    """enable: the LAD field of uniform Cartesian grids in two tile passes
+    (True, the default) or per-direction line passes (False)."""
+    _check(lib().wd_ctx_set_lad_tiles(ctx, int(bool(enable))), "wd_ctx_set_lad_tiles",
+           ok=(WD_OK,))
 
 
 def wd_ctx_set_explicit_onepass(ctx, enable) -> None:

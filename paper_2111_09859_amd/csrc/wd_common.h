@@ -140,6 +140,8 @@ struct GridDev {
                               // pass (stage values alternate ps / P[0])
     int xkz, xkz2;            // z planes per item (chunk of the march) of its
                               // fast and of its general tiles
+    int xlad;                 // 1: the LAD field in two passes over x-y tiles
+    int xlkz;                 // their z planes per item
     SegGeo sgeo[3];
     SegOpDev sdop[3];         // segmented first-derivative operator
     SegOpDev sfop[3];         // segmented filter-correction operator

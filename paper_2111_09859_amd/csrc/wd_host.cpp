@@ -819,6 +819,20 @@ int layout_grid(wd_ctx *ctx, const wd_grid_desc &d, const wd_method &m, void *ph
         g.xkz = chunk(nf, 1);
         g.xkz2 = chunk(ng, 0);
     }
+    // LAD field of a uniform Cartesian grid: two passes over x-y tiles (the
+    // fourth difference needs 5 points per line), z chunks of at least 8
+    // planes as many as fill one round of the smoothing pass's workgroups
+    g.xlad = ctx->use_xlad && g.lad && g.mode == MODE_CART &&
+             (double)N * (fp64 ? 8 : 4) < 2147483648.0;
+    for (int l = 0; l < d.ndim; ++l)
+        if (d.n[l] < 5) g.xlad = 0;
+    if (g.xlad) {
+        const int ntx = (d.n[0] + kXTX - 1) / kXTX, nty = (d.n[1] + kXTY - 1) / kXTY;
+        const int n2 = d.ndim == 3 ? d.n[2] : 1;
+        const int slots = ctx->cus * xlad_blocks_per_cu(fp64, 2);
+        const int nzc = std::max(1, std::min(slots / (ntx * nty), n2 / 8));
+        g.xlkz = (n2 + nzc - 1) / nzc;
+    }
     const size_t f = (size_t)N * (fp64 ? 8 : 4);
     g.phi = phi;
     g.ps = take(f);
@@ -1062,11 +1076,28 @@ void build_items(Plan &P)
             }
             P.xstage[r - 1][fast] = li;
         }
+    // two-pass LAD field: items are x-y tiles times z chunks, the same for
+    // the sensor (np 1) and the smoothing (np 2)
+    for (int ph = 0; ph < 2; ++ph) {
+        const int li = add_list(PASS_XLAD, 0, 0, 1 + ph);
+        for (int i = 0; i < n; ++i) {
+            const GridDev &g = P.grids[i];
+            if (!g.xlad) continue;
+            const int ntx = (g.n[0] + kXTX - 1) / kXTX, nty = (g.n[1] + kXTY - 1) / kXTY;
+            const int n2 = g.ndim == 3 ? g.n[2] : 1;
+            const int nt = ntx * nty * ((n2 + g.xlkz - 1) / g.xlkz);
+            for (int t = 0; t < nt; ++t) P.items.push_back(Item{i, t});
+            P.lists[li].count += nt;
+        }
+        P.xlad[ph] = li;
+    }
     for (int l = 0; l < 3; ++l)
-        seg_list(P.slad0[l], PASS_SLAD, l, 0, [](const GridDev &g) { return g.lad != 0; });
+        seg_list(P.slad0[l], PASS_SLAD, l, 0, [](const GridDev &g) {
+            return g.lad != 0 && !g.xlad;
+        });
     for (int l = 0; l < 3; ++l)
         seg_list(P.slad1[l], PASS_SLAD, l, 1, [l](const GridDev &g) {
-            return g.lad != 0 && l < g.ndim - 1;
+            return g.lad != 0 && !g.xlad && l < g.ndim - 1;
         });
     for (int l = 0; l < 3; ++l)
         seg_list(P.sfilt[l], PASS_SFILTER, l, 0, [](const GridDev &g) { return g.filter != 0; });
@@ -1101,11 +1132,11 @@ void build_items(Plan &P)
     // grids form the field inside their stage-0 passes.
     for (int l = 0; l < 3; ++l)
         line_slot(P.lad0[l], PASS_LAD, l, 0, [](const GridDev &g) {
-            return g.lad != 0 && g.mode == MODE_CART && !g.seg;
+            return g.lad != 0 && g.mode == MODE_CART && !g.seg && !g.xlad;
         });
     for (int l = 0; l < 3; ++l)
         line_slot(P.lad1[l], PASS_LAD, l, 1, [l](const GridDev &g) {
-            return g.lad != 0 && g.mode == MODE_CART && !g.seg && l < g.ndim - 1;
+            return g.lad != 0 && g.mode == MODE_CART && !g.seg && !g.xlad && l < g.ndim - 1;
         });
     for (int l = 0; l < 3; ++l)
         line_slot(P.filt[l], PASS_FILTER, l, 0, [](const GridDev &g) {
@@ -1152,6 +1183,7 @@ static const char *kind_name(int kind)
     case PASS_SCART_LAST: return "k_seg_cart_fin";
     case PASS_CFIN: return "k_cart_finish";
     case PASS_XSTAGE: return "k_xstage";
+    case PASS_XLAD: return "k_xlad";
     case PASS_SFILTER: return "k_seg_filter";
     case PASS_SLAD: return "k_seg_lad";
     default: return "k_finalize";
@@ -1194,6 +1226,8 @@ static double point_accesses(const GridDev &g, int kind, int l, int stage)
         return (1 + g.need_lap) + finish(0);       // the two sums + the finish's fields
     case PASS_XSTAGE:
         return finish(0);                          // the stage value (and its neighbours) + the finish's fields
+    case PASS_XLAD:
+        return 2;                                  // phi^n in, sensor out; sensor in, field out
     case PASS_D1:
         // phi in, F_l out; at stage 0 of an LAD grid the sensor part:
         // metrics in, sensor sum in (after the first direction) and out
@@ -1234,13 +1268,14 @@ static double launch_bytes(const Plan &P, const ItemList &L, int stage)
     if (L.kind == PASS_FACE) return 0.0;
     const double S = P.fp64 ? 8.0 : 4.0;
     double b = 0.0;
-    if (L.kind == PASS_XSTAGE) {
+    if (L.kind == PASS_XSTAGE || L.kind == PASS_XLAD) {
         // the points each item finishes (its tile's own part of its chunk)
         for (int i = 0; i < L.count; ++i) {
             const Item &it = P.items[L.first + i];
             const GridDev &g = P.grids[it.grid];
             const int ntx = (g.n[0] + kXTX - 1) / kXTX, nty = (g.n[1] + kXTY - 1) / kXTY;
-            const int n2 = g.ndim == 3 ? g.n[2] : 1, kz = L.np == 2 ? g.xkz : g.xkz2;
+            const int n2 = g.ndim == 3 ? g.n[2] : 1;
+            const int kz = L.kind == PASS_XLAD ? g.xlkz : L.np == 2 ? g.xkz : g.xkz2;
             const int tx = it.tile % ntx, ty = (it.tile / ntx) % nty, zc = it.tile / (ntx * nty);
             const double pts = (double)std::min(kXTX, g.n[0] - tx * kXTX) *
                                std::min(kXTY, g.n[1] - ty * kXTY) * std::min(kz, n2 - zc * kz);
@@ -1321,6 +1356,9 @@ static int nwg_for(wd_ctx *ctx, int fp64, int kind, int np, int count, int l = 0
     case PASS_XSTAGE:
         per = xstage_blocks_per_cu(fp64, l, np == 2);
         break;
+    case PASS_XLAD:
+        per = xlad_blocks_per_cu(fp64, np);
+        break;
     default:
         break;
     }
@@ -1348,6 +1386,9 @@ void issue_list(wd_ctx *ctx, const Plan &P, int li, int stage, hipStream_t s)
             break;
         case PASS_XSTAGE:
             name += L.np == 2 ? "/fast" : "/edge";
+            break;
+        case PASS_XLAD:
+            name += L.np == 2 ? "/smooth" : "/sensor";
             break;
         default:
             break;
@@ -1407,6 +1448,8 @@ void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s)
 {
     // LAD diffusivity from phi^n: sensor per direction (the last one also
     // smooths along itself), then smoothing along the other directions
+    issue_list(ctx, P, P.xlad[0], 0, s);
+    issue_list(ctx, P, P.xlad[1], 0, s);
     for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.lad0[l], 0, s);
     for (int l = 0; l < P.maxdim; ++l) issue_seg(ctx, P, P.slad0[l], 0, s);
     for (int l = 0; l < P.maxdim; ++l) issue_slot(ctx, P, P.lad1[l], 1, s);
@@ -2262,6 +2305,14 @@ int wd_ctx_set_explicit_onepass(wd_ctx *ctx, int enable)
     if (!ctx) return fail(WD_ERR_INVALID_ARG, "null context");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     ctx->use_xstage = enable ? 1 : 0;
+    return WD_OK;
+}
+
+int wd_ctx_set_lad_tiles(wd_ctx *ctx, int enable)
+{
+    if (!ctx) return fail(WD_ERR_INVALID_ARG, "null context");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->use_xlad = enable ? 1 : 0;
     return WD_OK;
 }
 

@@ -119,6 +119,7 @@ struct Plan {
     int fin = 0, resid = 0, init = 0, uwadv = 0, cfin = 0;
     int xstage[3][2] = {};       // one-pass explicit stages per scheme radius:
                                  // general and fast tiles
+    int xlad[2] = {0, 0};        // two-pass LAD field: sensor, smoothing
     TableArena *arena = nullptr;   // line-operator tables of a call that allocates nothing
     GridDev *d_grids = nullptr;
     GridDev *d_aux = nullptr, *d_aux2 = nullptr;
@@ -191,6 +192,7 @@ struct wd_ctx {
                                          // (16, 24, 32: segment length tried first)
     int seg_split_finish = 1;            // 1: a pointwise pass finishes their stages
     int use_xstage = 1;                  // explicit schemes on Cartesian grids: one
+    int use_xlad = 1;                    // Cartesian LAD grids: the field in two tile passes
                                          // pointwise pass per RK stage
     std::map<wd::TuneKey, int> tune;
     std::vector<wd::CachedGraph> graphs;

@@ -24,6 +24,7 @@ enum PassKind {
     PASS_SCART_LAST = 14,   // segmented Cartesian pass that finishes the stage
     PASS_CFIN = 15,         // pointwise stage finish of a segmented Cartesian grid
     PASS_XSTAGE = 16,       // one-pass stage of an explicit-scheme Cartesian grid
+    PASS_XLAD = 17,         // LAD field of a Cartesian grid in two passes (np 1 sensor, 2 smoothing)
                             // (l = the scheme's radius)
 };
 
@@ -58,6 +59,9 @@ WD_LINE_LAUNCHER(line_launch_f64_8)
 // workgroups of the one-pass explicit stage (scheme radius r, general or
 // fast tiles) that one compute unit holds at once
 int xstage_blocks_per_cu(int fp64, int r, int fast);
+// workgroups of the two LAD passes (np 1 sensor, 2 smoothing) that one
+// compute unit holds at once
+int xlad_blocks_per_cu(int fp64, int np);
 int line_blocks_per_cu(int kind, int fp64, int np);
 // level-set burnback (uniform grids)
 constexpr int kMaxLevels = 8;   // iso-values per length call

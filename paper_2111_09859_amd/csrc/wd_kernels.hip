@@ -800,6 +800,330 @@ k_xstage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int 
     }
 }
 
+// ---------------------------------------------------------------------
+// LAD diffusivity of a uniform Cartesian grid (Eq. Gamma_form2 with the
+// smoothing reading) in two passes over kXTX x kXTY x-y tiles marched along
+// z, as the one-pass stage: the sensor C |sum_l d4_l phi^n / h_l| (d4 the
+// five-point fourth difference along l, its centre moved inward of the
+// two points next to a non-periodic end) into P[1], then the nine-point
+// truncated Gaussian along x, y and z (ends clamped, periodic lines wrap)
+// into P[2].
+
+constexpr int kLadS = 2;   // sensor tile halo (the fourth difference)
+constexpr int kLadG = 4;   // smoothing tile halo (the Gaussian)
+
+template <typename T>
+__device__ __forceinline__ T xd4(const T *c, int s)
+{
+    return c[-2 * s] - (T)4 * c[-s] + (T)6 * c[0] - (T)4 * c[s] + c[2 * s];
+}
+
+// nine-point truncated Gaussian around c[0], neighbours at lo[o] / hi[o]
+template <typename T>
+__device__ __forceinline__ T xgauss(T c0, const T *lo, const T *hi)
+{
+    const T b[5] = {(T)(3565.0 / 10368.0), (T)(3091.0 / 12960.0), (T)(1997.0 / 25920.0),
+                    (T)(149.0 / 12960.0), (T)(107.0 / 103680.0)};
+    T acc = b[0] * c0;
+#pragma unroll
+    for (int o = 1; o <= 4; ++o) acc += b[o] * (lo[o] + hi[o]);
+    return acc;
+}
+
+// The tile decoding shared by both passes: origin, extent and z range of
+// work item `tile` of grid g (chunks of g.xlkz planes).
+struct XTileGeo {
+    int tx, ty, x0, y0, wx, wy, z0, z1, n0, n1, n2;
+    bool d3, px, py, pz;
+    int s1, s2;
+};
+
+__device__ inline XTileGeo xlad_geo(const GridDev &g, int tile)
+{
+    XTileGeo t;
+    t.n0 = g.n[0];
+    t.n1 = g.n[1];
+    t.d3 = g.ndim == 3;
+    t.n2 = t.d3 ? g.n[2] : 1;
+    const int ntx = (t.n0 + kXTX - 1) / kXTX, nty = (t.n1 + kXTY - 1) / kXTY;
+    t.tx = tile % ntx;
+    t.ty = (tile / ntx) % nty;
+    const int zc = tile / (ntx * nty);
+    t.x0 = xtile_origin(t.tx, kXTX, t.n0);
+    t.y0 = xtile_origin(t.ty, kXTY, t.n1);
+    t.wx = min(kXTX, t.n0);
+    t.wy = min(kXTY, t.n1);
+    t.z0 = zc * g.xlkz;
+    t.z1 = min(t.z0 + g.xlkz, t.n2);
+    t.px = g.periodic[0] != 0;
+    t.py = g.periodic[1] != 0;
+    t.pz = t.d3 && g.periodic[2] != 0;
+    t.s1 = (int)g.stride[1];
+    t.s2 = t.d3 ? (int)g.stride[2] : 0;
+    return t;
+}
+
+// byte offsets within a plane of element e of a tile with halo H (kXOut:
+// outside a non-periodic grid), and of this thread's points (loads: in the
+// grid; stores: the tile's own)
+template <int H>
+__device__ inline unsigned xtile_off(const XTileGeo &t, int e, unsigned E)
+{
+    constexpr int W = kXTX + 2 * H, Hh = kXTY + 2 * H;
+    const int ey = e / W, ex = e - ey * W;
+    int jx = t.x0 - H + ex, jy = t.y0 - H + ey;
+    bool ok = e < W * Hh && ex < t.wx + 2 * H && ey < t.wy + 2 * H;
+    if (t.px) jx = jx < 0 ? jx + t.n0 : (jx >= t.n0 ? jx - t.n0 : jx);
+    else ok = ok && jx >= 0 && jx < t.n0;
+    if (t.py) jy = jy < 0 ? jy + t.n1 : (jy >= t.n1 ? jy - t.n1 : jy);
+    else ok = ok && jy >= 0 && jy < t.n1;
+    return ok ? (unsigned)(jy * t.s1 + jx) * E : kXOut;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_xlad_sens(const GridDev *__restrict__ grids, const Item *__restrict__ items, int nitems)
+{
+    constexpr int H = kLadS, PW = kXTX + 2 * H, PH = kXTY + 2 * H;
+    constexpr int NT = (PW * PH + kThreads - 1) / kThreads;
+    constexpr unsigned E = sizeof(T);
+    __shared__ T sm[2][PW * PH];
+    const int tid = threadIdx.x, cx = tid % kXTX, r0 = tid / kXTX;
+    int step, end;
+    for (int it = item_begin(nitems, step, end); it < end; it += step) {
+        const Item item = items[it];
+        const GridDev &g = grids[item.grid];
+        if (gmem(g.state)->done) continue;
+        const XTileGeo t = xlad_geo(g, item.tile);
+        const T w0 = (T)g.invh[0], w1 = (T)g.invh[1], w2 = (T)g.invh[2], C = (T)g.C;
+        const long long fb = g.N * (long long)E;
+        const XBuf sb = xbuf_bytes(g.phi, fb);
+        const XBuf ob = xbuf_bytes(g.P[1], fb);
+        unsigned toff[NT];
+#pragma unroll
+        for (int m = 0; m < NT; ++m) toff[m] = xtile_off<H>(t, tid + m * kThreads, E);
+        const int gx = t.x0 + cx;
+        unsigned vin[kXPY], vown[kXPY];
+        int lx;   // the x centre of this thread's fourth difference, in the tile
+        {
+            const int c = t.px ? gx : min(max(gx, 2), t.n0 - 3);
+            lx = c - (t.x0 - H);
+        }
+        int ly[kXPY];
+#pragma unroll
+        for (int p = 0; p < kXPY; ++p) {
+            const int ry = r0 + kXRow * p, gy = t.y0 + ry;
+            const bool in = cx < t.wx && ry < t.wy;
+            const bool own = in && gx >= t.tx * kXTX && gy >= t.ty * kXTY;
+            const unsigned off = (unsigned)(gy * t.s1 + gx);
+            vin[p] = in ? off * E : kXOut;
+            vown[p] = own ? off * E : kXOut;
+            const int c = t.py ? gy : min(max(gy, 2), t.n1 - 3);
+            ly[p] = c - (t.y0 - H);
+        }
+        // z: the five planes of the fourth difference, zb .. zb + 4 (its
+        // centre zb + 2 stays inward of the two planes next to an end)
+        auto zbase = [&](int k) { return t.pz ? k - 2 : min(max(k - 2, 0), t.n2 - 5); };
+        T zq[kXPY][5];
+        int jb = INT_MIN;
+        T tv[NT];
+#pragma unroll
+        for (int m = 0; m < NT; ++m) tv[m] = xload<T>(sb, toff[m], (unsigned)(t.z0 * t.s2) * E);
+        lds_barrier();   // the previous item's reads of the tiles are done
+#pragma unroll
+        for (int m = 0; m < NT; ++m)
+            if (m < NT - 1 || tid + m * kThreads < PW * PH) sm[0][tid + m * kThreads] = tv[m];
+        int cur = 0;
+        for (int k = t.z0; k < t.z1; ++k) {
+            const unsigned so = (unsigned)(k * t.s2) * E;
+            if (t.d3 && zbase(k) != jb) {
+                jb = zbase(k);
+#pragma unroll
+                for (int p = 0; p < kXPY; ++p)
+#pragma unroll
+                    for (int m = 0; m < 5; ++m) {
+                        int kk = jb + m;
+                        kk = kk < 0 ? kk + t.n2 : (kk >= t.n2 ? kk - t.n2 : kk);
+                        zq[p][m] = xload<T>(sb, vin[p], (unsigned)(kk * t.s2) * E);
+                    }
+            }
+            const bool adv = t.d3 && k + 1 < t.z1 && zbase(k + 1) == jb + 1;
+            lds_barrier();
+            const T *ph = sm[cur];
+            T znx[kXPY];
+            {
+                int kn = adv ? jb + 5 : k;
+                kn = kn >= t.n2 ? kn - t.n2 : kn;
+#pragma unroll
+                for (int p = 0; p < kXPY; ++p)
+                    znx[p] = xload<T>(sb, vin[p], (unsigned)(kn * t.s2) * E);
+                const unsigned sn = (unsigned)(min(k + 1, t.z1 - 1) * t.s2) * E;
+#pragma unroll
+                for (int m = 0; m < NT; ++m) tv[m] = xload<T>(sb, toff[m], sn);
+            }
+            T out[kXPY];
+#pragma unroll
+            for (int p = 0; p < kXPY; ++p) {
+                const int ry = r0 + kXRow * p;
+                // sum over l in the order x, y, z
+                T sx = w0 * xd4<T>(ph + (ry + H) * PW + lx, 1);
+                sx = w1 * xd4<T>(ph + ly[p] * PW + cx + H, PW) + sx;
+                if (t.d3) sx = w2 * xd4<T>(&zq[p][2], 1) + sx;
+                out[p] = C * fabs(sx);
+            }
+            if (k + 1 < t.z1) {
+#pragma unroll
+                for (int m = 0; m < NT; ++m)
+                    if (m < NT - 1 || tid + m * kThreads < PW * PH)
+                        sm[cur ^ 1][tid + m * kThreads] = tv[m];
+            }
+            cur ^= 1;
+#pragma unroll
+            for (int p = 0; p < kXPY; ++p) xstore<T>(ob, out[p], vown[p], so);
+            if (adv) {
+                ++jb;
+#pragma unroll
+                for (int p = 0; p < kXPY; ++p) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) zq[p][m] = zq[p][m + 1];
+                    zq[p][4] = znx[p];
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_xlad_smooth(const GridDev *__restrict__ grids, const Item *__restrict__ items, int nitems)
+{
+    constexpr int H = kLadG, SW = kXTX + 2 * H, SH = kXTY + 2 * H;
+    constexpr int NT = (SW * SH + kThreads - 1) / kThreads;
+    constexpr int NGX = (SH * kXTX + kThreads - 1) / kThreads;
+    constexpr unsigned E = sizeof(T);
+    __shared__ T st[2][SW * SH];   // sensor tile (this plane's and the next one's)
+    __shared__ T gxs[SH * kXTX];   // smoothed along x, rows y0-H .. y0+TY+H-1
+    const int tid = threadIdx.x, cx = tid % kXTX, r0 = tid / kXTX;
+    int step, end;
+    for (int it = item_begin(nitems, step, end); it < end; it += step) {
+        const Item item = items[it];
+        const GridDev &g = grids[item.grid];
+        if (gmem(g.state)->done) continue;
+        const XTileGeo t = xlad_geo(g, item.tile);
+        const long long fb = g.N * (long long)E;
+        const XBuf sb = xbuf_bytes(g.P[1], fb);
+        const XBuf ob = xbuf_bytes(g.P[2], fb);
+        unsigned toff[NT];
+#pragma unroll
+        for (int m = 0; m < NT; ++m) toff[m] = xtile_off<H>(t, tid + m * kThreads, E);
+        const int gx = t.x0 + cx;
+        unsigned vown[kXPY];
+#pragma unroll
+        for (int p = 0; p < kXPY; ++p) {
+            const int ry = r0 + kXRow * p, gy = t.y0 + ry;
+            const bool own = cx < t.wx && ry < t.wy && gx >= t.tx * kXTX && gy >= t.ty * kXTY;
+            vown[p] = own ? (unsigned)(gy * t.s1 + gx) * E : kXOut;
+        }
+        // tile index of position j along a direction of n points (tile
+        // origin o0 - H): periodic lines read the wrapped copies the tile
+        // holds, non-periodic ones clamp to the end
+        auto tix = [&](int j, int n, bool per, int o0) {
+            return (per ? j : min(max(j, 0), n - 1)) - (o0 - H);
+        };
+        // virtual planes z0 - 4 .. z1 + 3 of the z smoothing, each the
+        // plane it reads (clamped or wrapped)
+        auto zmap = [&](int v) {
+            return t.pz ? (v < 0 ? v + t.n2 : (v >= t.n2 ? v - t.n2 : v))
+                        : min(max(v, 0), t.n2 - 1);
+        };
+        const int v0 = t.d3 ? t.z0 - 4 : 0, v1 = t.d3 ? t.z1 + 4 : 1;
+        T zq[kXPY][9];
+        T tv[NT];
+#pragma unroll
+        for (int m = 0; m < NT; ++m)
+            tv[m] = xload<T>(sb, toff[m], (unsigned)(zmap(v0) * t.s2) * E);
+        lds_barrier();   // the previous item's reads of the tiles are done
+#pragma unroll
+        for (int m = 0; m < NT; ++m)
+            if (m < NT - 1 || tid + m * kThreads < SW * SH) st[0][tid + m * kThreads] = tv[m];
+        int cur = 0, aprev = INT_MIN;
+        T sxy[kXPY];
+        for (int v = v0; v < v1; ++v) {
+            const int a = zmap(v);
+            if (a != aprev || t.pz) {
+                // this plane's sensor tile is in st[cur]
+                lds_barrier();
+                const T *sp = st[cur];
+                const int an = t.pz ? zmap(v + 1) : min(a + 1, t.n2 - 1);
+#pragma unroll
+                for (int m = 0; m < NT; ++m)
+                    tv[m] = xload<T>(sb, toff[m], (unsigned)(an * t.s2) * E);
+                // along x, every row of the tile
+#pragma unroll
+                for (int i = 0; i < NGX; ++i) {
+                    const int e = tid + i * kThreads;
+                    if (i < NGX - 1 || e < SH * kXTX) {
+                        const int r = e / kXTX, c = e - r * kXTX;
+                        const int j = t.x0 + c;
+                        const T *row = sp + r * SW;
+                        T lo[5], hi[5];
+#pragma unroll
+                        for (int o = 1; o <= 4; ++o) {
+                            lo[o] = row[tix(j - o, t.n0, t.px, t.x0)];
+                            hi[o] = row[tix(j + o, t.n0, t.px, t.x0)];
+                        }
+                        gxs[e] = xgauss<T>(row[tix(j, t.n0, t.px, t.x0)], lo, hi);
+                    }
+                }
+                lds_barrier();
+                // along y, this thread's points
+#pragma unroll
+                for (int p = 0; p < kXPY; ++p) {
+                    const int gy = t.y0 + r0 + kXRow * p;
+                    T lo[5], hi[5];
+#pragma unroll
+                    for (int o = 1; o <= 4; ++o) {
+                        lo[o] = gxs[tix(gy - o, t.n1, t.py, t.y0) * kXTX + cx];
+                        hi[o] = gxs[tix(gy + o, t.n1, t.py, t.y0) * kXTX + cx];
+                    }
+                    sxy[p] = xgauss<T>(gxs[tix(gy, t.n1, t.py, t.y0) * kXTX + cx], lo, hi);
+                }
+#pragma unroll
+                for (int m = 0; m < NT; ++m)
+                    if (m < NT - 1 || tid + m * kThreads < SW * SH)
+                        st[cur ^ 1][tid + m * kThreads] = tv[m];
+                cur ^= 1;
+                aprev = a;
+            }
+            if (!t.d3) {
+#pragma unroll
+                for (int p = 0; p < kXPY; ++p) xstore<T>(ob, sxy[p], vown[p], 0);
+                continue;
+            }
+            // along z: planes v - 8 .. v in the queue, the output at v - 4
+#pragma unroll
+            for (int p = 0; p < kXPY; ++p) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) zq[p][m] = zq[p][m + 1];
+                zq[p][8] = sxy[p];
+            }
+            if (v >= t.z0 + 4) {
+                const unsigned so = (unsigned)((v - 4) * t.s2) * E;
+#pragma unroll
+                for (int p = 0; p < kXPY; ++p) {
+                    T lo[5], hi[5];
+#pragma unroll
+                    for (int o = 1; o <= 4; ++o) {
+                        lo[o] = zq[p][4 - o];
+                        hi[o] = zq[p][4 + o];
+                    }
+                    xstore<T>(ob, xgauss<T>(zq[p][4], lo, hi), vown[p], so);
+                }
+            }
+        }
+    }
+}
+
 // Advective term of the upwind baseline for grids whose stage finish is
 // pointwise (Eikonal): P[1] <- U.grad(phi) of Eqs. UW1-UW5, uw2 <- |U|^2,
 // from the stage value, before the finish overwrites it.
@@ -1615,6 +1939,10 @@ static void point_launch(int kind, const GridDev *g, const Item *it, int nitems,
             else hipLaunchKernelGGL((k_xstage<T, 3, false>), grid, block, 0, s, g, it, nitems, stage);
         }
         break;
+    case PASS_XLAD:
+        if (np == 2) hipLaunchKernelGGL(k_xlad_smooth<T>, grid, block, 0, s, g, it, nitems);
+        else hipLaunchKernelGGL(k_xlad_sens<T>, grid, block, 0, s, g, it, nitems);
+        break;
     case PASS_UWADV: hipLaunchKernelGGL(k_uwadv<T>, grid, block, 0, s, g, it, nitems, stage); break;
     case PASS_RESID: hipLaunchKernelGGL(k_resid<T>, grid, block, 0, s, g, it, nitems); break;
     case PASS_FACE: hipLaunchKernelGGL(k_face<T>, grid, block, 0, s, g, it, nitems, l, stage); break;
@@ -1632,6 +1960,7 @@ void launch_pass(int kind, int fp64, int np, const GridDev *g, const Item *it, i
     case PASS_FINAL:
     case PASS_CFIN:
     case PASS_XSTAGE:
+    case PASS_XLAD:
     case PASS_UWADV:
     case PASS_RESID:
     case PASS_FACE:
@@ -1679,6 +2008,26 @@ int xstage_blocks_per_cu(int fp64, int r, int fast)
     int v = c.load(std::memory_order_relaxed);
     if (v > 0) return v;
     const void *f = fp64 ? xstage_fn<double>(r, fast != 0) : xstage_fn<float>(r, fast != 0);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kThreads, 0) != hipSuccess) n = 0;
+    v = std::max(1, n);
+    c.store(v, std::memory_order_relaxed);
+    return v;
+}
+
+int xlad_blocks_per_cu(int fp64, int np)
+{
+    static std::atomic<int> cache[2][2];
+    std::atomic<int> &c = cache[fp64 ? 1 : 0][np == 2 ? 1 : 0];
+    int v = c.load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    const void *f;
+    if (fp64)
+        f = np == 2 ? reinterpret_cast<const void *>(&k_xlad_smooth<double>)
+                    : reinterpret_cast<const void *>(&k_xlad_sens<double>);
+    else
+        f = np == 2 ? reinterpret_cast<const void *>(&k_xlad_smooth<float>)
+                    : reinterpret_cast<const void *>(&k_xlad_sens<float>);
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kThreads, 0) != hipSuccess) n = 0;
     v = std::max(1, n);
