@@ -480,6 +480,7 @@ def run_batch(args):
                    "fp32_iters": out["iters"], "fp64_iters": it64,
                    "fp32_status": out["status"], "fp64_status": st64,
                    "linf_fp32_minus_fp64": d3264,
+                   "max_abs_fp64": max_abs64,
                    "linf_err_fp32": e32, "linf_err_fp64": e64,
                    "grids_same_accuracy": len(ok),
                    "grids_fp32_within_1e-5_rel_of_fp64": len(close),
