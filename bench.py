@@ -412,7 +412,7 @@ def batch_tiles(spec, target=2048):
 
 
 def run_batch(args):
-    """Config 4: 64 seeded 2D grids (channel / cylinder / ellipse O-grids,
+    """The batch workload: 64 seeded 2D grids (channel / cylinder / ellipse O-grids,
     E6 / C6, LAD pseudo-HJ + curvature on O-grids) solved as ONE FP32 batch
     versus the same grids solved one at a time in FP64."""
     import torch
@@ -727,8 +727,8 @@ def run_moving(args):
 
 
 def run_serve(args):
-    """Config 5: open-loop Poisson arrivals (--serve-rate, default the
-    config's 200 req/s; a rate at or below the server's measured capacity
+    """The serving workload: open-loop Poisson arrivals (--serve-rate, default
+    200 req/s; a rate at or below the server's measured capacity
     gives latencies of the server rather than of an overloaded queue) of
     --serve-count 2D grids 129^2..2049^2 and 3D ducts 64^3..192^3 into the
     continuous-batching server, beside 4 closed-loop warm-started

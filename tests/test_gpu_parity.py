@@ -126,7 +126,7 @@ def test_fp64_fixed_iterations(solver, oracle, name, build, kw, n_iter):
     assert np.allclose(out["hist"][:, 0], h[:, 0], rtol=1e-8, atol=1e-14)
 
 
-def test_channel_config1_converged(solver, oracle):
+def test_channel_129x65_converged(solver, oracle):
     """129 x 65 channel, E4, RK3, standard HJ (eps 0.1), FP64 to 1e-10:
     the GPU stops at the oracle's iteration and matches its field."""
     spec = G.channel(129, 65)

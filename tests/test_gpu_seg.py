@@ -138,7 +138,7 @@ def test_segmented_fp32_vs_oracle(solver, oracle, name, mk, kw, n):
     assert e_seg <= FP32_TOL
 
 
-def test_segmented_converged_channel_config1(solver, oracle):
+def test_segmented_converged_channel(solver, oracle):
     """The 129 x 65 channel (standard HJ eps 0.1, E4, RK3, FP64 to 1e-10)
     through the segmented passes stops at the oracle's iteration and matches
     its field."""

@@ -134,7 +134,7 @@ def test_onepass_fp32_vs_oracle(solver, oracle, name, mk, kw, n):
     assert e1 <= FP32_TOL
 
 
-def test_onepass_channel_config1_converged(solver, oracle):
+def test_onepass_channel_converged(solver, oracle):
     """The 129 x 65 channel (standard HJ eps 0.1, E4, RK3, FP64 to 1e-10)
     through the one-pass stages stops at the oracle's iteration with its
     field."""
