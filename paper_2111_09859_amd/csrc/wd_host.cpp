@@ -983,6 +983,7 @@ void build_items(Plan &P)
     P.items.clear();
     P.lists.clear();
     const int n = P.n;
+    auto live = [&](int i) { return P.live.empty() || P.live[i] != 0; };
     auto add_list = [&](int kind, int l, int arg, int np) {
         ItemList L;
         L.kind = kind;
@@ -1001,6 +1002,7 @@ void build_items(Plan &P)
             const int np = 1 << c;
             int li = -1;
             for (int i = 0; i < n; ++i) {
+                if (!live(i)) continue;
                 const GridDev &g = P.grids[i];
                 if (l >= g.ndim || !use(g) || tile_np(g, l) != np) continue;
                 if (li < 0) li = add_list(kind, l, arg, np);
@@ -1013,6 +1015,7 @@ void build_items(Plan &P)
     auto point_list = [&](int kind, int l, int arg, auto count) {
         const int li = add_list(kind, l, arg, 1);
         for (int i = 0; i < n; ++i) {
+            if (!live(i)) continue;
             const int nt = count(i);
             for (int t = 0; t < nt; ++t) P.items.push_back(Item{i, t});
             P.lists[li].count += nt;
@@ -1029,6 +1032,7 @@ void build_items(Plan &P)
         for (int c = 0; c < 3; ++c) {
             int li = -1;
             for (int i = 0; i < n; ++i) {
+                if (!live(i)) continue;
                 const GridDev &g = P.grids[i];
                 if (!g.seg || l >= g.ndim || !use(g) || g.sgeo[l].M != Ms[c]) continue;
                 if (li < 0) li = add_list(kind, l, arg, Ms[c]);
@@ -1056,6 +1060,7 @@ void build_items(Plan &P)
         for (int fast = 0; fast < 2; ++fast) {
             const int li = add_list(PASS_XSTAGE, r, 0, 1 + fast);
             for (int i = 0; i < n; ++i) {
+                if (!live(i)) continue;
                 const GridDev &g = P.grids[i];
                 if (!g.xstage || g.dradius != r) continue;
                 const int ntx = (g.n[0] + kXTX - 1) / kXTX, nty = (g.n[1] + kXTY - 1) / kXTY;
@@ -1081,6 +1086,7 @@ void build_items(Plan &P)
     for (int ph = 0; ph < 2; ++ph) {
         const int li = add_list(PASS_XLAD, 0, 0, 1 + ph);
         for (int i = 0; i < n; ++i) {
+            if (!live(i)) continue;
             const GridDev &g = P.grids[i];
             if (!g.xlad) continue;
             const int ntx = (g.n[0] + kXTX - 1) / kXTX, nty = (g.n[1] + kXTY - 1) / kXTY;
@@ -1579,7 +1585,7 @@ void ctx_drop_graphs(wd_ctx *ctx)
 
 // Iterate until every grid of the plan has stopped.  States are read back
 // after each graph replay of K iterations.
-int run_plan(wd_ctx *ctx, const Plan &P, int K, std::vector<GridState> &states)
+int run_plan(wd_ctx *ctx, Plan &P, int K, std::vector<GridState> &states)
 {
     hipStream_t s = ctx->stream;
     int maxit = 0;
@@ -1589,6 +1595,12 @@ int run_plan(wd_ctx *ctx, const Plan &P, int K, std::vector<GridState> &states)
     CachedGraph *cg = use_graph ? graph_for(ctx, P, K) : nullptr;
     if (use_graph && !cg) return WD_ERR_HIP;
     states.resize(P.n);
+    // points the current work lists cover: once the grids still running
+    // hold half of them or less, the lists are rebuilt over those grids
+    // alone (a stopped grid's items only test its flag, but every pass of
+    // every iteration still launches over them)
+    long long plan_pts = 0;
+    for (int i = 0; i < P.n; ++i) plan_pts += P.grids[i].N;
     const long long max_rounds = (maxit + K - 1) / K + 1;
     int prev_iter = 0;
     for (long long r = 0; r < max_rounds; ++r) {
@@ -1622,6 +1634,22 @@ int run_plan(wd_ctx *ctx, const Plan &P, int K, std::vector<GridState> &states)
         }
         prev_iter = max_iter_now;
         if (all) return WD_OK;
+        long long live_pts = 0;
+        for (int i = 0; i < P.n; ++i)
+            if (!states[i].done) live_pts += P.grids[i].N;
+        if (P.n > 1 && 2 * live_pts <= plan_pts) {
+            P.live.assign(P.n, 0);
+            for (int i = 0; i < P.n; ++i) P.live[i] = states[i].done ? 0 : 1;
+            build_items(P);
+            if (hipMemcpyAsync(P.d_items, P.items.data(), P.items.size() * sizeof(Item),
+                               hipMemcpyHostToDevice, s) != hipSuccess)
+                return fail(WD_ERR_HIP, "item upload failed");
+            plan_pts = live_pts;
+            if (use_graph) {
+                cg = graph_for(ctx, P, K);
+                if (!cg) return WD_ERR_HIP;
+            }
+        }
     }
     return fail(WD_ERR_HIP, "grids did not stop within max_iter");
 }

@@ -120,6 +120,8 @@ struct Plan {
     int xstage[3][2] = {};       // one-pass explicit stages per scheme radius:
                                  // general and fast tiles
     int xlad[2] = {0, 0};        // two-pass LAD field: sensor, smoothing
+    std::vector<char> live;      // grids the work lists cover (empty: all of
+                                 // them); a solve drops grids that stopped
     TableArena *arena = nullptr;   // line-operator tables of a call that allocates nothing
     GridDev *d_grids = nullptr;
     GridDev *d_aux = nullptr, *d_aux2 = nullptr;
@@ -167,7 +169,7 @@ void issue_iteration(wd_ctx *ctx, const Plan &P, hipStream_t s);
 CachedGraph *graph_for(wd_ctx *ctx, const Plan &P, int K);
 void prof_collect(wd_ctx *ctx);
 void ctx_drop_graphs(wd_ctx *ctx);
-int run_plan(wd_ctx *ctx, const Plan &P, int K, std::vector<GridState> &states);
+int run_plan(wd_ctx *ctx, Plan &P, int K, std::vector<GridState> &states);
 int poisson_convert(wd_ctx *ctx, const Plan &P, int i, void *aux, hipStream_t s);
 int solve_plan(wd_ctx *ctx, Plan &P, void *const *aux, double *const *hists, int hist_cap,
                int *iters, int *status);
