@@ -278,11 +278,19 @@ static int run_group(wd_server *srv, const std::vector<long long> &ids, bool sam
     if (rc) return rc;
     launch_mirror(P.d_grids, P.n, s);
     issue_init(ctx, P, s);
-    // direct launches: the set changes at round boundaries and capture would
-    // serialise with the clients' runtime calls
+    // a set unchanged since the last round replays the graph of its K
+    // iterations (captured in relaxed mode, so the clients' runtime calls go
+    // on meanwhile; cached by the plan's contents); a new set launches
+    // directly, since it may last a single round
     const int K = srv->round_iters;
-    (void)same_set;
-    for (int k = 0; k < K; ++k) issue_iteration(ctx, P, s);
+    CachedGraph *cg = nullptr;
+    if (same_set && ctx->use_graphs && !ctx->profile) cg = graph_for(ctx, P, K);
+    if (cg) {
+        if (hipGraphLaunch(cg->exec, s) != hipSuccess)
+            return fail(WD_ERR_HIP, "server round graph launch failed");
+    } else {
+        for (int k = 0; k < K; ++k) issue_iteration(ctx, P, s);
+    }
     if (hipMemcpyAsync(ctx->pinned_states, P.d_states, P.n * sizeof(GridState),
                        hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)

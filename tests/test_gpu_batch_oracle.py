@@ -154,3 +154,38 @@ def test_served_warm_session_step_vs_oracle(solver, oracle, prec):
             assert np.allclose(hist[:, 0], h[:, 0], rtol=1e-8, atol=1e-14)
     finally:
         srv.close()
+
+
+def test_served_unchanged_set_rounds_vs_oracle(solver, oracle):
+    """Three grids served together for 80 iterations: five rounds of 16
+    with the same set, the last four replaying the graph the server
+    captures for an unchanged set (the round's states read back between
+    replays); each field against the oracle after the same iterations
+    (FP64, linear Gamma so that the 80 iterations stay comparable)."""
+    from paper_2111_09859_amd import api, _lib as L
+    cases = [
+        ("channel65x33_E6_linear", lambda: G.channel(65, 33), dict(eq="HJ", scheme="E6", eps=0.1)),
+        ("duct17x17x12_C6_linear", lambda: G.duct(17, nx=12), dict(eq="HJ", scheme="C6")),
+        ("star64_E6_linear_mask", lambda: G.star_grain(64), dict(eq="HJ", scheme="E6", eps=0.15)),
+    ]
+    n = 80
+    srv = api.Server(solver, budget_bytes=256 << 20, max_slots=8)
+    try:
+        ids, specs = [], []
+        for name, build, kw in cases:
+            spec = build()
+            specs.append(spec)
+            p = solver.prepare(spec, kw["scheme"], "fp64")
+            ids.append(srv.submit(p, gmethod(tol=0.0, max_iter=n, precision="fp64", **kw),
+                                  hist_cap=n))
+        for rid, spec, (name, _, kw) in zip(ids, specs, cases):
+            st = srv.wait(rid, 120.0)
+            assert st == L.WD_NOT_CONVERGED and srv.poll(rid)["iters"] == n, (name, st)
+            ref, _, it, h = oracle.solve(spec, omethod(oracle, fixed=n, **kw))
+            e = rel(srv.result(rid).double().cpu().numpy(), ref)
+            say(f"[served unchanged set fp64] {name}: rel_linf={e:.2e}")
+            assert e <= FP64_TOL, name
+            hist = np.array(srv.history(rid, n)).reshape(-1, 2)
+            assert np.allclose(hist[:, 0], h[:, 0], rtol=1e-8, atol=1e-14), name
+    finally:
+        srv.close()
