@@ -23,12 +23,6 @@ struct XBuf {
     __amdgpu_buffer_rsrc_t r;
 };
 
-template <typename T>
-__device__ __forceinline__ XBuf xbuf(const void *p, long long n)
-{
-    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0,
-                                              (int)(n * (long long)sizeof(T)), 0x00020000)};
-}
 
 // A resource over `bytes` bytes: an access at a per-lane offset at or
 // beyond that (kXOut, or any offset when bytes = 0) is out of range, which
@@ -219,131 +213,23 @@ k_cart_finish(const GridDev *__restrict__ grids, const Item *__restrict__ items,
 // the stage.  The stage value is read from one buffer and written to
 // another (the stencil reads neighbours the pass also writes).
 
-// first derivative at end position a (index space, counted from a
-// non-periodic end: a = 0 is the end point) from e[] (phi at end positions
-// 0, 1, ...); rows within R of the end are the one-sided closures.  At the
-// high end the end coordinate runs against the index, so the derivative
-// there is the negative of this one (the second derivative is unchanged).
+// first derivative at end position A < R (index space, counted from a
+// non-periodic end: A = 0 is the end point) from e[] (f at end positions
+// 0 .. 4): the one-sided closure rows.  At the high end the end coordinate
+// runs against the index, so the derivative there is the negative of this
+// one (the second derivative is unchanged).
 template <typename T, int R, int A>
-__device__ inline T xend_row(const GridDev &g, const T *e)
+__device__ inline T xend_row(const T *e)
 {
-    if (A < R) {
-        if (R == 1) return ((T)-3 * e[0] + (T)4 * e[1] - e[2]) * (T)0.5;
-        if (A == 0)
-            return ((T)-25 * e[0] + (T)48 * e[1] - (T)36 * e[2] + (T)16 * e[3] - (T)3 * e[4]) *
-                   (T)(1.0 / 12.0);
-        if (A == 1)
-            return ((T)-3 * e[0] - (T)10 * e[1] + (T)18 * e[2] - (T)6 * e[3] + e[4]) *
-                   (T)(1.0 / 12.0);
-        return (e[0] - (T)8 * e[1] + (T)8 * e[3] - e[4]) * (T)(1.0 / 12.0);
-    }
-    const T a = (T)(0.5 * g.da), b = (T)(0.25 * g.db), c = (T)(g.dc / 6.0);
-    T sum = a * (e[A + 1] - e[A - 1]);
-    if (R >= 2) sum += b * (e[A + 2] - e[A - 2]);
-    if (R >= 3) sum += c * (e[A + 3] - e[A - 3]);
-    return sum;
-}
-
-template <typename T, int R, int A>
-struct XEnd {
-    // lap[A'] for A' = 0 .. A-1 (compile-time recursion)
-    __device__ static void run(const GridDev &g, const T *Ue, T *lap)
-    {
-        XEnd<T, R, A - 1>::run(g, Ue, lap);
-        lap[A - 1] = xend_row<T, R, A - 1>(g, Ue);
-    }
-};
-template <typename T, int R>
-struct XEnd<T, R, 0> {
-    __device__ static void run(const GridDev &, const T *, T *) {}
-};
-
-template <typename T, int R, int A>
-struct XEndU {
-    __device__ static void run(const GridDev &g, const T *e, T *Ue)
-    {
-        XEndU<T, R, A - 1>::run(g, e, Ue);
-        Ue[A - 1] = xend_row<T, R, A - 1>(g, e);
-    }
-};
-template <typename T, int R>
-struct XEndU<T, R, 0> {
-    __device__ static void run(const GridDev &, const T *, T *) {}
-};
-
-
-// U_l and D_l U_l at point q (position i along l)
-template <typename T, int R>
-__device__ inline void xaxis(const GridDev &g, int l, gptr<const T> f, XBuf fb, long long q, int i,
-                             T &u, T &lap)
-{
-    const int n = g.n[l];
-    const long long st = g.stride[l];
-    const bool per = g.periodic[l] != 0;
-    const T ih = (T)g.invh[l];
-    const T a = (T)(0.5 * g.da), b = (T)(0.25 * g.db), c = (T)(g.dc / 6.0);
-    const bool inner = i >= 2 * R && i <= n - 1 - 2 * R;
-    if (per || inner) {
-        // interior (or periodic): phi at i-2R..i+2R, U at i-R..i+R
-        T v[4 * R + 1];
-        if (inner) {
-            // buffer loads from the stencil's first point: one offset
-            // register, scalar steps of the stride
-            constexpr unsigned E = sizeof(T);
-            const unsigned vo = (unsigned)(q - 2 * R * st) * E;
-#pragma unroll
-            for (int k = 0; k <= 4 * R; ++k) v[k] = xload<T>(fb, vo, (unsigned)(k * st) * E);
-        } else {
-#pragma unroll
-            for (int k = -2 * R; k <= 2 * R; ++k) {
-                int j = i + k;
-                j = j < 0 ? j + n : (j >= n ? j - n : j);
-                v[k + 2 * R] = f[q + (long long)(j - i) * st];
-            }
-        }
-        T U[2 * R + 1];
-#pragma unroll
-        for (int m = -R; m <= R; ++m) {
-            const int cj = 2 * R + m;
-            T sum = a * (v[cj + 1] - v[cj - 1]);
-            if (R >= 2) sum += b * (v[cj + 2] - v[cj - 2]);
-            if (R >= 3) sum += c * (v[cj + 3] - v[cj - 3]);
-            U[m + R] = sum * ih;
-        }
-        u = U[R];
-        T sl = a * (U[R + 1] - U[R - 1]);
-        if (R >= 2) sl += b * (U[R + 2] - U[R - 2]);
-        if (R >= 3) sl += c * (U[R + 3] - U[R - 3]);
-        lap = sl * ih;
-        return;
-    }
-    // within 2R of a non-periodic end: in end coordinates (a = 0 at the
-    // end, growing inward), phi at 0..4R, U at 0..max(3R, 5)-1, and the
-    // point's own row picked among the first 2R
-    const bool low = i < 2 * R;
-    const int ai = low ? i : n - 1 - i;
-    const T sgn = low ? (T)1 : (T)-1;
-    constexpr int NE = 4 * R + 1;
-    constexpr int NU = 3 * R > 5 ? 3 * R : 5;
-    T e[NE > NU + R ? NE : NU + R];
-#pragma unroll
-    for (int k = 0; k < (NE > NU + R ? NE : NU + R); ++k) {
-        const int pos = low ? min(k, n - 1) : max(n - 1 - k, 0);
-        e[k] = f[q + (long long)(pos - i) * st];
-    }
-    T Ue[NU];
-    XEndU<T, R, NU>::run(g, e, Ue);
-    T lp[2 * R];
-    XEnd<T, R, 2 * R>::run(g, Ue, lp);
-    T uu = Ue[0], ll = lp[0];
-#pragma unroll
-    for (int k = 1; k < 2 * R; ++k) {
-        uu = ai == k ? Ue[k] : uu;
-        ll = ai == k ? lp[k] : ll;
-    }
-    // U in index space; the second derivative is the same in both senses
-    u = sgn * uu * ih;
-    lap = ll * ih * ih;
+    static_assert(A < R, "closure rows only");
+    if (R == 1) return ((T)-3 * e[0] + (T)4 * e[1] - e[2]) * (T)0.5;
+    if (A == 0)
+        return ((T)-25 * e[0] + (T)48 * e[1] - (T)36 * e[2] + (T)16 * e[3] - (T)3 * e[4]) *
+               (T)(1.0 / 12.0);
+    if (A == 1)
+        return ((T)-3 * e[0] - (T)10 * e[1] + (T)18 * e[2] - (T)6 * e[3] + e[4]) *
+               (T)(1.0 / 12.0);
+    return (e[0] - (T)8 * e[1] + (T)8 * e[3] - e[4]) * (T)(1.0 / 12.0);
 }
 
 // Tiles of the one-pass stage: kXTX x kXTY points of an x-y plane per
@@ -351,10 +237,10 @@ __device__ inline void xaxis(const GridDev &g, int l, gptr<const T> f, XBuf fb, 
 // values and a halo of 2R points sit in LDS; U_x and U_y are formed there
 // once per position (the tile and a halo of R), so each point's D_l U_l
 // reads R neighbours of U on each side.  Along z every thread keeps a
-// queue of its columns' stage values (4R + 1 planes) and U_z (2R + 1
-// planes) in registers: a plane costs one new load and one new U_z per
-// point.  Planes within 2R of a non-periodic z end take their z terms from
-// the end-coordinate rows above instead.
+// queue per point in registers (XZq: U_z of 2R + 1 planes and the stage
+// values of the next 2R): a plane costs one new load and one new U_z per
+// point, and near a non-periodic z end the queue is refilled with each
+// position's own row.
 constexpr int kXRow = kThreads / kXTX;   // rows the threads cover at once
 constexpr int kXPY = kXTY / kXRow;       // points per thread and plane
 
@@ -381,8 +267,7 @@ struct XCo {
 };
 
 template <typename T, int R, typename F>
-__device__ __forceinline__ T xrow(const GridDev &g, const XCo<T> &co, int j, int n, bool per,
-                                  const F &f)
+__device__ __forceinline__ T xrow(const XCo<T> &co, int j, int n, bool per, const F &f)
 {
     if (per || (j >= R && j <= n - 1 - R)) {
         const T a = co.a, b = co.b, c = co.c;
@@ -397,9 +282,9 @@ __device__ __forceinline__ T xrow(const GridDev &g, const XCo<T> &co, int j, int
 #pragma unroll
     for (int m = 0; m < 5; ++m) e[m] = (R == 1 && m > 2) ? (T)0 : f(low ? m : n - 1 - m);
     T d;
-    if (R >= 3 && A == 2) d = xend_row<T, R, (R >= 3 ? 2 : 0)>(g, e);
-    else if (R >= 2 && A == 1) d = xend_row<T, R, (R >= 2 ? 1 : 0)>(g, e);
-    else d = xend_row<T, R, 0>(g, e);
+    if (R >= 3 && A == 2) d = xend_row<T, R, (R >= 3 ? 2 : 0)>(e);
+    else if (R >= 2 && A == 1) d = xend_row<T, R, (R >= 2 ? 1 : 0)>(e);
+    else d = xend_row<T, R, 0>(e);
     return low ? d : -d;
 }
 
@@ -436,7 +321,7 @@ struct XZq {
 };
 
 template <typename T, int R>
-__device__ __forceinline__ void xz_fill(const GridDev &g, const XCo<T> &co, XBuf sb, unsigned vo,
+__device__ __forceinline__ void xz_fill(const XCo<T> &co, XBuf sb, unsigned vo,
                                         int jb, int n2, int s2, bool pz, T ih2, XZq<T, R> &z)
 {
     constexpr unsigned E = sizeof(T);
@@ -460,16 +345,16 @@ __device__ __forceinline__ void xz_fill(const GridDev &g, const XCo<T> &co, XBuf
             hi[m] = xload<T>(sb, vo, (unsigned)(b * s2) * E);
         }
         T cl[3], ch[3];
-        cl[0] = xend_row<T, R, 0>(g, lo);
-        ch[0] = -xend_row<T, R, 0>(g, hi);
+        cl[0] = xend_row<T, R, 0>(lo);
+        ch[0] = -xend_row<T, R, 0>(hi);
         cl[1] = cl[2] = ch[1] = ch[2] = (T)0;
         if (R >= 2) {
-            cl[1] = xend_row<T, R, (R >= 2 ? 1 : 0)>(g, lo);
-            ch[1] = -xend_row<T, R, (R >= 2 ? 1 : 0)>(g, hi);
+            cl[1] = xend_row<T, R, (R >= 2 ? 1 : 0)>(lo);
+            ch[1] = -xend_row<T, R, (R >= 2 ? 1 : 0)>(hi);
         }
         if (R >= 3) {
-            cl[2] = xend_row<T, R, (R >= 3 ? 2 : 0)>(g, lo);
-            ch[2] = -xend_row<T, R, (R >= 3 ? 2 : 0)>(g, hi);
+            cl[2] = xend_row<T, R, (R >= 3 ? 2 : 0)>(lo);
+            ch[2] = -xend_row<T, R, (R >= 3 ? 2 : 0)>(hi);
         }
 #pragma unroll
         for (int i = 0; i <= 2 * R; ++i) {
@@ -490,7 +375,7 @@ __device__ __forceinline__ void xz_fill(const GridDev &g, const XCo<T> &co, XBuf
 // u_z and D_z u_z at plane k from the queue (base jb: k - R inside,
 // 0 or n2 - 1 - 2R within R of a non-periodic end)
 template <typename T, int R>
-__device__ __forceinline__ void xz_terms(const GridDev &g, const XCo<T> &co, const XZq<T, R> &z,
+__device__ __forceinline__ void xz_terms(const XCo<T> &co, const XZq<T, R> &z,
                                          int k, int jb, int n2, bool pz, T ih2, T &u2, T &l2)
 {
     if (pz || (k >= R && k <= n2 - 1 - R)) {
@@ -507,9 +392,9 @@ __device__ __forceinline__ void xz_terms(const GridDev &g, const XCo<T> &co, con
 #pragma unroll
     for (int i = 1; i <= 2 * R; ++i) u2 = d == i ? z.u[i] : u2;
     const int A = low ? k : n2 - 1 - k;
-    T l = xend_row<T, R, 0>(g, e);
-    if (R >= 2 && A == 1) l = xend_row<T, R, (R >= 2 ? 1 : 0)>(g, e);
-    if (R >= 3 && A == 2) l = xend_row<T, R, (R >= 3 ? 2 : 0)>(g, e);
+    T l = xend_row<T, R, 0>(e);
+    if (R >= 2 && A == 1) l = xend_row<T, R, (R >= 2 ? 1 : 0)>(e);
+    if (R >= 3 && A == 2) l = xend_row<T, R, (R >= 3 ? 2 : 0)>(e);
     l2 = (low ? l : -l) * ih2;
 }
 
@@ -648,7 +533,7 @@ k_xstage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int 
                 jb = zbase(k);
 #pragma unroll
                 for (int p = 0; p < kXPY; ++p)
-                    xz_fill<T, R>(g, co, sb, vin[p], jb, n2, s2, pz, ih2, zq[p]);
+                    xz_fill<T, R>(co, sb, vin[p], jb, n2, s2, pz, ih2, zq[p]);
             }
             // the queue moves on after this plane when the next plane's base
             // is one further and its new position takes the interior row
@@ -703,7 +588,7 @@ k_xstage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int 
                     T v = (T)0;
                     if (ry < wy && ex < wx + 2 * R && (px || (jx >= 0 && jx < n0))) {
                         const int base = (ry + 2 * R) * PW - (x0 - 2 * R);
-                        v = xrow<T, R>(g, co, jx, n0, px, [&](int m) { return ph[base + m]; }) *
+                        v = xrow<T, R>(co, jx, n0, px, [&](int m) { return ph[base + m]; }) *
                             ih0;
                     }
                     sm.ux[e] = v;
@@ -714,7 +599,7 @@ k_xstage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int 
                     T v = (T)0;
                     if (c < wx && ey < wy + 2 * R && (py || (jy >= 0 && jy < n1))) {
                         const int base = 2 * R + c - (y0 - 2 * R) * PW;
-                        v = xrow<T, R>(g, co, jy, n1, py,
+                        v = xrow<T, R>(co, jy, n1, py,
                                        [&](int m) { return ph[base + m * PW]; }) *
                             ih1;
                     }
@@ -738,10 +623,10 @@ k_xstage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int 
                         l1 = xcentral_at<T, R, kXTX>(co, ucy) * ih1;
                     } else {
                         const int ub = ry * UW - (x0 - R);
-                        l0 = xrow<T, R>(g, co, gx, n0, px, [&](int m) { return sm.ux[ub + m]; }) *
+                        l0 = xrow<T, R>(co, gx, n0, px, [&](int m) { return sm.ux[ub + m]; }) *
                              ih0;
                         const int vb = cx - (y0 - R) * kXTX;
-                        l1 = xrow<T, R>(g, co, gy, n1, py,
+                        l1 = xrow<T, R>(co, gy, n1, py,
                                         [&](int m) { return sm.uy[vb + m * kXTX]; }) *
                              ih1;
                     }
@@ -752,7 +637,7 @@ k_xstage(const GridDev *__restrict__ grids, const Item *__restrict__ items, int 
                     lap += l1;
                     if (d3) {
                         T u2, l2;
-                        xz_terms<T, R>(g, co, zq[p], k, jb, n2, pz, ih2, u2, l2);
+                        xz_terms<T, R>(co, zq[p], k, jb, n2, pz, ih2, u2, l2);
                         g2 += u2 * u2;
                         lap += l2;
                     }
