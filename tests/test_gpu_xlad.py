@@ -53,6 +53,8 @@ LAD = dict(eq="HJ", gamma="LAD", alpha_f=0.48)
 
 CASES = [
     ("duct64x40x40_C6", lambda: G.duct(40, nx=64), dict(LAD, scheme="C6"), 4),
+    # the benchmarked duct's tiles and z chunks, at a quarter of its x
+    ("duct64x256x256_C6", lambda: G.duct(256, nx=64), dict(LAD, scheme="C6"), 3),
     ("duct64x40x40_E6", lambda: G.duct(40, nx=64), dict(LAD, scheme="E6"), 4),
     ("slab64x40x24_C6", slab, dict(LAD, scheme="C6"), 4),
     ("duct40x33x33_E4", lambda: G.duct(33, nx=40), dict(LAD, scheme="E4"), 4),
@@ -78,7 +80,7 @@ def test_lad_tiles_fp64_vs_oracle(solver, oracle, name, mk, kw, n):
     assert np.allclose(out["hist"][:, 0], h[:, 0], rtol=1e-8, atol=1e-14)
 
 
-FP32_CASES = [c for c in CASES if c[0] in ("duct64x40x40_C6", "slab64x40x24_C6",
+FP32_CASES = [c for c in CASES if c[0] in ("duct64x40x40_C6", "duct64x256x256_C6", "slab64x40x24_C6",
                                            "channel129x65_C6", "star96_E6_mask")]
 
 

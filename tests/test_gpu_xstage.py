@@ -89,6 +89,10 @@ CASES = [
      dict(eq="HJ", gamma="LINEAR", scheme="E2", rk="RK3", eps=0.1, alpha_f=0.48), 25),
     ("duct16x256x256_E6_lad", lambda: G.duct(256, nx=16),
      dict(eq="HJ", gamma="LAD", scheme="E6", alpha_f=0.48), 4),
+    # the benchmarked duct's lines (256 points along y and z, fast tiles,
+    # the z march in chunks with both end zones) at a quarter of its x
+    ("duct64x256x256_E6_lad", lambda: G.duct(256, nx=64),
+     dict(eq="HJ", gamma="LAD", scheme="E6", alpha_f=0.48), 4),
     ("box100_E6_lad", lambda: G.box2d(100), dict(eq="HJ", gamma="LAD", scheme="E6", alpha_f=0.48), 12),
     ("box100_E4_eikonal", lambda: G.box2d(100), dict(eq="EIKONAL", scheme="E4", alpha_f=0.48), 40),
     ("star96_E6_lad_mask", lambda: G.star_grain(96),
@@ -118,6 +122,7 @@ def test_onepass_fp64_vs_oracle(solver, oracle, name, mk, kw, n):
 
 
 FP32_CASES = [c for c in CASES if c[0] in ("duct40x33x33_E4_lad", "duct16x256x256_E6_lad",
+                                           "duct64x256x256_E6_lad",
                                            "box100_E6_lad", "star96_E6_lad_mask",
                                            "duct40x33x33_E6_poisson", "duct64x40x40_E6_lad",
                                            "slab64x40x24_E6_lad", "box200_E6_lad")]
