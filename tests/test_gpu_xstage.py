@@ -75,6 +75,13 @@ CASES = [
     ("duct64x40x40_E2_poisson", lambda: G.duct(40, nx=64),
      dict(eq="POISSON", scheme="E2", alpha_f=0.48), 25),
     ("slab64x40x24_E6_lad", slab, dict(eq="HJ", gamma="LAD", scheme="E6", alpha_f=0.48), 12),
+    # 3D at the shortest z the pass takes for E6 (4R + 2 = 14 planes: the
+    # queue's refills come within reach of both ends), non-periodic and
+    # periodic
+    ("duct64x14x14_E6_linear", lambda: G.duct(14, nx=64),
+     dict(eq="HJ", gamma="LINEAR", scheme="E6", eps=0.1, alpha_f=0.48), 20),
+    ("slab64x40x14_E6_linear", lambda: slab(64, 40, 14),
+     dict(eq="HJ", gamma="LINEAR", scheme="E6", eps=0.1, alpha_f=0.48), 20),
     ("slab64x40x24_E4_eikonal", slab, dict(eq="EIKONAL", scheme="E4", alpha_f=0.48), 30),
     ("box200_E6_linear", lambda: G.box2d(200),
      dict(eq="HJ", gamma="LINEAR", scheme="E6", eps=0.1, alpha_f=0.48), 20),
