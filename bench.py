@@ -69,11 +69,14 @@ def workload(name):
     return spec, kw, desc
 
 
+FP32_STALL = 200    # iterations without a smaller max change that end an FP32 solve
+
+
 def stop_rule(prec, fixed):
     if fixed:
         return dict(tol=0.0, max_iter=fixed, stall_window=0)
     if prec == "fp32":
-        return dict(tol=1e-6, max_iter=20000, stall_window=1000)
+        return dict(tol=1e-6, max_iter=20000, stall_window=FP32_STALL)
     return dict(tol=1e-10, max_iter=20000, stall_window=0)
 
 
@@ -874,14 +877,18 @@ def main():
     ap.add_argument("--burn-big-steps", type=int, default=40)
     ap.add_argument("--burn-big3", type=int, default=256)
     ap.add_argument("--moving-steps", type=int, default=24)
+    ap.add_argument("--stall-window", type=int, default=None,
+                    help="FP32 solves: iterations without a smaller max change that end them")
     ap.add_argument("--scheme", default=None,
                     help="derivative scheme in place of the workload's (E2, E4, E6, C4, C6)")
     ap.add_argument("--seg", type=int, default=1,
                     help="segmented Cartesian passes: 0 off, 1 auto, 16/24/32 segment length")
     args = ap.parse_args()
-    global ALPHA_F
+    global ALPHA_F, FP32_STALL
     if args.alpha_f is not None:
         ALPHA_F = args.alpha_f
+    if args.stall_window is not None:
+        FP32_STALL = args.stall_window
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(grids are independent; see the multi-GPU design notes)", file=sys.stderr)
