@@ -12,6 +12,10 @@ Cylinder O-grid 512 x 256 (C6, 10th-order filter, curvature):
   * converged FP64 and FP32 fields against the oracle's converged field at
     all 131,072 points, stored in tests/golden (written by
     tests/golden/make_golden.py).
+Square duct 256^3, the benchmarked method (LAD pseudo-HJ, alpha_f 0.495,
+RK4) with C6 (segmented line passes, LAD field in tile passes) and E6
+(one pass per RK stage), FP64 and FP32: element-wise against the FP64
+oracle at all 16.8 M points after 3 pseudo iterations from phi = 0.
 Square duct 256^3 (C6, LAD pseudo-HJ and Poisson, FP32): properties that
 hold at any size -- every x-plane equal (x periodic and uniform), the
 y <-> z and y <-> 1 - y symmetries, and the error against
@@ -106,6 +110,44 @@ def test_cylinder_512x256_converged_field(big, precision):
     else:
         assert out["status"] in (0, 2)
         assert d / np.abs(ref).max() <= FP32_TOL
+
+
+DUCT_KW = dict(eq="HJ", gamma="LAD", eps=0.2, rk="RK4", alpha_f=0.495)
+DUCT_ITERS = 3
+
+
+@pytest.fixture(scope="module")
+def duct_oracle(oracle):
+    """The oracle's 256^3 duct after DUCT_ITERS iterations, per scheme."""
+    cache = {}
+
+    def get(scheme):
+        if scheme not in cache:
+            o, _, it, h = oracle.solve(G.duct(256),
+                                       omethod(oracle, fixed=DUCT_ITERS, scheme=scheme, **DUCT_KW))
+            assert it == DUCT_ITERS
+            cache[scheme] = (o, h)
+        return cache[scheme]
+
+    return get
+
+
+@pytest.mark.parametrize("scheme", ["C6", "E6"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_duct_256_fixed_iterations(big, duct_oracle, scheme, precision):
+    spec = G.duct(256)
+    m = gmethod(tol=0.0, max_iter=DUCT_ITERS, precision=precision, scheme=scheme, **DUCT_KW)
+    say(f"[full size {precision}] duct 256^3 {scheme} LAD iters={DUCT_ITERS}")
+    prep = tuned(big, spec, scheme, precision, m)
+    out = big.solve(prep, m)
+    assert out["iters"] == DUCT_ITERS
+    phi = out["phi"].double().cpu().numpy()
+    ref, h = duct_oracle(scheme)
+    e = rel(phi, ref)
+    say(f"   rel L-inf vs oracle {e:.2e} (max |phi| {np.abs(ref).max():.3e})")
+    assert e <= (FP64_TOL if precision == "fp64" else FP32_TOL)
+    if precision == "fp64":
+        assert np.allclose(out["hist"][:, 0], h[:, 0], rtol=1e-8, atol=1e-14)
 
 
 def _duct_checks(phi, spec):
