@@ -15,7 +15,8 @@ Cylinder O-grid 512 x 256 (C6, 10th-order filter, curvature):
 Square duct 256^3, the benchmarked method (LAD pseudo-HJ, alpha_f 0.495,
 RK4) with C6 (segmented line passes, LAD field in tile passes) and E6
 (one pass per RK stage), FP64 and FP32: element-wise against the FP64
-oracle at all 16.8 M points after 3 pseudo iterations from phi = 0.
+oracle at all 16.8 M points after 3 pseudo iterations from phi = 0, and
+with linear Gamma after 12.
 Square duct 256^3 (C6, LAD pseudo-HJ and Poisson, FP32): properties that
 hold at any size -- every x-plane equal (x periodic and uniform), the
 y <-> z and y <-> 1 - y symmetries, and the error against
@@ -112,37 +113,41 @@ def test_cylinder_512x256_converged_field(big, precision):
         assert d / np.abs(ref).max() <= FP32_TOL
 
 
-DUCT_KW = dict(eq="HJ", gamma="LAD", eps=0.2, rk="RK4", alpha_f=0.495)
-DUCT_ITERS = 3
+DUCT_KW = dict(eq="HJ", eps=0.2, rk="RK4", alpha_f=0.495)
+DUCT_ITERS = {"LAD": 3, "LINEAR": 12}
 
 
 @pytest.fixture(scope="module")
 def duct_oracle(oracle):
-    """The oracle's 256^3 duct after DUCT_ITERS iterations, per scheme."""
+    """The oracle's 256^3 duct after DUCT_ITERS[gamma] iterations, per
+    scheme and Gamma."""
     cache = {}
 
-    def get(scheme):
-        if scheme not in cache:
-            o, _, it, h = oracle.solve(G.duct(256),
-                                       omethod(oracle, fixed=DUCT_ITERS, scheme=scheme, **DUCT_KW))
-            assert it == DUCT_ITERS
-            cache[scheme] = (o, h)
-        return cache[scheme]
+    def get(scheme, gamma):
+        if (scheme, gamma) not in cache:
+            n = DUCT_ITERS[gamma]
+            o, _, it, h = oracle.solve(G.duct(256), omethod(oracle, fixed=n, scheme=scheme,
+                                                            gamma=gamma, **DUCT_KW))
+            assert it == n
+            cache[(scheme, gamma)] = (o, h)
+        return cache[(scheme, gamma)]
 
     return get
 
 
+@pytest.mark.parametrize("gamma", ["LAD", "LINEAR"])
 @pytest.mark.parametrize("scheme", ["C6", "E6"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_duct_256_fixed_iterations(big, duct_oracle, scheme, precision):
+def test_duct_256_fixed_iterations(big, duct_oracle, scheme, precision, gamma):
     spec = G.duct(256)
-    m = gmethod(tol=0.0, max_iter=DUCT_ITERS, precision=precision, scheme=scheme, **DUCT_KW)
-    say(f"[full size {precision}] duct 256^3 {scheme} LAD iters={DUCT_ITERS}")
+    n = DUCT_ITERS[gamma]
+    m = gmethod(tol=0.0, max_iter=n, precision=precision, scheme=scheme, gamma=gamma, **DUCT_KW)
+    say(f"[full size {precision}] duct 256^3 {scheme} {gamma} iters={n}")
     prep = tuned(big, spec, scheme, precision, m)
     out = big.solve(prep, m)
-    assert out["iters"] == DUCT_ITERS
+    assert out["iters"] == n
     phi = out["phi"].double().cpu().numpy()
-    ref, h = duct_oracle(scheme)
+    ref, h = duct_oracle(scheme, gamma)
     e = rel(phi, ref)
     say(f"   rel L-inf vs oracle {e:.2e} (max |phi| {np.abs(ref).max():.3e})")
     assert e <= (FP64_TOL if precision == "fp64" else FP32_TOL)
