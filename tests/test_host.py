@@ -28,6 +28,17 @@ def test_exports_every_declared_symbol(L):
     assert not missing, missing
 
 
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU: --gpus above 1 ends with a message
+    and a non-zero status before anything touches a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stdout + r.stderr
+
+
 def test_version_and_defaults(L):
     assert "gfx950" in L.wd_version()
     m = L.wd_method_default()
