@@ -843,10 +843,12 @@ def main():
     ap.add_argument("--fixed-iters", type=int, default=None,
                     help="pseudo iterations per step (default: 200 for the duct, a full "
                          "solve otherwise; 0 = full solve)")
-    ap.add_argument("--cpu-iters", type=int, default=2,
-                    help="oracle iterations of the all-core CPU baseline")
-    ap.add_argument("--cpu-iters-1t", type=int, default=1,
-                    help="oracle iterations of the one-thread CPU baseline")
+    ap.add_argument("--cpu-iters", type=int, default=None,
+                    help="oracle iterations of the all-core CPU baseline (default: "
+                         "2 x 256^3 point-updates' worth, at least 2)")
+    ap.add_argument("--cpu-iters-1t", type=int, default=None,
+                    help="oracle iterations of the one-thread CPU baseline (default: "
+                         "256^3 point-updates' worth, at least 1)")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the all-core baseline (0: OMP_NUM_THREADS, else all)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -1001,6 +1003,13 @@ def main():
     if not args.no_cpu:
         model, ncpu, avail = cpu_info()
         threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS") or 0) or avail
+        # a bounded sample of the workload: about as many point-updates as
+        # 2 (all cores) and 1 (one thread) iterations of the 256^3 duct, a
+        # few seconds to some tens of seconds of host work whatever the grid
+        if args.cpu_iters is None:
+            args.cpu_iters = max(2, round(2 * 256 ** 3 / spec.npoints))
+        if args.cpu_iters_1t is None:
+            args.cpu_iters_1t = max(1, round(256 ** 3 / spec.npoints))
         v, dt, used = run_cpu_baseline(spec, kw, args.cpu_iters, threads)
         print(f"[bench] oracle, {used} threads: {dt:.1f} s", file=sys.stderr, flush=True)
         v1, dt1, _ = run_cpu_baseline(spec, kw, args.cpu_iters_1t, 1)
